@@ -1,0 +1,227 @@
+"""O6: contraction-path cost model, greedy and randomised-greedy search, and
+index slicing (Sec. 3.1: Flop-minimising pairwise order, slicing of indices
+into independent sub-networks).
+
+The paper states the goal (a pseudo-optimal pairwise order found quickly,
+then slicing to bound intermediate memory) but not the heuristics.  This
+module fixes one reading, and the native planner implements the same
+reading independently; the tests require both to produce the same path,
+cost and slice set.
+
+Cost model, evaluated in IEEE double arithmetic in exactly this order
+    size(S)   = product of extents over S, labels in ascending order
+    flops     = 8 * size(A u B) per step (one complex multiply-add = 8 real
+                flops), summed over steps in path order
+    result    = labels of A u B that are open or still held by another live
+                tensor (ascending)
+    peak      = max over steps of [sum of sizes of all live tensors before the
+                step + size(C) + size(A) + size(B)]; the second A and B terms
+                reserve room for permuted copies.  Bytes = 8 * peak (complex64).
+Greedy step
+    candidates: pairs of live tensors sharing a label (all pairs if none do);
+    choose the minimum of (size(C) - size(A) - size(B), flops, i, j), i < j.
+Randomised greedy
+    sigma = sign(d) * log2(1 + |d|) with d as above; candidate c is drawn with
+    weight exp(-(sigma_c - sigma_min) / T), candidates in (i, j) order, using
+    SplitMix64 (Steele, Lea, Flood 2014): state += 0x9E3779B97F4A7C15, then
+    the published mixing steps; a uniform is (z >> 11) * 2^-53.  Trial r
+    seeds its own state with the first output of a generator started at
+    seed + r * 0x9E3779B97F4A7C15.  The deterministic greedy path is trial
+    -1; the best trial by (flops, peak) wins, earlier trials on ties.
+Slicing
+    while 8 * peak > budget: among non-open, not yet sliced labels of A, B
+    and C at the first step attaining the peak, slice the one giving the
+    smallest (peak, total flops over all slices, label).
+
+Parity pins (tests): hand-computed costs of small paths; greedy never worse
+than... (none; greedy is a heuristic) -- instead an exhaustive search over
+all pairwise orders on <= 7 tensors bounds it from below; sliced peak <=
+budget; slicing invariance of the contracted value (with O2).
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Dict, Iterable, List, Sequence, Tuple
+
+MASK64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+
+
+class SplitMix64:
+    def __init__(self, state: int):
+        self.state = state & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + GOLDEN) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+
+def size_of(labels: Iterable[int], ext: Dict[int, int]) -> float:
+    s = 1.0
+    for l in sorted(labels):
+        s = s * float(ext[l])
+    return s
+
+
+class _State:
+    def __init__(self, leaves: Sequence[Iterable[int]], open_set, sliced):
+        self.sets = {i: frozenset(l for l in ls if l not in sliced) for i, ls in enumerate(leaves)}
+        self.open = frozenset(open_set)
+        self.count: Dict[int, int] = {}
+        for s in self.sets.values():
+            for l in s:
+                self.count[l] = self.count.get(l, 0) + 1
+        self.next_id = len(leaves)
+
+    def result(self, i: int, j: int) -> frozenset:
+        a, b = self.sets[i], self.sets[j]
+        out = []
+        for l in a | b:
+            other = self.count[l] - (l in a) - (l in b)
+            if l in self.open or other > 0:
+                out.append(l)
+        return frozenset(out)
+
+    def merge(self, i: int, j: int) -> Tuple[frozenset, frozenset, frozenset, int]:
+        a, b = self.sets.pop(i), self.sets.pop(j)
+        for l in a:
+            self.count[l] -= 1
+        for l in b:
+            self.count[l] -= 1
+        c = []
+        for l in a | b:
+            if l in self.open or self.count[l] > 0:
+                c.append(l)
+        c = frozenset(c)
+        for l in c:
+            self.count[l] = self.count.get(l, 0) + 1
+        nid = self.next_id
+        self.sets[nid] = c
+        self.next_id += 1
+        return a, b, c, nid
+
+    def candidates(self) -> List[Tuple[int, int]]:
+        by_label: Dict[int, List[int]] = {}
+        for i, s in self.sets.items():
+            for l in s:
+                by_label.setdefault(l, []).append(i)
+        pairs = set()
+        for ids in by_label.values():
+            ids = sorted(ids)
+            for x in range(len(ids)):
+                for y in range(x + 1, len(ids)):
+                    pairs.add((ids[x], ids[y]))
+        if not pairs:
+            ids = sorted(self.sets)
+            pairs = {(ids[x], ids[y]) for x in range(len(ids)) for y in range(x + 1, len(ids))}
+        return sorted(pairs)
+
+
+def _score(st: _State, i: int, j: int, ext) -> Tuple[float, float]:
+    c = st.result(i, j)
+    d = size_of(c, ext) - size_of(st.sets[i], ext) - size_of(st.sets[j], ext)
+    fl = 8.0 * size_of(st.sets[i] | st.sets[j], ext)
+    return d, fl
+
+
+def greedy_path(leaves, ext, open_set=(), rng: SplitMix64 | None = None,
+                temperature: float = 1.0) -> List[Tuple[int, int]]:
+    """Deterministic greedy (rng None) or one randomised-greedy trial."""
+    st = _State(leaves, open_set, ())
+    path = []
+    while len(st.sets) > 1:
+        cands = st.candidates()
+        scored = [(_score(st, i, j, ext), i, j) for (i, j) in cands]
+        if rng is None:
+            (d, fl), i, j = min(scored, key=lambda x: (x[0][0], x[0][1], x[1], x[2]))
+        else:
+            sig = [math.copysign(math.log2(1.0 + abs(s[0][0])), s[0][0]) for s in scored]
+            smin = min(sig)
+            w = [math.exp(-(s - smin) / temperature) for s in sig]
+            tot = 0.0
+            for x in w:
+                tot += x
+            u = rng.uniform() * tot
+            acc = 0.0
+            pick = len(w) - 1
+            for k, x in enumerate(w):
+                acc += x
+                if acc >= u:
+                    pick = k
+                    break
+            _, i, j = scored[pick]
+        st.merge(i, j)
+        path.append((i, j))
+    return path
+
+
+def path_stats(leaves, ext, path, open_set=(), sliced=()) -> dict:
+    """Per-slice flops, peak live elements and per-step label sets."""
+    st = _State(leaves, open_set, set(sliced))
+    live = 0.0
+    for s in st.sets.values():
+        live += size_of(s, ext)
+    flops = 0.0
+    peak = 0.0
+    peak_step = -1
+    steps = []
+    for t, (i, j) in enumerate(path):
+        sa, sb = st.sets[i], st.sets[j]
+        c = st.result(i, j)
+        szA, szB, szC = size_of(sa, ext), size_of(sb, ext), size_of(c, ext)
+        p = live + szC + szA + szB
+        if p > peak:
+            peak, peak_step = p, t
+        flops += 8.0 * size_of(sa | sb, ext)
+        a, b, c2, _ = st.merge(i, j)
+        assert c2 == c
+        live = live - szA - szB + szC
+        steps.append((sa, sb, c))
+    n_slices = 1.0
+    for l in sorted(sliced):
+        n_slices *= float(ext[l])
+    return {"flops": flops, "peak": peak, "peak_step": peak_step, "steps": steps,
+            "n_slices": n_slices, "total_flops": flops * n_slices}
+
+
+def random_greedy_path(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
+                       temperature: float = 1.0):
+    best = greedy_path(leaves, ext, open_set)
+    bs = path_stats(leaves, ext, best, open_set)
+    best_key = (bs["flops"], bs["peak"])
+    for r in range(trials):
+        g = SplitMix64((seed + r * GOLDEN) & MASK64)
+        rng = SplitMix64(g.next_u64())
+        p = greedy_path(leaves, ext, open_set, rng=rng, temperature=temperature)
+        s = path_stats(leaves, ext, p, open_set)
+        key = (s["flops"], s["peak"])
+        if key < best_key:
+            best, best_key = p, key
+    return best
+
+
+def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:
+    """Labels to slice so that 8 * peak <= budget (empty list if it fits)."""
+    sliced: List[int] = []
+    cur = path_stats(leaves, ext, path, open_set, sliced)
+    while 8.0 * cur["peak"] > budget_bytes:
+        sa, sb, sc = cur["steps"][cur["peak_step"]]
+        cands = sorted(l for l in (sa | sb | sc) if l not in open_set and l not in sliced)
+        if not cands:
+            raise ValueError("memory budget cannot be met by slicing")
+        best = None
+        for l in cands:
+            s = path_stats(leaves, ext, path, open_set, sliced + [l])
+            key = (s["peak"], s["total_flops"], l)
+            if best is None or key < best[0]:
+                best = (key, l, s)
+        sliced.append(best[1])
+        cur = best[2]
+    return sliced
