@@ -1,0 +1,320 @@
+/*
+ * tn.h -- C ABI of the MI355X tensor-network circuit simulator.
+ *
+ * The library contracts the complex tensor network that a quantum circuit
+ * defines (gate tensors, Kraus-channel tensors, MPS site tensors) along a
+ * precomputed pairwise path over independent index slices, on one gfx950
+ * GPU.  Everything that crosses this boundary is a plain pointer or size.
+ *
+ * Conventions shared by every call
+ *   - Status: every call returns tn_status; TN_OK (0) on success, a negative
+ *     code otherwise.  tn_last_error() returns a thread-local message for the
+ *     last failing call on the calling thread.  No C++ exception crosses the
+ *     ABI.  Errors of asynchronous device work surface at the next call that
+ *     synchronises, as TN_ERR_DEVICE.
+ *   - Complex numbers: interleaved (re, im).  complex64 = two floats,
+ *     complex128 = two doubles.
+ *   - Bit order: qubit 0 is the most significant bit of a flat amplitude
+ *     index.  Two-qubit matrices act on |a b> where a is the op's first qubit
+ *     (the more significant bit); row = output, column = input.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *     default stream).  Device work is enqueued on it; calls do not
+ *     synchronise the stream unless stated.
+ *   - Ownership: handles (tn_network, tn_path, tn_mps, tn_model) are created
+ *     and destroyed by the library.  Device buffers passed in are owned by the
+ *     caller and are never freed by the library.
+ */
+#ifndef TN_H_
+#define TN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tn_status;
+
+enum {
+  TN_OK = 0,
+  TN_ERR_ARG = -1,         /* null pointer, negative size, bad enum value     */
+  TN_ERR_MODES = -2,       /* repeated label in one tensor, label not found   */
+  TN_ERR_EXTENT = -3,      /* the same label has different extents            */
+  TN_ERR_BITS = -4,        /* bit-string length/values/open set inconsistent  */
+  TN_ERR_BUDGET = -5,      /* no slicing meets the memory budget              */
+  TN_ERR_WORKSPACE = -6,   /* workspace missing or smaller than the plan needs*/
+  TN_ERR_DEVICE = -7,      /* a HIP runtime call or a kernel launch failed    */
+  TN_ERR_GATE = -8,        /* unknown gate, bad qubit index, channel where a  */
+                           /* unitary is required, non-unitary gate matrix    */
+  TN_ERR_SITE = -9,        /* MPS site out of range                           */
+  TN_ERR_UNSUPPORTED = -10,/* valid request this build does not implement     */
+  TN_ERR_NOMEM = -11,      /* host or device allocation failed                */
+  TN_ERR_STATE = -12       /* handle used in a state that does not allow it   */
+};
+
+/* Thread-local message for the last failing call ("" if none). */
+const char* tn_last_error(void);
+/* Library version string, e.g. "tn-mi355x 0.1 gfx950". */
+const char* tn_version(void);
+
+/* ---------------------------------------------------------------------- */
+/* Circuits (Sec. 3.1: qubits, one- and two-qubit gates; Sec. 3.3, Eq. 3:  */
+/* Kraus channels)                                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Gate / channel identifiers.  The library builds each matrix itself from
+ * the id and params: sqrt_x, sqrt_y, sqrt_w are R_P(pi/2) =
+ * cos(pi/4) I - i sin(pi/4) P for P = X, Y, (X+Y)/sqrt2; FSIM(theta, phi)
+ * has cos(theta) on |01>,|10> diagonal, -i sin(theta) between them and
+ * exp(-i phi) on |11>; CPHASE(phi) puts exp(i phi) on |11>; RZ(phi) =
+ * diag(exp(-i phi/2), exp(i phi/2)); CX has q0 as control.
+ * CUSTOM1 / CUSTOM2 take `matrix` (2x2 / 4x4 complex128, row-major).
+ * Channels: DEPOL1(p) Kraus {sqrt(1-p) I, sqrt(p/3) X, Y, Z};
+ * DEPOL2(p) {sqrt(1-p) II, sqrt(p/15) PQ for the 15 non-identity Pauli pairs,
+ * P over I,X,Y,Z on q0 the outer loop}; AMP_DAMP(g) {[[1,0],[0,sqrt(1-g)]],
+ * [[0,sqrt(g)],[0,0]]}.  Branch k of a channel is chosen when a uniform u
+ * falls in [P_0+..+P_{k-1}, P_0+..+P_k). */
+enum {
+  TN_GATE_SQRT_X = 1, TN_GATE_SQRT_Y, TN_GATE_SQRT_W, TN_GATE_H, TN_GATE_X,
+  TN_GATE_Y, TN_GATE_Z, TN_GATE_S, TN_GATE_T, TN_GATE_RZ,
+  TN_GATE_CZ = 20, TN_GATE_CX, TN_GATE_FSIM, TN_GATE_CPHASE, TN_GATE_SWAP,
+  TN_GATE_CUSTOM1 = 40, TN_GATE_CUSTOM2,
+  TN_CHAN_DEPOL1 = 60, TN_CHAN_DEPOL2, TN_CHAN_AMP_DAMP
+};
+
+typedef struct {
+  int32_t gate;          /* TN_GATE_* or TN_CHAN_*                          */
+  int32_t q0;            /* first qubit                                     */
+  int32_t q1;            /* second qubit, -1 for one-qubit ops              */
+  double param[2];       /* angles (radians) or channel rates               */
+  const double* matrix;  /* CUSTOM1/2 only: 2x2 or 4x4 complex128, read once */
+} tn_op;
+
+typedef struct {
+  int32_t n_qubits;      /* 1 .. 4096                                       */
+  int64_t n_ops;
+  const tn_op* ops;      /* host memory, copied by the callee               */
+} tn_circuit;
+
+/* ---------------------------------------------------------------------- */
+/* Network (Sec. 3.1, Fig. 1; small gates absorbed, Sec. 3.1.1)           */
+/* ---------------------------------------------------------------------- */
+
+typedef struct tn_network tn_network;
+
+/* Build the tensor network of a noiseless circuit.  The |0> inputs and all
+ * one-qubit gates are folded into neighbouring two-qubit gate tensors (a
+ * wire without two-qubit gates becomes one rank-1 tensor); output legs stay
+ * open until tn_amplitudes projects them.  Host only (no device work).
+ * Errors: TN_ERR_ARG (null, n_qubits out of range), TN_ERR_GATE (unknown
+ * id, bad qubit, q0 == q1, channel op). */
+tn_status tn_build_network(const tn_circuit* c, tn_network** out);
+tn_status tn_network_destroy(tn_network* n);
+
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_tensors;
+  int32_t n_labels;      /* labels are 0 .. n_labels-1                      */
+} tn_network_info;
+tn_status tn_network_get_info(const tn_network* n, tn_network_info* info);
+/* Tensor i: rank, labels (axis order) and complex128 data (row-major,
+ * 2^rank entries).  labels / data may be NULL to query the rank only. */
+tn_status tn_network_get_tensor(const tn_network* n, int32_t i, int32_t* rank,
+                                int32_t* labels, double* data);
+/* Output label of every qubit (n_qubits entries). */
+tn_status tn_network_output_labels(const tn_network* n, int32_t* labels);
+
+/* ---------------------------------------------------------------------- */
+/* Contraction path and slicing (Sec. 3.1: Flop-minimising order, slicing) */
+/* ---------------------------------------------------------------------- */
+
+typedef struct tn_path tn_path;
+typedef struct tn_model tn_model;
+
+enum { TN_PATH_GREEDY = 0, TN_PATH_RANDOM_GREEDY = 1, TN_PATH_LEARNED = 2 };
+
+typedef struct {
+  int32_t algo;               /* TN_PATH_*                                  */
+  int32_t trials;             /* random greedy: number of trials (>= 0)     */
+  uint64_t seed;              /* random greedy: SplitMix64 seed             */
+  double temperature;         /* random greedy: > 0, log2 units             */
+  double mem_budget_bytes;    /* slice until 8*peak <= budget; <= 0: never  */
+  const int8_t* open_mask;    /* n_qubits entries, 1 = output leg stays     */
+                              /* open; NULL = every leg projected           */
+  const tn_model* model;      /* TN_PATH_LEARNED: trained scorer            */
+} tn_path_opts;
+
+typedef struct {
+  double flops_per_slice;     /* 8 * sum over steps of prod(extents A u B)  */
+  double total_flops;         /* flops_per_slice * n_slices                 */
+  double peak_elems;          /* max over steps: live + |C| + |A| + |B|     */
+  double n_slices;
+  int32_t n_steps;
+  int32_t n_sliced;
+  int32_t algo_used;          /* LEARNED falls back to GREEDY when cheaper  */
+  int32_t reserved;
+} tn_path_cost;
+
+/* Search a pairwise order (SSA pairs: leaves 0..n-1, step t creates id
+ * n+t), then slice.  Cost model and heuristics: a greedy step picks the
+ * connected pair minimising (|C|-|A|-|B|, flops, i, j); the randomised
+ * version samples exp(-(sigma - sigma_min)/T), sigma = sign(d)log2(1+|d|),
+ * from SplitMix64 and keeps the best of greedy + `trials` by (flops, peak).
+ * Slicing adds, while 8*peak > budget, the label of the peak step that
+ * minimises (peak, total flops, label).  Host only.
+ * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */
+tn_status tn_find_path(const tn_network* n, const tn_path_opts* o,
+                       tn_path** out, tn_path_cost* cost);
+/* Use a caller-given SSA path (2*n_steps ints) and slice it per o. */
+tn_status tn_path_from_pairs(const tn_network* n, const tn_path_opts* o,
+                             const int32_t* pairs, int32_t n_steps,
+                             tn_path** out, tn_path_cost* cost);
+/* Copy out the pairs (2*n_steps) and sliced labels (n_sliced); either may be
+ * NULL. */
+tn_status tn_path_get(const tn_path* p, int32_t* pairs, int32_t* sliced_labels);
+tn_status tn_path_destroy(tn_path* p);
+
+/* ---------------------------------------------------------------------- */
+/* Pairwise contraction (Sec. 3.1; Table 2 is dominated by it)            */
+/* ---------------------------------------------------------------------- */
+
+enum { TN_C64 = 0, TN_C128 = 1 };
+
+/* Arithmetic of the complex GEMMs.  FP32: FP32 MFMA.  BF16X3: each operand
+ * split as hi + lo bfloat16, products hi*hi + hi*lo + lo*hi, FP32
+ * accumulation.  BF16X6: three-way bfloat16 split, six products (about FP32
+ * accuracy).  AUTO: the library picks per contraction from an error
+ * estimate (BF16X3 for large contractions, FP32 elsewhere). */
+enum { TN_PREC_FP32 = 0, TN_PREC_BF16X3 = 1, TN_PREC_BF16X6 = 2,
+       TN_PREC_AUTO = 3 };
+
+typedef struct {
+  void* data;                 /* device pointer, row-major, caller-owned    */
+  int32_t rank;               /* 0 .. 64                                    */
+  int32_t dtype;              /* TN_C64 (TN_C128 -> TN_ERR_UNSUPPORTED)     */
+  const int64_t* extents;     /* host array of `rank` extents (>= 1)        */
+} tn_tensor;
+
+/* Caller-owned device scratch for tn_contract_pair and tn_amplitudes.  The
+ * pointer must stay valid until replaced; calls that overlap on one device
+ * share it.  bytes == 0 clears it. */
+tn_status tn_set_workspace(void* device_ptr, size_t bytes);
+
+/* C[modesC] = sum over the other labels of A[modesA] * B[modesB] (einsum
+ * semantics): a label in A and B but not C is summed; in one input and C it
+ * is free; in A, B and C it is a batch label; in one input only and not in C
+ * it is summed out of that input.  modes are host arrays of `rank` ints.
+ * Asynchronous on `stream`.  Uses up to |A|+|B|+|C| complex64 of workspace
+ * when operands must be permuted.
+ * Errors: TN_ERR_ARG, TN_ERR_MODES (repeat, or C label not in A or B),
+ * TN_ERR_EXTENT, TN_ERR_UNSUPPORTED (C128), TN_ERR_WORKSPACE,
+ * TN_ERR_DEVICE. */
+tn_status tn_contract_pair(const tn_tensor* A, const int32_t* modesA,
+                           const tn_tensor* B, const int32_t* modesB,
+                           tn_tensor* C, const int32_t* modesC,
+                           int32_t precision, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Amplitudes (Eq. 1; batches, Sec. 3.1; marginal slices, Sec. 4.4)       */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+  double seconds;             /* device time of the run (HIP events)        */
+  double flops;               /* algorithmic flops executed                 */
+  double bytes;               /* algorithmic HBM bytes of the kernels       */
+  double slices_run;          /* bit-string x slice jobs executed           */
+  double kernels;             /* kernel launches per job                    */
+  int32_t precision;          /* precision used (AUTO resolved)             */
+  int32_t nonfinite;          /* 1 if an output entry is NaN or Inf         */
+  double err_bound;           /* a-priori relative error estimate           */
+} tn_report;
+
+typedef struct {
+  int32_t precision;          /* TN_PREC_*                                  */
+  int32_t use_graph;          /* 1: capture one job as a hipGraph, replay   */
+  int64_t slice_begin;        /* first slice of the range to run            */
+  int64_t slice_count;        /* number of slices; -1 = all                 */
+  int32_t accumulate;         /* 1: add into `out`; 0: overwrite            */
+  int32_t sync;               /* 1: wait for the stream before returning    */
+                              /* (fills seconds / nonfinite)                */
+} tn_exec_opts;
+
+/* Amplitudes <x|U|0..0> for n_bs bit-strings (host int8 array n_bs x
+ * n_qubits, values 0, 1 or -1 = open).  Every bit-string must have the open
+ * set the path was built for (TN_ERR_BITS otherwise).  `out` is a device
+ * array of n_bs x 2^(#open) complex128: open qubits ascending, the first one
+ * the most significant bit.  The result is the sum over the path's slices
+ * (or over [slice_begin, slice_begin+slice_count)) of the per-slice
+ * complex64 contraction, accumulated in FP64.  opts may be NULL (FP32, all
+ * slices, overwrite, no sync).  rep may be NULL.
+ * Errors: TN_ERR_ARG, TN_ERR_BITS, TN_ERR_WORKSPACE, TN_ERR_DEVICE. */
+tn_status tn_amplitudes(const tn_network* n, const tn_path* p,
+                        const int8_t* bits, int64_t n_bs,
+                        const tn_exec_opts* opts, void* out, tn_report* rep,
+                        void* stream);
+
+/* Workspace bytes tn_amplitudes needs for this path, n_bs bit-strings and
+ * precision (job control words, bit-strings, gathered leaves, intermediates
+ * and permute / split-K scratch of one job).  Host only. */
+tn_status tn_amplitudes_workspace(const tn_network* n, const tn_path* p,
+                                  int64_t n_bs, int32_t precision,
+                                  size_t* bytes);
+
+/* ---------------------------------------------------------------------- */
+/* Matrix product states (Sec. 3.2)                                       */
+/* ---------------------------------------------------------------------- */
+
+typedef struct tn_mps tn_mps;
+
+/* |0...0> on n_sites qubits with bond dimensions up to chi_max (1..1024).
+ * The site tensors live in library-owned device memory.
+ * Errors: TN_ERR_ARG, TN_ERR_NOMEM, TN_ERR_DEVICE. */
+tn_status tn_mps_create(int32_t n_sites, int32_t chi_max, void* stream,
+                        tn_mps** out);
+tn_status tn_mps_destroy(tn_mps* m);
+/* One-qubit gate (2x2 complex128 row-major, host) absorbed into the site. */
+tn_status tn_mps_apply_gate1(tn_mps* m, int32_t site, const double* gate,
+                             void* stream);
+/* Two-qubit gate (4x4 complex128, host) on sites (site, site+1), with the
+ * more significant bit on `site`: move the orthogonality centre to `site`
+ * (FP64 QR), contract both sites with the gate, FP64 SVD of the
+ * (2 chi_l) x (2 chi_r) matrix, keep at most chi_max singular values with
+ * s/s_max > cutoff, renormalise the kept values to unit norm, write back.
+ * *discarded (may be NULL) receives the discarded weight sum s_dropped^2 /
+ * sum s^2.  Synchronises the stream.
+ * Errors: TN_ERR_SITE, TN_ERR_ARG (chi_max < 1, cutoff < 0), TN_ERR_DEVICE. */
+tn_status tn_mps_apply_gate(tn_mps* m, int32_t site, const double* gate,
+                            int32_t chi_max, double cutoff,
+                            double* discarded, void* stream);
+/* Bond dimensions (n_sites - 1 ints, host). */
+tn_status tn_mps_bond_dims(const tn_mps* m, int32_t* dims);
+/* <Z_i> for every site (host array of n_sites doubles).  Synchronises. */
+tn_status tn_mps_expect_z(tn_mps* m, double* out, void* stream);
+/* Amplitudes of n_bs 0/1 bit-strings (host int8 n_bs x n_sites) into host
+ * complex128 `out`.  Synchronises. */
+tn_status tn_mps_amplitudes(tn_mps* m, const int8_t* bits, int64_t n_bs,
+                            double* out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Stochastic Kraus trajectories (Sec. 3.3, Eq. 3, sampled)               */
+/* ---------------------------------------------------------------------- */
+
+/* Run traj_per_circ trajectories of every circuit (noisy ops included) as
+ * one batch.  For channel event e of trajectory t the branch is chosen by
+ * uniforms[t * ld_uniforms + e] against p_k = |A_k psi|^2 (FP64), then the
+ * state is renormalised.  Trajectory t = c * traj_per_circ + j runs circuit
+ * c.  z_out (host, n_circ*traj_per_circ x n_qubits doubles) receives <Z_q>
+ * of each final state.  All circuits must have the same n_qubits (<= 30).
+ * Synchronises.  Errors: TN_ERR_ARG, TN_ERR_GATE, TN_ERR_NOMEM,
+ * TN_ERR_DEVICE. */
+tn_status tn_run_trajectories(const tn_circuit* const* circs, int32_t n_circ,
+                              int32_t traj_per_circ, const double* uniforms,
+                              int64_t ld_uniforms, double* z_out,
+                              tn_report* rep, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_H_ */

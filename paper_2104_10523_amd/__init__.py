@@ -1,0 +1,291 @@
+"""Python binding of the MI355X tensor-network simulator (libtn.so).
+
+Functions carry the C ABI's names and only marshal arguments: device
+buffers are torch tensors, streams are torch streams, every computation runs
+in the native library.  There is no CPU fallback: without the built library
+every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+from ._native import (GATE_IDS, PATH_ALGO, PREC, TnCircuit, TnExecOpts, TnNetworkInfo, TnOp,
+                      TnPathCost, TnPathOpts, TnReport, TnTensor, TnError, check, lib)
+
+__all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
+           "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
+           "tn_amplitudes_workspace", "tn_mps_create", "tn_mps_apply_gate",
+           "tn_run_trajectories", "PREC", "lib"]
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class _CircuitArgs:
+    """Keeps the ctypes op array (and custom matrices) alive for one call."""
+
+    def __init__(self, n_qubits: int, ops: Iterable):
+        ops = list(ops)
+        self.arr = (TnOp * max(len(ops), 1))()
+        self.keep = []
+        for i, op in enumerate(ops):
+            name, qubits, params = op[0], tuple(op[1]), tuple(op[2]) if len(op) > 2 else ()
+            o = self.arr[i]
+            o.gate = GATE_IDS[name] if isinstance(name, str) else int(name)
+            o.q0 = int(qubits[0])
+            o.q1 = int(qubits[1]) if len(qubits) > 1 else -1
+            mat = None
+            if name in ("custom1", "custom2"):
+                mat = np.ascontiguousarray(np.asarray(params[0], dtype=np.complex128)).view(np.float64)
+                self.keep.append(mat)
+                o.matrix = mat.ctypes.data_as(C.POINTER(C.c_double))
+            else:
+                for k, v in enumerate(params[:2]):
+                    o.param[k] = float(v)
+        self.circ = TnCircuit(int(n_qubits), len(ops), self.arr)
+
+
+class Network:
+    def __init__(self, handle: int, n_qubits: int):
+        self.h = C.c_void_p(handle)
+        self.n_qubits = n_qubits
+
+    def __del__(self):
+        if getattr(self, "h", None) and lib is not None:
+            try:
+                lib().tn_network_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def info(self) -> TnNetworkInfo:
+        info = TnNetworkInfo()
+        check(lib().tn_network_get_info(self.h, C.byref(info)))
+        return info
+
+    def tensor(self, i: int):
+        rank = C.c_int32()
+        check(lib().tn_network_get_tensor(self.h, i, C.byref(rank), None, None))
+        labels = (C.c_int32 * max(rank.value, 1))()
+        data = np.zeros(2 * (1 << rank.value), dtype=np.float64)
+        check(lib().tn_network_get_tensor(self.h, i, C.byref(rank), labels,
+                                          data.ctypes.data_as(C.POINTER(C.c_double))))
+        return data.view(np.complex128).reshape((2,) * rank.value), list(labels)[:rank.value]
+
+    def output_labels(self) -> List[int]:
+        out = (C.c_int32 * self.n_qubits)()
+        check(lib().tn_network_output_labels(self.h, out))
+        return list(out)
+
+
+class Path:
+    def __init__(self, handle: int, cost: TnPathCost):
+        self.h = C.c_void_p(handle)
+        self.cost = cost
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().tn_path_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    @property
+    def pairs(self) -> List[tuple]:
+        n = self.cost.n_steps
+        buf = (C.c_int32 * max(2 * n, 1))()
+        check(lib().tn_path_get(self.h, buf, None))
+        return [(buf[2 * t], buf[2 * t + 1]) for t in range(n)]
+
+    @property
+    def sliced(self) -> List[int]:
+        n = self.cost.n_sliced
+        buf = (C.c_int32 * max(n, 1))()
+        check(lib().tn_path_get(self.h, None, buf))
+        return list(buf)[:n]
+
+
+def tn_build_network(n_qubits: int, ops) -> Network:
+    ca = _CircuitArgs(n_qubits, ops)
+    h = C.c_void_p()
+    check(lib().tn_build_network(C.byref(ca.circ), C.byref(h)))
+    return Network(h.value, n_qubits)
+
+
+def _path_opts(n_qubits, algo, trials, seed, temperature, budget, open_mask):
+    o = TnPathOpts()
+    o.algo = PATH_ALGO[algo] if isinstance(algo, str) else int(algo)
+    o.trials = int(trials)
+    o.seed = int(seed)
+    o.temperature = float(temperature)
+    o.mem_budget_bytes = float(budget)
+    keep = None
+    if open_mask is not None:
+        keep = np.ascontiguousarray(np.asarray(open_mask, dtype=np.int8))
+        assert keep.size == n_qubits
+        o.open_mask = keep.ctypes.data_as(C.POINTER(C.c_int8))
+    return o, keep
+
+
+def tn_find_path(net: Network, algo: str = "greedy", trials: int = 32, seed: int = 0,
+                 temperature: float = 1.0, mem_budget_bytes: float = 0.0,
+                 open_mask: Optional[Sequence[int]] = None) -> Path:
+    o, _keep = _path_opts(net.n_qubits, algo, trials, seed, temperature, mem_budget_bytes, open_mask)
+    h = C.c_void_p()
+    cost = TnPathCost()
+    check(lib().tn_find_path(net.h, C.byref(o), C.byref(h), C.byref(cost)))
+    return Path(h.value, cost)
+
+
+def tn_path_from_pairs(net: Network, pairs, mem_budget_bytes: float = 0.0,
+                       open_mask: Optional[Sequence[int]] = None) -> Path:
+    o, _keep = _path_opts(net.n_qubits, 0, 0, 0, 1.0, mem_budget_bytes, open_mask)
+    flat = (C.c_int32 * max(2 * len(pairs), 1))(*[int(x) for p in pairs for x in p])
+    h = C.c_void_p()
+    cost = TnPathCost()
+    check(lib().tn_path_from_pairs(net.h, C.byref(o), flat, len(pairs), C.byref(h), C.byref(cost)))
+    return Path(h.value, cost)
+
+
+def tn_set_workspace(buf) -> None:
+    """Register a device buffer (a torch tensor, kept alive by the caller)."""
+    if buf is None:
+        check(lib().tn_set_workspace(None, 0))
+    else:
+        check(lib().tn_set_workspace(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
+
+def _tensor(t, extents=None) -> tuple:
+    import torch
+    assert t.dtype == torch.complex64 and t.is_cuda and t.is_contiguous()
+    ext = list(t.shape) if extents is None else list(extents)
+    arr = (C.c_int64 * max(len(ext), 1))(*ext)
+    T = TnTensor(C.c_void_p(t.data_ptr()), len(ext), 0, arr)
+    return T, arr
+
+
+def tn_contract_pair(A, modesA, B, modesB, Cout, modesC, precision: str = "fp32", stream=None):
+    """Cout[modesC] = sum A[modesA] * B[modesB] (einsum semantics), on the GPU."""
+    TA, ka = _tensor(A)
+    TB, kb = _tensor(B)
+    TC, kc = _tensor(Cout)
+    ma = (C.c_int32 * max(len(modesA), 1))(*modesA)
+    mb = (C.c_int32 * max(len(modesB), 1))(*modesB)
+    mc = (C.c_int32 * max(len(modesC), 1))(*modesC)
+    check(lib().tn_contract_pair(C.byref(TA), ma, C.byref(TB), mb, C.byref(TC), mc,
+                                 PREC[precision] if isinstance(precision, str) else int(precision),
+                                 C.c_void_p(_stream_ptr(stream))))
+
+
+def tn_amplitudes_workspace(net: Network, path: Path, n_bs: int, precision: str = "fp32") -> int:
+    n = C.c_size_t()
+    check(lib().tn_amplitudes_workspace(net.h, path.h, int(n_bs), PREC[precision], C.byref(n)))
+    return n.value
+
+
+def tn_amplitudes(net: Network, path: Path, bits, out=None, precision: str = "fp32",
+                  use_graph: bool = False, slice_begin: int = 0, slice_count: int = -1,
+                  accumulate: bool = False, sync: bool = True, stream=None):
+    """Amplitudes of bit-strings (int array n_bs x n_qubits with 0/1/-1).
+
+    Returns (out, report): out is a complex128 CUDA tensor n_bs x 2^#open.
+    """
+    import torch
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.int8))
+    if b.ndim == 1:
+        b = b[None, :]
+    n_bs = b.shape[0]
+    n_open = int((b[0] < 0).sum())
+    if out is None:
+        out = torch.zeros((n_bs, 1 << n_open), dtype=torch.complex128, device="cuda")
+    o = TnExecOpts(PREC[precision], int(use_graph), int(slice_begin), int(slice_count),
+                   int(accumulate), int(sync))
+    rep = TnReport()
+    check(lib().tn_amplitudes(net.h, path.h, b.ctypes.data_as(C.POINTER(C.c_int8)), n_bs,
+                              C.byref(o), C.c_void_p(out.data_ptr()), C.byref(rep),
+                              C.c_void_p(_stream_ptr(stream))))
+    return out, rep
+
+
+class Mps:
+    def __init__(self, handle: int, n: int):
+        self.h = C.c_void_p(handle)
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().tn_mps_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def apply_gate1(self, site: int, U, stream=None):
+        u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128)).view(np.float64)
+        check(lib().tn_mps_apply_gate1(self.h, int(site), u.ctypes.data_as(C.POINTER(C.c_double)),
+                                       C.c_void_p(_stream_ptr(stream))))
+
+    def bond_dims(self) -> List[int]:
+        out = (C.c_int32 * max(self.n - 1, 1))()
+        check(lib().tn_mps_bond_dims(self.h, out))
+        return list(out)[:self.n - 1]
+
+    def expect_z(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.n)
+        check(lib().tn_mps_expect_z(self.h, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                    C.c_void_p(_stream_ptr(stream))))
+        return out
+
+    def amplitudes(self, bits, stream=None) -> np.ndarray:
+        b = np.ascontiguousarray(np.asarray(bits, dtype=np.int8))
+        if b.ndim == 1:
+            b = b[None, :]
+        out = np.zeros(2 * b.shape[0])
+        check(lib().tn_mps_amplitudes(self.h, b.ctypes.data_as(C.POINTER(C.c_int8)), b.shape[0],
+                                      out.ctypes.data_as(C.POINTER(C.c_double)),
+                                      C.c_void_p(_stream_ptr(stream))))
+        return out.view(np.complex128)
+
+
+def tn_mps_create(n_sites: int, chi_max: int, stream=None) -> Mps:
+    h = C.c_void_p()
+    check(lib().tn_mps_create(int(n_sites), int(chi_max), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    return Mps(h.value, n_sites)
+
+
+def tn_mps_apply_gate(mps: Mps, site: int, U, chi_max: int, cutoff: float = 1e-12, stream=None) -> float:
+    """Two-qubit gate on (site, site+1); returns the discarded weight."""
+    u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128)).view(np.float64)
+    disc = C.c_double()
+    check(lib().tn_mps_apply_gate(mps.h, int(site), u.ctypes.data_as(C.POINTER(C.c_double)),
+                                  int(chi_max), float(cutoff), C.byref(disc),
+                                  C.c_void_p(_stream_ptr(stream))))
+    return disc.value
+
+
+def tn_run_trajectories(circuits, traj_per_circ: int, uniforms, stream=None):
+    """circuits: list of (n_qubits, ops) with channels; uniforms: (n_traj, n_events) float64.
+
+    Returns (z, report) with z of shape (n_traj, n_qubits).
+    """
+    args = [_CircuitArgs(n, ops) for n, ops in circuits]
+    arr = (C.POINTER(TnCircuit) * len(args))(*[C.pointer(a.circ) for a in args])
+    u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+    n_traj = len(args) * traj_per_circ
+    nq = circuits[0][0]
+    z = np.zeros((n_traj, nq))
+    rep = TnReport()
+    check(lib().tn_run_trajectories(arr, len(args), int(traj_per_circ),
+                                    u.ctypes.data_as(C.POINTER(C.c_double)), u.shape[1],
+                                    z.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep),
+                                    C.c_void_p(_stream_ptr(stream))))
+    return z, rep

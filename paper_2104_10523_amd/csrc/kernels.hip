@@ -1,0 +1,756 @@
+// gfx950 kernels of the contraction hot path.
+//
+//  * permute_tiled   : bit permutation of a complex64 tensor through an LDS
+//                      tile; 32-element (256 B) runs on both the read and the
+//                      write side.
+//  * apply_small     : contraction of a large tensor with a small one
+//                      (<= 64 x 16 matrix) addressed by bit positions, so the
+//                      large operand is read once, in place, without a
+//                      separate permutation pass.
+//  * gemm_mfma       : complex GEMM on MFMA.  The complex product is a real
+//                      GEMM of the interleaved A (M x 2K) with the 2x2 real
+//                      block form of B ([[br, bi], [-bi, br]], 2K x 2N); the
+//                      product is C in interleaved form.  FP32 uses
+//                      v_mfma_f32_32x32x2_f32; BF16X3 / BF16X6 split each
+//                      operand into bfloat16 parts in LDS and use
+//                      v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
+//  * dot             : full contractions (M = N = 1) with split-K, FP64 sums.
+//  * gather / accumulate / job control: per-job leaf projection and FP64
+//                      accumulation of slice results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/tn.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace tn {
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static int grid_cap() { return 256 * 16; }
+
+// ------------------------------------------------------------------ permute
+
+struct PermArgs {
+  int tb, rb;
+  int64_t n_tiles;
+  int8_t tpos[10];
+  int8_t opos[10];
+  int8_t map[10];
+  int8_t r_in[kMaxBits];
+  int8_t r_out[kMaxBits];
+};
+
+__global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __restrict__ in,
+                                                            float2* __restrict__ out,
+                                                            PermArgs P) {
+  __shared__ int64_t s_in_lo[32], s_in_hi[32], s_out_lo[32], s_out_hi[32];
+  __shared__ int s_l_lo[32], s_l_hi[32];
+  __shared__ float2 tile[1024 + 32];
+  const int t = threadIdx.x;
+  if (t < 32) {
+    int64_t il = 0, ih = 0, ol = 0, oh = 0;
+    int ll = 0, lh = 0;
+    for (int i = 0; i < 5; ++i) {
+      if (!((t >> i) & 1)) continue;
+      if (i < P.tb) {
+        il |= int64_t(1) << P.tpos[i];
+        ol |= int64_t(1) << P.opos[i];
+        ll |= 1 << P.map[i];
+      }
+      if (i + 5 < P.tb) {
+        ih |= int64_t(1) << P.tpos[i + 5];
+        oh |= int64_t(1) << P.opos[i + 5];
+        lh |= 1 << P.map[i + 5];
+      }
+    }
+    s_in_lo[t] = il; s_in_hi[t] = ih;
+    s_out_lo[t] = ol; s_out_hi[t] = oh;
+    s_l_lo[t] = ll; s_l_hi[t] = lh;
+  }
+  __syncthreads();
+  const int tsize = 1 << P.tb;
+  for (int64_t tau = blockIdx.x; tau < P.n_tiles; tau += gridDim.x) {
+    int64_t ib = 0, ob = 0;
+    for (int k = 0; k < P.rb; ++k) {
+      if ((tau >> k) & 1) {
+        ib |= int64_t(1) << P.r_in[k];
+        ob |= int64_t(1) << P.r_out[k];
+      }
+    }
+    for (int e = t; e < tsize; e += 256)
+      tile[e + (e >> 5)] = in[ib + s_in_lo[e & 31] + s_in_hi[e >> 5]];
+    __syncthreads();
+    for (int f = t; f < tsize; f += 256) {
+      const int e = s_l_lo[f & 31] | s_l_hi[f >> 5];
+      out[ob + s_out_lo[f & 31] + s_out_hi[f >> 5]] = tile[e + (e >> 5)];
+    }
+    __syncthreads();
+  }
+}
+
+struct PermSimpleArgs {
+  int nb;
+  int8_t src[kMaxBits];
+};
+
+__global__ __launch_bounds__(256) void permute_simple_kernel(const float2* __restrict__ in,
+                                                             float2* __restrict__ out,
+                                                             PermSimpleArgs P, int64_t n) {
+  for (int64_t o = int64_t(blockIdx.x) * 256 + threadIdx.x; o < n; o += int64_t(gridDim.x) * 256) {
+    int64_t off = 0;
+    for (int j = 0; j < P.nb; ++j)
+      if (P.src[j] >= 0 && ((o >> j) & 1)) off |= int64_t(1) << P.src[j];
+    out[o] = in[off];
+  }
+}
+
+void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t s) {
+  const int nb = d.nb;
+  TN_REQUIRE(nb >= 0 && nb <= 62, TN_ERR_UNSUPPORTED, "tensor too large to permute");
+  const int64_t n = int64_t(1) << nb;
+  bool is_perm = d.nb_in == nb;
+  bool ident = true;
+  std::vector<int> inv(std::max(nb, 1), -1);
+  for (int j = 0; j < nb && is_perm; ++j) {
+    if (d.src[j] < 0 || d.src[j] >= nb || inv[d.src[j]] >= 0) {
+      is_perm = false;
+      break;
+    }
+    inv[d.src[j]] = j;
+    if (d.src[j] != j) ident = false;
+  }
+  if (is_perm && ident) {
+    TN_HIP(hipMemcpyAsync(out, in, size_t(n) * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  if (!is_perm || nb < 6) {
+    PermSimpleArgs P;
+    P.nb = nb;
+    for (int j = 0; j < kMaxBits; ++j) P.src[j] = j < nb ? d.src[j] : -1;
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
+    permute_simple_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, n);
+    TN_HIP(hipGetLastError());
+    return;
+  }
+  // tile bits: the 5 lowest input bits and the input bits of the 5 lowest
+  // output bits, padded with the next lowest input bits up to 10.
+  std::vector<char> inT(nb, 0);
+  const int a = std::min(5, nb);
+  for (int i = 0; i < a; ++i) inT[i] = 1;
+  for (int j = 0; j < a; ++j) inT[d.src[j]] = 1;
+  int cnt = 0;
+  for (int i = 0; i < nb; ++i) cnt += inT[i];
+  const int want = std::min(10, nb);
+  for (int i = 0; i < nb && cnt < want; ++i)
+    if (!inT[i]) { inT[i] = 1; ++cnt; }
+  PermArgs P;
+  std::memset(&P, 0, sizeof(P));
+  P.tb = cnt;
+  std::vector<int> tpos, opos;
+  for (int i = 0; i < nb; ++i)
+    if (inT[i]) tpos.push_back(i);
+  for (int j = 0; j < nb; ++j)
+    if (inT[d.src[j]]) opos.push_back(j);
+  for (int p = 0; p < cnt; ++p) {
+    P.tpos[p] = int8_t(tpos[p]);
+    P.opos[p] = int8_t(opos[p]);
+    const int src = d.src[opos[p]];
+    P.map[p] = int8_t(std::find(tpos.begin(), tpos.end(), src) - tpos.begin());
+  }
+  int rb = 0;
+  for (int i = 0; i < nb; ++i)
+    if (!inT[i]) {
+      P.r_in[rb] = int8_t(i);
+      P.r_out[rb] = int8_t(inv[i]);
+      ++rb;
+    }
+  P.rb = rb;
+  P.n_tiles = int64_t(1) << rb;
+  const int64_t blocks = std::min<int64_t>(P.n_tiles, 256 * 32);
+  permute_tiled_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P);
+  TN_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------------- apply_small
+
+struct ApplyArgs {
+  int nk, nn, n_b_extra;
+  int64_t n_rows;
+  int8_t kpos[8];
+  int8_t bk[8];
+  int8_t bn[8];
+  int8_t b_extra[12];
+};
+
+__device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
+
+template <int NN>
+__global__ __launch_bounds__(256) void apply_small_kernel(const float2* __restrict__ A,
+                                                          const float2* __restrict__ B,
+                                                          float2* __restrict__ C, ApplyArgs P) {
+  __shared__ float2 sB[64 * NN];
+  __shared__ int64_t s_koff[64];
+  const int KK = 1 << P.nk;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < KK * NN; idx += 256) {
+    const int k = idx / NN, n = idx % NN;
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if (P.bk[i] >= 0 && ((k >> i) & 1)) off |= int64_t(1) << P.bk[i];
+    for (int i = 0; i < P.nn; ++i)
+      if ((n >> i) & 1) off |= int64_t(1) << P.bn[i];
+    float2 v = make_float2(0.f, 0.f);
+    for (int e = 0; e < (1 << P.n_b_extra); ++e) {
+      int64_t o2 = off;
+      for (int i = 0; i < P.n_b_extra; ++i)
+        if ((e >> i) & 1) o2 |= int64_t(1) << P.b_extra[i];
+      const float2 b = B[o2];
+      v.x += b.x;
+      v.y += b.y;
+    }
+    sB[idx] = v;
+  }
+  if (t < KK) {
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if ((t >> i) & 1) off |= int64_t(1) << P.kpos[i];
+    s_koff[t] = off;
+  }
+  __syncthreads();
+  for (int64_t m = int64_t(blockIdx.x) * 256 + t; m < P.n_rows; m += int64_t(gridDim.x) * 256) {
+    int64_t base = m;
+    for (int i = 0; i < P.nk; ++i) {
+      const int p = P.kpos[i];
+      base = ((base >> p) << (p + 1)) | (base & ((int64_t(1) << p) - 1));
+    }
+    float2 acc[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) acc[n] = make_float2(0.f, 0.f);
+    for (int k = 0; k < KK; ++k) {
+      const float2 a = A[base + s_koff[k]];
+#pragma unroll
+      for (int n = 0; n < NN; ++n) cmac(acc[n], a, sB[k * NN + n]);
+    }
+#pragma unroll
+    for (int n = 0; n < NN; ++n) C[m * NN + n] = acc[n];
+  }
+}
+
+void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
+                        hipStream_t s) {
+  TN_REQUIRE(d.nk >= 0 && d.nk <= 6 && d.nn >= 0 && d.nn <= 4 && d.n_b_extra <= 12,
+             TN_ERR_UNSUPPORTED, "apply_small shape out of range");
+  ApplyArgs P;
+  std::memset(&P, 0, sizeof(P));
+  P.nk = d.nk;
+  P.nn = d.nn;
+  P.n_b_extra = d.n_b_extra;
+  P.n_rows = int64_t(1) << (d.a_bits - d.nk);
+  for (int i = 0; i < 8; ++i) {
+    P.kpos[i] = d.kpos[i];
+    P.bk[i] = d.bk[i];
+    P.bn[i] = d.bn[i];
+  }
+  for (int i = 0; i < 12; ++i) P.b_extra[i] = d.b_extra[i];
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
+  const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
+  switch (1 << d.nn) {
+    case 1: apply_small_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 2: apply_small_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 4: apply_small_kernel<4><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 8: apply_small_kernel<8><<<g, b, 0, s>>>(A, B, C, P); break;
+    default: apply_small_kernel<16><<<g, b, 0, s>>>(A, B, C, P); break;
+  }
+  TN_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------------- MFMA GEMM
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Split a complex value into NP bfloat16 parts, each packed (re | im << 16).
+template <int NP>
+__device__ __forceinline__ void split_c(float2 v, uint32_t* w) {
+  float r = v.x, i = v.y;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t hr = bf16_bits(r), hi = bf16_bits(i);
+    w[p] = hr | (hi << 16);
+    r -= bf16_to_float(hr);
+    i -= bf16_to_float(hi);
+  }
+}
+
+struct GemmArgs {
+  int64_t M, N, K;
+  int64_t kchunk;       // K range per split
+  int ksplit;
+  int transA, transB;
+  int tiles_m, tiles_n;
+};
+
+// Block tile BM x BN complex outputs, BK complex per K step; 4 waves laid out
+// WGM x WGN; each wave owns (BM/WGM) x (BN/WGN) = TM x TN MFMA tiles of
+// 32 rows x 16 complex columns.
+template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict__ A,
+                                                        const float2* __restrict__ B,
+                                                        float2* __restrict__ C, GemmArgs P) {
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 16;
+  static_assert(TM >= 1 && TN >= 1, "wave tile too small");
+  constexpr int NP = PREC == TN_PREC_FP32 ? 0 : (PREC == TN_PREC_BF16X3 ? 2 : 3);
+  // LDS: FP32 keeps float2; split modes keep NP packed bf16 planes.
+  constexpr int LDK = NP == 0 ? BK + 1 : BK + 4;          // row stride (elements)
+  constexpr int ELEM = NP == 0 ? 2 : NP;                   // 32-bit words per complex
+  __shared__ __attribute__((aligned(16))) uint32_t lds[(BM + BN) * LDK * ELEM];
+  uint32_t* As = lds;
+  uint32_t* Bs = lds + BM * LDK * ELEM;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+
+  // XCD-aware tile order: consecutive logical tiles land on one XCD.
+  const int nblk = gridDim.x;
+  int pid = blockIdx.x;
+  if ((nblk & 7) == 0) pid = (pid & 7) * (nblk >> 3) + (pid >> 3);
+  constexpr int GROUP = 8;
+  const int group_size = GROUP * P.tiles_n;
+  const int g = pid / group_size;
+  const int first_m = g * GROUP;
+  const int gm = min(P.tiles_m - first_m, GROUP);
+  const int tm_idx = first_m + (pid % group_size) % gm;
+  const int tn_idx = (pid % group_size) / gm;
+  const int64_t m0 = int64_t(tm_idx) * BM, n0 = int64_t(tn_idx) * BN;
+
+  const int zb = blockIdx.z;
+  const int ks = zb % P.ksplit;
+  const int64_t bidx = zb / P.ksplit;
+  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int64_t kend = min(P.K, kbeg + P.kchunk);
+  const float2* Ab = A + bidx * P.M * P.K;
+  const float2* Bb = B + bidx * P.K * P.N;
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  constexpr int A_PER = (BM * BK + 255) / 256, B_PER = (BN * BK + 255) / 256;
+  float2 ra[A_PER], rb[B_PER];
+
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int idx = tid + 256 * i;
+      int r, c;
+      if (P.transA == 0) { r = idx / BK; c = idx % BK; } else { c = idx / BM; r = idx % BM; }
+      const int64_t m = m0 + r, k = k0 + c;
+      float2 v = make_float2(0.f, 0.f);
+      if (idx < BM * BK && m < P.M && k < kend) v = P.transA == 0 ? Ab[m * P.K + k] : Ab[k * P.M + m];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int idx = tid + 256 * i;
+      int r, c;  // r = n, c = k
+      if (P.transB == 1) { r = idx / BK; c = idx % BK; } else { c = idx / BN; r = idx % BN; }
+      const int64_t n = n0 + r, k = k0 + c;
+      float2 v = make_float2(0.f, 0.f);
+      if (idx < BN * BK && n < P.N && k < kend) v = P.transB == 1 ? Bb[n * P.K + k] : Bb[k * P.N + n];
+      rb[i] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int idx = tid + 256 * i;
+      if (idx >= BM * BK) break;
+      int r, c;
+      if (P.transA == 0) { r = idx / BK; c = idx % BK; } else { c = idx / BM; r = idx % BM; }
+      if constexpr (NP == 0) {
+        As[(r * LDK + c) * 2] = __float_as_uint(ra[i].x);
+        As[(r * LDK + c) * 2 + 1] = __float_as_uint(ra[i].y);
+      } else {
+        uint32_t w[NP];
+        split_c<NP>(ra[i], w);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) As[(p * BM + r) * LDK + c] = w[p];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int idx = tid + 256 * i;
+      if (idx >= BN * BK) break;
+      int r, c;
+      if (P.transB == 1) { r = idx / BK; c = idx % BK; } else { c = idx / BN; r = idx % BN; }
+      if constexpr (NP == 0) {
+        Bs[(r * LDK + c) * 2] = __float_as_uint(rb[i].x);
+        Bs[(r * LDK + c) * 2 + 1] = __float_as_uint(rb[i].y);
+      } else {
+        uint32_t w[NP];
+        split_c<NP>(rb[i], w);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) Bs[(p * BN + r) * LDK + c] = w[p];
+      }
+    }
+  };
+
+  const int li = lane & 31, lh = lane >> 5;
+  const int bn_local = li >> 1, bt = li & 1;
+
+  if (kbeg < kend) load_tiles(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (k0 + BK < kend) load_tiles(k0 + BK);
+    if constexpr (NP == 0) {
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        float av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          av[i] = __uint_as_float(As[((wm0 + i * 32 + li) * LDK + kk) * 2 + lh]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int row = (wn0 + j * 16 + bn_local) * LDK + kk;
+          const float br = __uint_as_float(Bs[row * 2]), bi = __uint_as_float(Bs[row * 2 + 1]);
+          bv[j] = lh == 0 ? (bt == 0 ? br : bi) : (bt == 0 ? -bi : br);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 8) {
+        u32x4 av[NP][TM], bv[NP][TN];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+            av[p][i] = *reinterpret_cast<const u32x4*>(&As[(p * BM + wm0 + i * 32 + li) * LDK + kk + 4 * lh]);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            u32x4 w = *reinterpret_cast<const u32x4*>(&Bs[(p * BN + wn0 + j * 16 + bn_local) * LDK + kk + 4 * lh]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] = bt == 0 ? (w[q] ^ 0x80000000u) : ((w[q] >> 16) | (w[q] << 16));
+            bv[p][j] = w;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            // smallest products first: the FP32 accumulator sees them before
+            // the leading term is added
+#pragma unroll
+            for (int s = NP - 1; s >= 1; --s)
+#pragma unroll
+              for (int pa = 0; pa <= s; ++pa) {
+                const int pb = s - pa;
+                if (pb >= NP) continue;
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                    __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]),
+                    acc[i][j], 0, 0, 0);
+              }
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, av[0][i]), __builtin_bit_cast(bf16x8, bv[0][j]), acc[i][j],
+                0, 0, 0);
+          }
+      }
+    }
+  }
+
+  float* Cf = reinterpret_cast<float*>(C + (int64_t(ks) * gridDim.z / P.ksplit + bidx) * P.M * P.N);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t m = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int64_t n = n0 + wn0 + j * 16 + bn_local;
+        if (m < P.M && n < P.N) Cf[(m * P.N + n) * 2 + bt] = acc[i][j][r];
+      }
+}
+
+__global__ __launch_bounds__(256) void reduce_splitk_kernel(const float2* __restrict__ part,
+                                                            float2* __restrict__ C, int ksplit,
+                                                            int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    float2 s = part[i];
+    for (int k = 1; k < ksplit; ++k) {
+      const float2 v = part[int64_t(k) * n + i];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    C[i] = s;
+  }
+}
+
+namespace {
+struct TileCfg {
+  int bm, bn, bk;
+};
+TileCfg pick_tile(const GemmDesc& g) {
+  const int bk = g.precision == TN_PREC_FP32 ? 8 : 16;
+  if (g.N <= 16) return {256, 16, bk};
+  if (g.N <= 32) return {128, 32, bk};
+  return {128, 64, bk};
+}
+int pick_ksplit(const GemmDesc& g, const TileCfg& t, int64_t* kchunk) {
+  const int64_t tiles = ceil_div(g.M, t.bm) * ceil_div(g.N, t.bn) * g.batch;
+  int ks = 1;
+  const int64_t ksteps = ceil_div(g.K, t.bk);
+  while (tiles * ks < 1024 && ksteps / (ks * 2) >= 16 && ks < 256) ks *= 2;
+  *kchunk = ceil_div(ksteps, ks) * t.bk;
+  ks = int(ceil_div(g.K, *kchunk));
+  return ks;
+}
+}  // namespace
+
+size_t gemm_workspace_bytes(const GemmDesc& g) {
+  const TileCfg t = pick_tile(g);
+  int64_t kchunk;
+  const int ks = pick_ksplit(g, t, &kchunk);
+  return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
+static void launch_gemm_cfg(const float2* A, const float2* B, float2* C, const GemmArgs& P,
+                            int64_t batch, hipStream_t s) {
+  dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
+  gemm_mfma_kernel<BM, BN, BK, WGM, WGN, PREC><<<grid, 256, 0, s>>>(A, B, C, P);
+}
+
+template <int PREC, int BK>
+static void launch_gemm_prec(const float2* A, const float2* B, float2* C, const GemmArgs& P,
+                             int64_t batch, int bn, hipStream_t s) {
+  if (bn == 16) launch_gemm_cfg<256, 16, BK, 4, 1, PREC>(A, B, C, P, batch, s);
+  else if (bn == 32) launch_gemm_cfg<128, 32, BK, 4, 1, PREC>(A, B, C, P, batch, s);
+  else launch_gemm_cfg<128, 64, BK, 2, 2, PREC>(A, B, C, P, batch, s);
+}
+
+void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
+                 hipStream_t s) {
+  TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1, TN_ERR_ARG, "bad GEMM shape");
+  TN_REQUIRE(g.batch <= 65535, TN_ERR_UNSUPPORTED, "GEMM batch too large");
+  const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision
+                                                                                   : TN_PREC_FP32;
+  TileCfg t = pick_tile(g);
+  if (prec != TN_PREC_FP32) t.bk = 16;
+  GemmArgs P;
+  P.M = g.M;
+  P.N = g.N;
+  P.K = g.K;
+  P.transA = g.transA;
+  P.transB = g.transB;
+  P.ksplit = pick_ksplit(g, t, &P.kchunk);
+  P.tiles_m = int(ceil_div(g.M, t.bm));
+  P.tiles_n = int(ceil_div(g.N, t.bn));
+  TN_REQUIRE(int64_t(P.tiles_m) * P.tiles_n < (int64_t(1) << 31) &&
+                 g.batch * P.ksplit <= 65535,
+             TN_ERR_UNSUPPORTED, "GEMM grid too large");
+  float2* out = C;
+  if (P.ksplit > 1) {
+    TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "split-K GEMM needs workspace");
+    out = static_cast<float2*>(work);
+  }
+  switch (prec) {
+    case TN_PREC_FP32: launch_gemm_prec<TN_PREC_FP32, 8>(A, B, out, P, g.batch, t.bn, s); break;
+    case TN_PREC_BF16X3: launch_gemm_prec<TN_PREC_BF16X3, 16>(A, B, out, P, g.batch, t.bn, s); break;
+    default: launch_gemm_prec<TN_PREC_BF16X6, 16>(A, B, out, P, g.batch, t.bn, s); break;
+  }
+  TN_HIP(hipGetLastError());
+  if (P.ksplit > 1) {
+    const int64_t n = g.batch * g.M * g.N;
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
+    reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, P.ksplit, n);
+    TN_HIP(hipGetLastError());
+  }
+}
+
+// --------------------------------------------------------------------- dot
+
+__global__ __launch_bounds__(256) void dot_partial_kernel(const float2* __restrict__ A,
+                                                          const float2* __restrict__ B,
+                                                          double2* __restrict__ part, int64_t K) {
+  __shared__ double2 red[256];
+  const int64_t b = blockIdx.y;
+  const float2* a = A + b * K;
+  const float2* bb = B + b * K;
+  double sr = 0.0, si = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < K; k += int64_t(gridDim.x) * 256) {
+    const float2 x = a[k], y = bb[k];
+    sr += double(x.x) * double(y.x) - double(x.y) * double(y.y);
+    si += double(x.x) * double(y.y) + double(x.y) * double(y.x);
+  }
+  red[threadIdx.x] = make_double2(sr, si);
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x].x += red[threadIdx.x + w].x;
+      red[threadIdx.x].y += red[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void dot_final_kernel(const double2* __restrict__ part, float2* __restrict__ C, int nparts,
+                                 int64_t batch) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double sr = 0.0, si = 0.0;
+  for (int p = 0; p < nparts; ++p) {
+    sr += part[b * nparts + p].x;
+    si += part[b * nparts + p].y;
+  }
+  C[b] = make_float2(float(sr), float(si));
+}
+
+static int dot_parts(int64_t K) { return int(std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(K, 4096)))); }
+
+size_t dot_workspace_bytes(int64_t K, int64_t batch) {
+  return size_t(dot_parts(K)) * size_t(batch) * sizeof(double2);
+}
+
+void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, void* work,
+                hipStream_t s) {
+  TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "dot needs workspace");
+  TN_REQUIRE(batch <= 65535, TN_ERR_UNSUPPORTED, "dot batch too large");
+  const int parts = dot_parts(K);
+  dot_partial_kernel<<<dim3(parts, unsigned(batch)), 256, 0, s>>>(A, B, static_cast<double2*>(work), K);
+  TN_HIP(hipGetLastError());
+  dot_final_kernel<<<dim3(unsigned(ceil_div(batch, 256))), 256, 0, s>>>(static_cast<double2*>(work), C,
+                                                                       parts, batch);
+  TN_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------- jobs, leaves, output
+
+__global__ void set_job_kernel(int64_t* ctl, int64_t job) { ctl[0] = job; }
+__global__ void advance_job_kernel(int64_t* ctl) { ctl[0] += 1; }
+
+void launch_set_job(int64_t* ctl, int64_t job, hipStream_t s) {
+  set_job_kernel<<<1, 1, 0, s>>>(ctl, job);
+  TN_HIP(hipGetLastError());
+}
+void launch_advance_job(int64_t* ctl, hipStream_t s) {
+  advance_job_kernel<<<1, 1, 0, s>>>(ctl);
+  TN_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void gather_leaves_kernel(const float2* __restrict__ full,
+                                                            float2* __restrict__ arena,
+                                                            const LeafDesc* __restrict__ descs,
+                                                            const int8_t* __restrict__ bits,
+                                                            int n_qubits,
+                                                            const int64_t* __restrict__ ctl) {
+  const LeafDesc& d = descs[blockIdx.x];
+  const int64_t job = ctl[0], sbeg = ctl[1], scount = ctl[2];
+  const int64_t bs = job / scount;
+  const int64_t slice = sbeg + job % scount;
+  int64_t fixed_off = 0;
+  for (int f = 0; f < d.n_fixed; ++f) {
+    const LeafFixed& x = d.fixed[f];
+    const int v = x.kind == 0 ? int(bits[bs * n_qubits + x.which]) : int((slice >> x.which) & 1);
+    if (v) fixed_off |= int64_t(1) << x.pos;
+  }
+  const int n = 1 << d.out_bits;
+  for (int o = threadIdx.x; o < n; o += blockDim.x) {
+    int64_t off = fixed_off;
+    for (int j = 0; j < d.out_bits; ++j)
+      if ((o >> j) & 1) off |= int64_t(1) << d.in_pos[j];
+    arena[d.dst_off + o] = full[d.src_off + off];
+  }
+}
+
+void launch_gather_leaves(const float2* full, float2* arena, const LeafDesc* descs, int n_leaves,
+                          int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
+                          hipStream_t s) {
+  if (n_leaves == 0) return;
+  const int threads = std::min(256, std::max(64, 1 << max_out));
+  gather_leaves_kernel<<<dim3(n_leaves), dim3(threads), 0, s>>>(full, arena, descs, bits, n_qubits, ctl);
+  TN_HIP(hipGetLastError());
+}
+
+struct AccArgs {
+  int nbits;
+  int accumulate;
+  int8_t pos[kMaxBits];
+};
+
+__global__ __launch_bounds__(256) void accumulate_kernel(const float2* __restrict__ R,
+                                                         double2* __restrict__ out, AccArgs P,
+                                                         const int64_t* __restrict__ ctl) {
+  const int64_t job = ctl[0], scount = ctl[2];
+  const int64_t bs = job / scount;
+  const bool add = P.accumulate || (job % scount) != 0;
+  const int64_t n = int64_t(1) << P.nbits;
+  double2* o = out + bs * n;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    int64_t src = 0;
+    for (int j = 0; j < P.nbits; ++j)
+      if ((i >> j) & 1) src |= int64_t(1) << P.pos[j];
+    const float2 v = R[src];
+    double2 r = make_double2(double(v.x), double(v.y));
+    if (add) {
+      r.x += o[i].x;
+      r.y += o[i].y;
+    }
+    o[i] = r;
+  }
+}
+
+void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* pos_of_bit,
+                       const int64_t* ctl, int accumulate, hipStream_t s) {
+  AccArgs P;
+  std::memset(&P, 0, sizeof(P));
+  P.nbits = nbits;
+  P.accumulate = accumulate;
+  for (int j = 0; j < nbits; ++j) P.pos[j] = pos_of_bit[j];
+  const int64_t n = int64_t(1) << nbits;
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
+  accumulate_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(R, out, P, ctl);
+  TN_HIP(hipGetLastError());
+}
+
+__global__ void nonfinite_kernel(const double2* __restrict__ x, int64_t n, int* flag) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    if (!isfinite(x[i].x) || !isfinite(x[i].y)) *flag = 1;
+}
+
+void launch_nonfinite(const double2* x, int64_t n, int* flag, hipStream_t s) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 1024));
+  nonfinite_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(x, n, flag);
+  TN_HIP(hipGetLastError());
+}
+
+}  // namespace tn

@@ -1,0 +1,89 @@
+// Launch interface of the gfx950 kernels.  Every tensor is complex64
+// (float2), row-major, with power-of-two extents viewed as bits: bit 0 is the
+// fastest-varying index bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tn {
+
+constexpr int kMaxBits = 64;
+
+// Bit permutation out[o] = in[gather(o)]: output bit j takes input bit src[j];
+// src[j] == -1 broadcasts (stride 0).  `nb` output bits; `nb_in` input bits.
+struct PermuteDesc {
+  int nb = 0;
+  int nb_in = 0;
+  int8_t src[kMaxBits];
+};
+void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t s);
+
+// C[m * 2^nn + n] = sum_k A[expand(m) + kscat(k)] * B[bscat(k, n)]
+//   A: `a_bits` bits; K bits of A at positions kpos (ascending), others are M.
+//   B: small (<= 2^12 entries); its K bits at bk[] and N bits at bn[] (bit
+//      positions in B's index; -1 = stride 0, i.e. B broadcast along a bit);
+//   A's "dangling" bits (summed out) are K bits with bk = -1.
+// Row-major output [M bits of A in A's order][N bits in bn order].
+struct ApplySmallDesc {
+  int a_bits = 0;
+  int nk = 0;              // number of K bits (<= 6)
+  int nn = 0;              // number of N bits (<= 4)
+  int nb_b = 0;            // bits of B
+  int8_t kpos[8];          // in A, ascending
+  int8_t bk[8];            // K bit i of B (bit i of k <-> kpos[i])
+  int8_t bn[8];            // N bit i of B
+  int8_t b_extra[12];      // B bits summed out (dangling in B), -1 padded
+  int n_b_extra = 0;
+};
+void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
+                        hipStream_t s);
+
+// Complex GEMM C[b][m][n] = sum_k A[b](m,k) * B[b](k,n), contiguous operands.
+// transA = 0: A[b][m][k]; 1: A[b][k][m].  transB = 0: B[b][k][n]; 1: B[b][n][k].
+struct GemmDesc {
+  int64_t M = 1, N = 1, K = 1, batch = 1;
+  int transA = 0, transB = 0;
+  int precision = 0;       // TN_PREC_FP32 / BF16X3 / BF16X6
+};
+// Workspace needed for split-K partials (bytes); 0 when no split is used.
+size_t gemm_workspace_bytes(const GemmDesc& g);
+void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
+                 hipStream_t s);
+
+// Gather every leaf of one job into the leaf arena: fixed labels take their
+// value from the job's bit-string (kind 0) or slice index (kind 1).
+struct LeafFixed {
+  int8_t pos;      // bit position in the full (unprojected) leaf
+  int8_t kind;     // 0: bit-string entry, 1: slice bit
+  int16_t which;   // qubit index, or slice bit number (0 = LSB of slice id)
+};
+struct LeafDesc {
+  int64_t src_off;
+  int64_t dst_off;
+  int32_t out_bits;
+  int32_t n_fixed;
+  int8_t in_pos[8];          // full-leaf bit position of output bit j
+  LeafFixed fixed[8];
+};
+// ctl: device int64 [0] = job index, [1] = slice_begin, [2] = slice_count.
+void launch_gather_leaves(const float2* full, float2* arena, const LeafDesc* descs, int n_leaves,
+                          int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
+                          hipStream_t s);
+void launch_set_job(int64_t* ctl, int64_t job, hipStream_t s);
+void launch_advance_job(int64_t* ctl, hipStream_t s);
+
+// out[b][i] (complex128) (+)= R[gather(i)]; b = job / slice_count.
+void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* pos_of_bit,
+                       const int64_t* ctl, int accumulate_first, hipStream_t s);
+
+// Dot products (M = N = 1) with split-K; result written as complex64.
+size_t dot_workspace_bytes(int64_t K, int64_t batch);
+void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, void* work,
+                hipStream_t s);
+
+// Sets *flag to 1 if any entry of x is non-finite.
+void launch_nonfinite(const double2* x, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace tn

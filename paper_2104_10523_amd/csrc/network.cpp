@@ -1,0 +1,331 @@
+// Circuit -> tensor network (Sec. 3.1, Fig. 1) and the pairwise path planner
+// (Sec. 3.1: Flop-minimising contraction order, index slicing).
+//
+// Network: qubits are rank-1 tensors, one-qubit gates rank-2 and two-qubit
+// gates rank-4.  Small gate tensors are folded into the two-qubit gates
+// (Sec. 3.1.1): a wire's |0> input and the one-qubit gates before a two-qubit
+// gate go into that gate's input side, trailing one-qubit gates into the last
+// gate's output leg; a wire without two-qubit gates is one rank-1 tensor.
+// Tensors: two-qubit gates in circuit order, then lone wires in qubit order.
+// Labels are handed out as legs are created (a's output, then b's).
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+#include "network.hpp"
+
+namespace tn {
+
+Network build_network(const tn_circuit& c) {
+  TN_REQUIRE(c.n_qubits >= 1 && c.n_qubits <= 4096, TN_ERR_ARG, "n_qubits out of range");
+  TN_REQUIRE(c.n_ops >= 0 && (c.n_ops == 0 || c.ops != nullptr), TN_ERR_ARG, "bad op list");
+  const int n = c.n_qubits;
+  Network net;
+  net.n_qubits = n;
+  std::vector<Mat> pend(n, Mat::identity(2));
+  std::vector<int> wire(n, -1);
+  std::vector<std::pair<int, int>> owner(n, {-1, -1});
+  int nxt = 0;
+  for (int64_t k = 0; k < c.n_ops; ++k) {
+    const tn_op& op = c.ops[k];
+    TN_REQUIRE(!gate_is_channel(op.gate), TN_ERR_GATE,
+               "channel op in a noiseless network (use tn_run_trajectories)");
+    const int ar = gate_arity(op.gate);
+    TN_REQUIRE(op.q0 >= 0 && op.q0 < n, TN_ERR_GATE, "qubit index out of range");
+    if (ar == 1) {
+      pend[op.q0] = matmul(gate_unitary(op), pend[op.q0]);
+      continue;
+    }
+    const int a = op.q0, b = op.q1;
+    TN_REQUIRE(b >= 0 && b < n && a != b, TN_ERR_GATE, "bad second qubit");
+    Mat U = matmul(gate_unitary(op), kron(pend[a], pend[b]));
+    pend[a] = Mat::identity(2);
+    pend[b] = Mat::identity(2);
+    // U row = (oa, ob), col = (ia, ib); tensor axes [oa, ob, (ia), (ib)]
+    const bool keep_a = wire[a] >= 0, keep_b = wire[b] >= 0;
+    NetTensor t;
+    t.labels = {nxt, nxt + 1};
+    if (keep_a) t.labels.push_back(wire[a]);
+    if (keep_b) t.labels.push_back(wire[b]);
+    nxt += 2;
+    const int ra = keep_a ? 2 : 1, rb = keep_b ? 2 : 1;
+    t.data.assign(size_t(4) * ra * rb, cd(0, 0));
+    for (int oa = 0; oa < 2; ++oa)
+      for (int ob = 0; ob < 2; ++ob)
+        for (int ia = 0; ia < ra; ++ia)
+          for (int ib = 0; ib < rb; ++ib)
+            t.data[((size_t(oa) * 2 + ob) * ra + ia) * rb + ib] = U(oa * 2 + ob, ia * 2 + ib);
+    const int tid = int(net.tensors.size());
+    net.tensors.push_back(std::move(t));
+    wire[a] = nxt - 2;
+    wire[b] = nxt - 1;
+    owner[a] = {tid, 0};
+    owner[b] = {tid, 1};
+  }
+  for (int q = 0; q < n; ++q) {
+    if (owner[q].first < 0 || is_identity(pend[q])) continue;
+    NetTensor& t = net.tensors[owner[q].first];
+    const int ax = owner[q].second, rank = int(t.labels.size());
+    const size_t stride = size_t(1) << (rank - 1 - ax);
+    for (size_t i = 0; i < t.data.size(); ++i) {
+      if (i & stride) continue;
+      const cd x0 = t.data[i], x1 = t.data[i | stride];
+      t.data[i] = pend[q](0, 0) * x0 + pend[q](0, 1) * x1;
+      t.data[i | stride] = pend[q](1, 0) * x0 + pend[q](1, 1) * x1;
+    }
+  }
+  for (int q = 0; q < n; ++q) {
+    if (owner[q].first >= 0) continue;
+    NetTensor t;
+    t.labels = {nxt};
+    t.data = {pend[q](0, 0), pend[q](1, 0)};
+    net.tensors.push_back(std::move(t));
+    wire[q] = nxt++;
+  }
+  net.out_label = wire;
+  net.n_labels = nxt;
+  return net;
+}
+
+// ---------------------------------------------------------------- planner
+
+uint64_t splitmix64_next(uint64_t* s) {
+  *s += 0x9E3779B97F4A7C15ull;
+  uint64_t z = *s;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double splitmix64_uniform(uint64_t* s) {
+  return double(splitmix64_next(s) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+namespace {
+
+using Set = std::vector<int>;  // sorted labels
+
+Set set_union(const Set& a, const Set& b) {
+  Set r;
+  r.reserve(a.size() + b.size());
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
+  return r;
+}
+
+double size_of(const Set& s, const std::vector<double>& ext) {
+  double v = 1.0;
+  for (int l : s) v = v * ext[l];
+  return v;
+}
+
+struct State {
+  const PathProblem& pr;
+  std::vector<Set> sets;     // by SSA id; empty + !alive when consumed
+  std::vector<char> alive;
+  std::vector<int> count;
+  int n_alive = 0;
+
+  State(const PathProblem& p, const std::vector<int>& sliced) : pr(p), count(p.ext.size(), 0) {
+    std::vector<char> cut(p.ext.size(), 0);
+    for (int l : sliced) cut[l] = 1;
+    for (const Set& s : p.leaves) {
+      Set t;
+      for (int l : s)
+        if (!cut[l]) t.push_back(l);
+      for (int l : t) count[l]++;
+      sets.push_back(std::move(t));
+      alive.push_back(1);
+      n_alive++;
+    }
+  }
+
+  Set result(int i, int j) const {
+    const Set &a = sets[i], &b = sets[j];
+    Set u = set_union(a, b), c;
+    for (int l : u) {
+      const int in_a = std::binary_search(a.begin(), a.end(), l);
+      const int in_b = std::binary_search(b.begin(), b.end(), l);
+      if (pr.open[l] || count[l] - in_a - in_b > 0) c.push_back(l);
+    }
+    return c;
+  }
+
+  int merge(int i, int j) {
+    Set c = result(i, j);
+    for (int l : sets[i]) count[l]--;
+    for (int l : sets[j]) count[l]--;
+    for (int l : c) count[l]++;
+    sets[i].clear();
+    sets[j].clear();
+    alive[i] = alive[j] = 0;
+    sets.push_back(std::move(c));
+    alive.push_back(1);
+    n_alive--;
+    return int(sets.size()) - 1;
+  }
+
+  std::vector<std::pair<int, int>> candidates() const {
+    std::vector<std::vector<int>> by_label(pr.ext.size());
+    for (size_t i = 0; i < sets.size(); ++i)
+      if (alive[i])
+        for (int l : sets[i]) by_label[l].push_back(int(i));
+    std::vector<std::pair<int, int>> pairs;
+    for (const auto& ids : by_label)
+      for (size_t x = 0; x < ids.size(); ++x)
+        for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
+    if (pairs.empty()) {
+      std::vector<int> ids;
+      for (size_t i = 0; i < sets.size(); ++i)
+        if (alive[i]) ids.push_back(int(i));
+      for (size_t x = 0; x < ids.size(); ++x)
+        for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
+    }
+    std::sort(pairs.begin(), pairs.end());
+    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+    return pairs;
+  }
+};
+
+}  // namespace
+
+std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng,
+                                             double temperature) {
+  State st(pr, {});
+  std::vector<std::pair<int, int>> path;
+  while (st.n_alive > 1) {
+    auto cands = st.candidates();
+    std::vector<double> d(cands.size()), fl(cands.size());
+    for (size_t k = 0; k < cands.size(); ++k) {
+      const auto [i, j] = cands[k];
+      const Set c = st.result(i, j);
+      d[k] = size_of(c, pr.ext) - size_of(st.sets[i], pr.ext) - size_of(st.sets[j], pr.ext);
+      fl[k] = 8.0 * size_of(set_union(st.sets[i], st.sets[j]), pr.ext);
+    }
+    size_t pick = 0;
+    if (rng == nullptr) {
+      for (size_t k = 1; k < cands.size(); ++k) {
+        if (d[k] < d[pick] || (d[k] == d[pick] && (fl[k] < fl[pick] ||
+            (fl[k] == fl[pick] && cands[k] < cands[pick]))))
+          pick = k;
+      }
+    } else {
+      std::vector<double> sig(cands.size());
+      double smin = std::numeric_limits<double>::infinity();
+      for (size_t k = 0; k < cands.size(); ++k) {
+        sig[k] = std::copysign(std::log2(1.0 + std::fabs(d[k])), d[k]);
+        smin = std::min(smin, sig[k]);
+      }
+      std::vector<double> w(cands.size());
+      double tot = 0.0;
+      for (size_t k = 0; k < cands.size(); ++k) {
+        w[k] = std::exp(-(sig[k] - smin) / temperature);
+        tot += w[k];
+      }
+      const double u = splitmix64_uniform(rng) * tot;
+      double acc = 0.0;
+      pick = cands.size() - 1;
+      for (size_t k = 0; k < cands.size(); ++k) {
+        acc += w[k];
+        if (acc >= u) { pick = k; break; }
+      }
+    }
+    st.merge(cands[pick].first, cands[pick].second);
+    path.push_back(cands[pick]);
+  }
+  return path;
+}
+
+PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                     const std::vector<int>& sliced) {
+  State st(pr, sliced);
+  const int n_leaves = int(pr.leaves.size());
+  TN_REQUIRE(int(path.size()) == std::max(n_leaves - 1, 0), TN_ERR_ARG,
+             "path must have n_tensors - 1 steps");
+  PathStats ps;
+  double live = 0.0;
+  for (const Set& s : st.sets) live += size_of(s, pr.ext);
+  for (size_t t = 0; t < path.size(); ++t) {
+    const int i = path[t].first, j = path[t].second;
+    TN_REQUIRE(i >= 0 && j >= 0 && i != j && i < int(st.sets.size()) && j < int(st.sets.size()) &&
+                   st.alive[i] && st.alive[j],
+               TN_ERR_ARG, "path step uses a consumed or unknown tensor");
+    Step s;
+    s.i = i;
+    s.j = j;
+    s.a = st.sets[i];
+    s.b = st.sets[j];
+    s.c = st.result(i, j);
+    const double sa = size_of(s.a, pr.ext), sb = size_of(s.b, pr.ext), sc = size_of(s.c, pr.ext);
+    const double p = live + sc + sa + sb;
+    if (p > ps.peak) {
+      ps.peak = p;
+      ps.peak_step = int(t);
+    }
+    ps.flops += 8.0 * size_of(set_union(s.a, s.b), pr.ext);
+    st.merge(i, j);
+    live = live - sa - sb + sc;
+    ps.steps.push_back(std::move(s));
+  }
+  if (path.empty()) ps.peak = live;
+  Set sl(sliced.begin(), sliced.end());
+  std::sort(sl.begin(), sl.end());
+  ps.n_slices = 1.0;
+  for (int l : sl) ps.n_slices *= pr.ext[l];
+  ps.total_flops = ps.flops * ps.n_slices;
+  return ps;
+}
+
+std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
+                                                    int trials, double temperature) {
+  auto best = greedy_path(pr, nullptr, temperature);
+  PathStats bs = path_stats(pr, best, {});
+  double bf = bs.flops, bp = bs.peak;
+  for (int r = 0; r < trials; ++r) {
+    uint64_t g = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
+    uint64_t st = splitmix64_next(&g);
+    auto p = greedy_path(pr, &st, temperature);
+    PathStats s = path_stats(pr, p, {});
+    if (s.flops < bf || (s.flops == bf && s.peak < bp)) {
+      best = std::move(p);
+      bf = s.flops;
+      bp = s.peak;
+    }
+  }
+  return best;
+}
+
+std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                            double budget_bytes) {
+  std::vector<int> sliced;
+  if (budget_bytes <= 0) return sliced;
+  PathStats cur = path_stats(pr, path, sliced);
+  while (8.0 * cur.peak > budget_bytes) {
+    TN_REQUIRE(cur.peak_step >= 0, TN_ERR_BUDGET, "memory budget smaller than the leaves");
+    const Step& s = cur.steps[cur.peak_step];
+    Set u = set_union(set_union(s.a, s.b), s.c);
+    bool found = false;
+    double bpk = 0, bfl = 0;
+    int bl = -1;
+    PathStats bst;
+    for (int l : u) {
+      if (pr.open[l] || std::find(sliced.begin(), sliced.end(), l) != sliced.end()) continue;
+      auto trial = sliced;
+      trial.push_back(l);
+      PathStats ts = path_stats(pr, path, trial);
+      if (!found || ts.peak < bpk || (ts.peak == bpk && (ts.total_flops < bfl ||
+                                                        (ts.total_flops == bfl && l < bl)))) {
+        found = true;
+        bpk = ts.peak;
+        bfl = ts.total_flops;
+        bl = l;
+        bst = std::move(ts);
+      }
+    }
+    TN_REQUIRE(found, TN_ERR_BUDGET, "memory budget cannot be met by slicing");
+    sliced.push_back(bl);
+    cur = std::move(bst);
+  }
+  return sliced;
+}
+
+}  // namespace tn

@@ -1,0 +1,62 @@
+// Circuit -> tensor network and the path planner (host side).
+#pragma once
+
+#include <map>
+#include <vector>
+
+#include "common.hpp"
+#include "gates.hpp"
+
+namespace tn {
+
+// One network tensor: axes labelled by integers, every extent 2 (qubit legs).
+struct NetTensor {
+  std::vector<int> labels;   // axis order, row-major data
+  std::vector<cd> data;      // 2^rank entries
+};
+
+struct Network {
+  int n_qubits = 0;
+  int n_labels = 0;
+  std::vector<NetTensor> tensors;
+  std::vector<int> out_label;  // per qubit
+};
+
+// Folds |0> inputs and one-qubit gates into two-qubit gate tensors; see tn.h.
+Network build_network(const tn_circuit& c);
+
+// Cost model evaluated in IEEE double arithmetic (mirrors tn.h).
+struct Step {
+  int i, j;                    // SSA ids of the operands
+  std::vector<int> a, b, c;    // sorted label sets after slicing
+};
+
+struct PathStats {
+  double flops = 0;            // per slice
+  double peak = 0;             // live + |C| + |A| + |B| (elements)
+  int peak_step = -1;
+  double n_slices = 1;
+  double total_flops = 0;
+  std::vector<Step> steps;
+};
+
+using LabelSets = std::vector<std::vector<int>>;  // sorted labels per leaf
+
+struct PathProblem {
+  LabelSets leaves;            // labels after removing projected outputs
+  std::vector<double> ext;     // extent per label
+  std::vector<char> open;      // per label: 1 = open output
+};
+
+std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng_state,
+                                             double temperature);
+std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
+                                                    int trials, double temperature);
+PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                     const std::vector<int>& sliced);
+std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                            double budget_bytes);
+uint64_t splitmix64_next(uint64_t* state);
+double splitmix64_uniform(uint64_t* state);
+
+}  // namespace tn

@@ -1,0 +1,500 @@
+// Plan compiler: a pairwise contraction becomes one of
+//   apply  - large operand read in place by bit positions, small operand
+//            (<= 2^12 entries) staged in LDS;
+//   gemm   - operands brought into [batch][M][K] / [batch][K][N] (or the
+//            transposed forms) by bit permutations only when their layout is
+//            not already grouped that way, then a complex MFMA GEMM;
+//   dot    - full contraction of two operands.
+// Results of the GEMM are laid out [batch][M][N], so the next step often
+// finds its operand grouped already.  Workspace is carved from one arena by
+// liveness (first fit).
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <set>
+
+namespace tn {
+
+// ------------------------------------------------------------------ arena
+
+int64_t Arena::alloc(int64_t elems) {
+  const int64_t len = ((std::max<int64_t>(elems, 1) + 31) / 32) * 32;
+  int64_t cur = 0;
+  size_t pos = 0;
+  for (; pos < used_.size(); ++pos) {
+    if (used_[pos].first - cur >= len) break;
+    cur = used_[pos].first + used_[pos].second;
+  }
+  used_.insert(used_.begin() + pos, {cur, len});
+  high_ = std::max(high_, cur + len);
+  return cur;
+}
+
+void Arena::release(int64_t off) {
+  for (size_t i = 0; i < used_.size(); ++i)
+    if (used_[i].first == off) {
+      used_.erase(used_.begin() + i);
+      return;
+    }
+  throw Error(TN_ERR_ARG, "internal: arena release of unknown block");
+}
+
+// ------------------------------------------------------------ pair compile
+
+namespace {
+
+int pos_of(const std::vector<int>& layout, int label) {
+  const auto it = std::find(layout.begin(), layout.end(), label);
+  if (it == layout.end()) return -1;
+  return int(layout.size()) - 1 - int(it - layout.begin());
+}
+
+std::vector<int> filter(const std::vector<int>& v, const std::set<int>& s, bool in) {
+  std::vector<int> r;
+  for (int l : v)
+    if ((s.count(l) > 0) == in) r.push_back(l);
+  return r;
+}
+
+std::vector<int> cat(std::initializer_list<std::vector<int>> parts) {
+  std::vector<int> r;
+  for (const auto& p : parts) r.insert(r.end(), p.begin(), p.end());
+  return r;
+}
+
+// relative order of `sub` labels as they appear in `layout`
+std::vector<int> order_in(const std::vector<int>& layout, const std::set<int>& sub) {
+  std::vector<int> r;
+  for (int l : layout)
+    if (sub.count(l)) r.push_back(l);
+  return r;
+}
+
+double p2(size_t bits) { return std::ldexp(1.0, int(bits)); }
+
+TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
+                  std::vector<PlanOp>& ops, std::vector<int64_t>* scratch, int out_buf = -1,
+                  int64_t out_off = 0) {
+  PlanOp op;
+  op.kind = OP_PERMUTE;
+  op.pm.nb = int(target.size());
+  op.pm.nb_in = int(in.labels.size());
+  TN_REQUIRE(op.pm.nb <= kMaxBits && op.pm.nb_in <= kMaxBits, TN_ERR_UNSUPPORTED, "rank > 64");
+  for (int j = 0; j < op.pm.nb; ++j)
+    op.pm.src[j] = int8_t(pos_of(in.labels, target[op.pm.nb - 1 - j]));
+  TRef out;
+  out.labels = target;
+  if (out_buf >= 0) {
+    out.buf = out_buf;
+    out.off = out_off;
+  } else {
+    out.buf = BUF_WORK;
+    out.off = arena.alloc(int64_t(1) << op.pm.nb);
+    scratch->push_back(out.off);
+  }
+  op.a_buf = in.buf;
+  op.a_off = in.off;
+  op.c_buf = out.buf;
+  op.c_off = out.off;
+  op.bytes = 8.0 * (p2(op.pm.nb) + p2(op.pm.nb_in));
+  ops.push_back(op);
+  return out;
+}
+
+// Sum out `dang` labels of X (apply against the constant 1).
+TRef emit_sum_out(const TRef& X, const std::vector<int>& dang, Arena& arena,
+                  std::vector<PlanOp>& ops, std::vector<int64_t>* scratch) {
+  TN_REQUIRE(dang.size() <= 6, TN_ERR_UNSUPPORTED, "too many summed-out labels");
+  PlanOp op;
+  op.kind = OP_APPLY;
+  std::memset(&op.ap, 0, sizeof(op.ap));
+  std::memset(op.ap.b_extra, -1, sizeof(op.ap.b_extra));
+  op.ap.a_bits = int(X.labels.size());
+  std::vector<int> kp;
+  for (int l : dang) kp.push_back(pos_of(X.labels, l));
+  std::sort(kp.begin(), kp.end());
+  op.ap.nk = int(kp.size());
+  for (int i = 0; i < 8; ++i) {
+    op.ap.kpos[i] = i < op.ap.nk ? int8_t(kp[i]) : 0;
+    op.ap.bk[i] = -1;
+    op.ap.bn[i] = 0;
+  }
+  op.ap.nn = 0;
+  op.ap.nb_b = 0;
+  TRef out;
+  out.labels = filter(X.labels, std::set<int>(dang.begin(), dang.end()), false);
+  out.buf = BUF_WORK;
+  out.off = arena.alloc(int64_t(1) << out.labels.size());
+  scratch->push_back(out.off);
+  op.a_buf = X.buf;
+  op.a_off = X.off;
+  op.b_buf = BUF_ONE;
+  op.b_off = 0;
+  op.c_buf = out.buf;
+  op.c_off = out.off;
+  op.flops = 8.0 * p2(X.labels.size());
+  op.bytes = 8.0 * (p2(X.labels.size()) + p2(out.labels.size()));
+  ops.push_back(op);
+  return out;
+}
+
+int resolve_precision(int precision, int64_t M, int64_t N, int64_t K) {
+  if (precision != TN_PREC_AUTO) return precision;
+  return (K >= 64 && M >= 1024 && N >= 64) ? TN_PREC_BF16X3 : TN_PREC_FP32;
+}
+
+}  // namespace
+
+TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v,
+                  const std::vector<int>* want, int want_buf, int64_t want_off, Arena& arena,
+                  int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch) {
+  const std::set<int> keep(keep_v.begin(), keep_v.end());
+  TRef X = X0, Y = Y0;
+  {
+    std::set<int> sx(X.labels.begin(), X.labels.end()), sy(Y.labels.begin(), Y.labels.end());
+    for (int l : keep) TN_REQUIRE(sx.count(l) || sy.count(l), TN_ERR_MODES, "result label not in an operand");
+  }
+  auto dangling = [&](const TRef& T, const TRef& O) {
+    std::set<int> so(O.labels.begin(), O.labels.end());
+    std::vector<int> d;
+    for (int l : T.labels)
+      if (!so.count(l) && !keep.count(l)) d.push_back(l);
+    return d;
+  };
+  const auto dx = dangling(X, Y), dy = dangling(Y, X);
+  const bool x_big = X.labels.size() >= Y.labels.size();
+  TRef& big = x_big ? X : Y;
+  TRef& small = x_big ? Y : X;
+  const std::set<int> sbig(big.labels.begin(), big.labels.end()), ssmall(small.labels.begin(), small.labels.end());
+  std::vector<int> K, batch, Nsm;
+  for (int l : big.labels)
+    if (ssmall.count(l)) (keep.count(l) ? batch : K).push_back(l);
+  for (int l : small.labels)
+    if (!sbig.count(l) && keep.count(l)) Nsm.push_back(l);
+  const auto& dbig = x_big ? dx : dy;
+  const auto& dsmall = x_big ? dy : dx;
+
+  // ------------------------------------------------------------ apply path
+  if (batch.empty() && small.labels.size() <= 12 && K.size() + dbig.size() <= 6 && Nsm.size() <= 4 &&
+      dsmall.size() <= 12) {
+    const std::set<int> kset(K.begin(), K.end()), dbset(dbig.begin(), dbig.end());
+    std::vector<int> Mbig;
+    for (int l : big.labels)
+      if (!kset.count(l) && !dbset.count(l)) Mbig.push_back(l);
+    std::vector<int> Norder = Nsm;
+    bool direct = false;
+    if (want) {
+      if (want->size() == Mbig.size() + Nsm.size() &&
+          std::equal(Mbig.begin(), Mbig.end(), want->begin())) {
+        std::vector<int> wn(want->begin() + Mbig.size(), want->end());
+        std::vector<int> a = wn, b = Nsm;
+        std::sort(a.begin(), a.end());
+        std::sort(b.begin(), b.end());
+        if (a == b) {
+          Norder = wn;
+          direct = true;
+        }
+      }
+    }
+    PlanOp op;
+    op.kind = OP_APPLY;
+    std::memset(&op.ap, 0, sizeof(op.ap));
+    std::memset(op.ap.b_extra, -1, sizeof(op.ap.b_extra));
+    op.ap.a_bits = int(big.labels.size());
+    std::vector<std::pair<int, int>> kp;  // (pos in big, label or -1)
+    for (int l : K) kp.push_back({pos_of(big.labels, l), l});
+    for (int l : dbig) kp.push_back({pos_of(big.labels, l), -1});
+    std::sort(kp.begin(), kp.end());
+    op.ap.nk = int(kp.size());
+    for (int i = 0; i < op.ap.nk; ++i) {
+      op.ap.kpos[i] = int8_t(kp[i].first);
+      op.ap.bk[i] = kp[i].second < 0 ? int8_t(-1) : int8_t(pos_of(small.labels, kp[i].second));
+    }
+    op.ap.nn = int(Norder.size());
+    for (int i = 0; i < op.ap.nn; ++i) op.ap.bn[i] = int8_t(pos_of(small.labels, Norder[op.ap.nn - 1 - i]));
+    op.ap.n_b_extra = int(dsmall.size());
+    for (size_t i = 0; i < dsmall.size(); ++i) op.ap.b_extra[i] = int8_t(pos_of(small.labels, dsmall[i]));
+    op.ap.nb_b = int(small.labels.size());
+    TRef out;
+    out.labels = cat({Mbig, Norder});
+    if (want && direct) {
+      out.buf = want_buf;
+      out.off = want_off;
+    } else {
+      out.buf = BUF_WORK;
+      out.off = arena.alloc(int64_t(1) << out.labels.size());
+      if (want) scratch->push_back(out.off);
+    }
+    op.a_buf = big.buf;
+    op.a_off = big.off;
+    op.b_buf = small.buf;
+    op.b_off = small.off;
+    op.c_buf = out.buf;
+    op.c_off = out.off;
+    const double rows = p2(big.labels.size() - kp.size());
+    op.flops = 8.0 * rows * p2(kp.size()) * p2(Norder.size());
+    op.bytes = 8.0 * (p2(big.labels.size()) + rows * p2(Norder.size()) + p2(small.labels.size()));
+    ops.push_back(op);
+    if (want && !direct) return emit_permute(out, *want, arena, ops, scratch, want_buf, want_off);
+    return out;
+  }
+
+  // ------------------------------------------------------------ gemm path
+  if (!dx.empty()) X = emit_sum_out(X, dx, arena, ops, scratch);
+  if (!dy.empty()) Y = emit_sum_out(Y, dy, arena, ops, scratch);
+  const std::set<int> sx(X.labels.begin(), X.labels.end()), sy(Y.labels.begin(), Y.labels.end());
+  std::set<int> bset, kset;
+  for (int l : X.labels)
+    if (sy.count(l)) (keep.count(l) ? bset : kset).insert(l);
+  std::set<int> mx, ny;
+  for (int l : X.labels)
+    if (!sy.count(l)) mx.insert(l);
+  for (int l : Y.labels)
+    if (!sx.count(l)) ny.insert(l);
+
+  // roles: A carries M, B carries N.  Try to match a requested layout.
+  bool a_is_x = mx.size() >= ny.size();
+  std::vector<int> b_o, m_o, n_o;
+  bool direct = false;
+  auto try_role = [&](bool ax) {
+    const std::set<int>& ms = ax ? mx : ny;
+    const std::set<int>& ns = ax ? ny : mx;
+    const size_t nb = bset.size(), nm = ms.size(), nn = ns.size();
+    if (want->size() != nb + nm + nn) return false;
+    for (size_t i = 0; i < nb; ++i)
+      if (!bset.count((*want)[i])) return false;
+    for (size_t i = nb; i < nb + nm; ++i)
+      if (!ms.count((*want)[i])) return false;
+    for (size_t i = nb + nm; i < want->size(); ++i)
+      if (!ns.count((*want)[i])) return false;
+    a_is_x = ax;
+    b_o.assign(want->begin(), want->begin() + nb);
+    m_o.assign(want->begin() + nb, want->begin() + nb + nm);
+    n_o.assign(want->begin() + nb + nm, want->end());
+    return true;
+  };
+  if (want) direct = try_role(a_is_x) || try_role(!a_is_x);
+  TRef& A = a_is_x ? X : Y;
+  TRef& B = a_is_x ? Y : X;
+  const bool a_larger = A.labels.size() >= B.labels.size();
+  if (!direct) {
+    b_o = order_in(a_larger ? A.labels : B.labels, bset);
+    m_o = order_in(A.labels, a_is_x ? mx : ny);
+    n_o = order_in(B.labels, a_is_x ? ny : mx);
+  }
+  const std::vector<int> k_o = order_in(a_larger ? A.labels : B.labels, kset);
+  const int64_t Mn = int64_t(1) << m_o.size(), Nn = int64_t(1) << n_o.size(),
+                Kn = int64_t(1) << k_o.size(), Bn = int64_t(1) << b_o.size();
+
+  auto lowest = [](const TRef& T) { return T.labels.empty() ? -1 : T.labels.back(); };
+  int transA = 0, transB = 0;
+  TRef Ap = A, Bp = B;
+  if (Mn == 1 && Nn == 1) {
+    const auto fa = cat({b_o, k_o});
+    if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
+    if (B.labels != fa) Bp = emit_permute(B, fa, arena, ops, scratch);
+  } else {
+    const auto fa0 = cat({b_o, m_o, k_o}), fa1 = cat({b_o, k_o, m_o});
+    if (A.labels == fa0) transA = 0;
+    else if (A.labels == fa1) transA = 1;
+    else {
+      transA = kset.count(lowest(A)) ? 0 : 1;
+      Ap = emit_permute(A, transA ? fa1 : fa0, arena, ops, scratch);
+    }
+    const auto fb0 = cat({b_o, k_o, n_o}), fb1 = cat({b_o, n_o, k_o});
+    if (B.labels == fb0) transB = 0;
+    else if (B.labels == fb1) transB = 1;
+    else {
+      transB = kset.count(lowest(B)) ? 1 : 0;
+      Bp = emit_permute(B, transB ? fb1 : fb0, arena, ops, scratch);
+    }
+  }
+  TRef out;
+  out.labels = cat({b_o, m_o, n_o});
+  if (want && direct) {
+    out.buf = want_buf;
+    out.off = want_off;
+  } else {
+    out.buf = BUF_WORK;
+    out.off = arena.alloc(Bn * Mn * Nn);
+    if (want) scratch->push_back(out.off);
+  }
+  PlanOp op;
+  op.a_buf = Ap.buf;
+  op.a_off = Ap.off;
+  op.b_buf = Bp.buf;
+  op.b_off = Bp.off;
+  op.c_buf = out.buf;
+  op.c_off = out.off;
+  if (Mn == 1 && Nn == 1) {
+    op.kind = OP_DOT;
+    op.dot_k = Kn;
+    op.dot_batch = Bn;
+    op.work_off = arena.alloc(int64_t((dot_workspace_bytes(Kn, Bn) + 7) / 8));
+    scratch->push_back(op.work_off);
+  } else {
+    op.kind = OP_GEMM;
+    op.gm.M = Mn;
+    op.gm.N = Nn;
+    op.gm.K = Kn;
+    op.gm.batch = Bn;
+    op.gm.transA = transA;
+    op.gm.transB = transB;
+    op.gm.precision = resolve_precision(precision, Mn, Nn, Kn);
+    const size_t wb = gemm_workspace_bytes(op.gm);
+    if (wb > 0) {
+      op.work_off = arena.alloc(int64_t((wb + 7) / 8));
+      scratch->push_back(op.work_off);
+    }
+  }
+  op.flops = 8.0 * double(Bn) * double(Mn) * double(Nn) * double(Kn);
+  op.bytes = 8.0 * double(Bn) * (double(Mn) * Kn + double(Kn) * Nn + double(Mn) * Nn);
+  ops.push_back(op);
+  if (want && !direct) return emit_permute(out, *want, arena, ops, scratch, want_buf, want_off);
+  return out;
+}
+
+void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s) {
+  for (const PlanOp& op : ops) {
+    const float2* a = bufs[op.a_buf] + op.a_off;
+    const float2* b = bufs[op.b_buf] + op.b_off;
+    float2* c = bufs[op.c_buf] + op.c_off;
+    void* w = op.work_off >= 0 ? static_cast<void*>(bufs[BUF_WORK] + op.work_off) : nullptr;
+    switch (op.kind) {
+      case OP_APPLY: launch_apply_small(a, b, c, op.ap, s); break;
+      case OP_PERMUTE: launch_permute(a, c, op.pm, s); break;
+      case OP_GEMM: launch_gemm(a, b, c, op.gm, w, s); break;
+      case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, w, s); break;
+    }
+  }
+}
+
+// ------------------------------------------------------ amplitude planning
+
+AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, int>>& path,
+                           const std::vector<int>& sliced, const std::vector<char>& open_q,
+                           int precision) {
+  AmpPlan P;
+  P.n_qubits = net.n_qubits;
+  P.precision = precision;
+  P.sliced = sliced;
+  const int n_sl = int(sliced.size());
+  TN_REQUIRE(n_sl <= 62, TN_ERR_UNSUPPORTED, "too many sliced labels");
+  P.n_slices = std::ldexp(1.0, n_sl);
+  // fixed labels: projected outputs and sliced labels
+  std::vector<int> fixed_kind(net.n_labels, -1), fixed_which(net.n_labels, 0);
+  std::vector<char> open_label(net.n_labels, 0);
+  for (int q = 0; q < net.n_qubits; ++q) {
+    const int l = net.out_label[q];
+    if (open_q[q]) {
+      open_label[l] = 1;
+      P.open_qubits.push_back(q);
+    } else {
+      fixed_kind[l] = 0;
+      fixed_which[l] = q;
+    }
+  }
+  for (int s = 0; s < n_sl; ++s) {
+    TN_REQUIRE(!open_label[sliced[s]], TN_ERR_ARG, "an open label cannot be sliced");
+    fixed_kind[sliced[s]] = 1;
+    fixed_which[sliced[s]] = n_sl - 1 - s;
+  }
+  P.n_open = int(P.open_qubits.size());
+  TN_REQUIRE(P.n_open <= 40, TN_ERR_UNSUPPORTED, "more than 40 open qubits");
+
+  const int nt = int(net.tensors.size());
+  std::vector<TRef> refs(nt);
+  int64_t src_off = 0;
+  for (int i = 0; i < nt; ++i) {
+    const auto& L = net.tensors[i].labels;
+    const int r = int(L.size());
+    LeafDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.src_off = src_off;
+    src_off += int64_t(1) << r;
+    std::vector<int> red;
+    for (int l : L)
+      if (fixed_kind[l] < 0) red.push_back(l);
+    d.out_bits = int(red.size());
+    TN_REQUIRE(r <= 8, TN_ERR_UNSUPPORTED, "leaf rank > 8");
+    for (int j = 0; j < d.out_bits; ++j) {
+      const int lab = red[d.out_bits - 1 - j];
+      d.in_pos[j] = int8_t(r - 1 - int(std::find(L.begin(), L.end(), lab) - L.begin()));
+    }
+    for (int a = 0; a < r; ++a) {
+      const int l = L[a];
+      if (fixed_kind[l] < 0) continue;
+      LeafFixed& f = d.fixed[d.n_fixed++];
+      f.pos = int8_t(r - 1 - a);
+      f.kind = int8_t(fixed_kind[l]);
+      f.which = int16_t(fixed_which[l]);
+    }
+    d.dst_off = P.leaf_elems;
+    P.leaf_elems += ((int64_t(1) << d.out_bits) + 7) / 8 * 8;
+    P.max_leaf_bits = std::max(P.max_leaf_bits, d.out_bits);
+    P.leaves.push_back(d);
+    refs[i].buf = BUF_LEAF;
+    refs[i].off = d.dst_off;
+    refs[i].labels = red;
+  }
+
+  // per-step result label sets from the cost model (same reading as the path)
+  PathProblem pr;
+  pr.ext.assign(net.n_labels, 2.0);
+  pr.open.assign(net.n_labels, 0);
+  for (int l = 0; l < net.n_labels; ++l) pr.open[l] = open_label[l];
+  for (int i = 0; i < nt; ++i) {
+    std::vector<int> s;
+    for (int l : net.tensors[i].labels)
+      if (fixed_kind[l] != 0) s.push_back(l);
+    std::sort(s.begin(), s.end());
+    pr.leaves.push_back(s);
+  }
+  const PathStats ps = path_stats(pr, path, sliced);
+
+  Arena arena;
+  double err2 = 0;
+  for (size_t t = 0; t < path.size(); ++t) {
+    const auto [i, j] = path[t];
+    std::vector<int64_t> scratch;
+    const size_t first = P.ops.size();
+    TRef r = compile_pair(refs[i], refs[j], ps.steps[t].c, nullptr, 0, 0, arena, precision, P.ops,
+                          &scratch);
+    for (size_t k = first; k < P.ops.size(); ++k) {
+      const PlanOp& op = P.ops[k];
+      P.flops_per_job += op.flops;
+      P.bytes_per_job += op.bytes;
+      if (op.kind == OP_GEMM) {
+        P.gemm_ops++;
+        const double u = op.gm.precision == TN_PREC_BF16X3 ? std::ldexp(1.0, -17) : std::ldexp(1.0, -24);
+        err2 += u * u * (1.0 + std::log2(double(op.gm.K)));
+      } else if (op.kind != OP_PERMUTE) {
+        err2 += std::ldexp(1.0, -48);
+      }
+    }
+    for (int64_t off : scratch) arena.release(off);
+    if (refs[i].buf == BUF_WORK) arena.release(refs[i].off);
+    if (refs[j].buf == BUF_WORK) arena.release(refs[j].off);
+    refs.push_back(r);
+  }
+  P.err_bound = std::sqrt(err2);
+  const TRef& fin = refs.back();
+  P.final_buf = fin.buf;
+  P.final_off = fin.off;
+  P.final_bits = P.n_open;
+  TN_REQUIRE(int(fin.labels.size()) == P.n_open, TN_ERR_ARG,
+             "internal: final tensor does not carry exactly the open legs");
+  std::memset(P.final_pos, 0, sizeof(P.final_pos));
+  for (int j = 0; j < P.n_open; ++j) {
+    const int q = P.open_qubits[P.n_open - 1 - j];
+    const int p = pos_of(fin.labels, net.out_label[q]);
+    TN_REQUIRE(p >= 0, TN_ERR_ARG, "internal: open leg missing from the result");
+    P.final_pos[j] = int8_t(p);
+  }
+  P.work_elems = arena.high_water();
+  return P;
+}
+
+}  // namespace tn

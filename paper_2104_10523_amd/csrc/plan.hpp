@@ -1,0 +1,86 @@
+// Plan compiler and executor: SSA path -> kernel sequence for one job
+// (one bit-string x one slice), replayed over all jobs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <vector>
+
+#include "kernels.hpp"
+#include "network.hpp"
+
+namespace tn {
+
+enum Buf : int { BUF_LEAF = 0, BUF_WORK = 1, BUF_EXT_A = 2, BUF_EXT_B = 3, BUF_EXT_C = 4, BUF_ONE = 5 };
+
+struct TRef {
+  int buf = BUF_WORK;
+  int64_t off = 0;            // element offset in the buffer
+  std::vector<int> labels;    // layout, outermost first; every label is one bit
+};
+
+enum OpKind : int { OP_APPLY = 0, OP_PERMUTE = 1, OP_GEMM = 2, OP_DOT = 3 };
+
+struct PlanOp {
+  OpKind kind;
+  int a_buf = 0, b_buf = 0, c_buf = 0;
+  int64_t a_off = 0, b_off = 0, c_off = 0;
+  int64_t work_off = -1;      // split-K / dot scratch (elements of float2)
+  ApplySmallDesc ap;
+  PermuteDesc pm;
+  GemmDesc gm;
+  int64_t dot_k = 0, dot_batch = 0;
+  double flops = 0, bytes = 0;
+};
+
+// Arena allocator over element offsets (first fit, 256-byte aligned).
+class Arena {
+ public:
+  int64_t alloc(int64_t elems);
+  void release(int64_t off);
+  int64_t high_water() const { return high_; }
+
+ private:
+  std::vector<std::pair<int64_t, int64_t>> used_;  // (off, len), sorted
+  int64_t high_ = 0;
+};
+
+// Emits the ops of one pairwise contraction.  X and Y are the operands,
+// `keep` the labels of the result (any order); if `want` is non-empty the
+// result must land in that layout at (want_buf, want_off).  Returns the
+// result reference.  Scratch and the result come from `arena` (unless
+// `want` is given); precision applies to MFMA GEMMs.
+TRef compile_pair(const TRef& X, const TRef& Y, const std::vector<int>& keep,
+                  const std::vector<int>* want, int want_buf, int64_t want_off, Arena& arena,
+                  int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch);
+
+void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s);
+
+struct AmpPlan {
+  int n_qubits = 0;
+  int n_open = 0;
+  std::vector<int> open_qubits;
+  std::vector<int> sliced;        // labels, slot 0 = most significant slice bit
+  double n_slices = 1;
+  std::vector<LeafDesc> leaves;
+  int max_leaf_bits = 0;
+  int64_t leaf_elems = 0;
+  int64_t work_elems = 0;
+  std::vector<PlanOp> ops;
+  int final_buf = BUF_LEAF;
+  int64_t final_off = 0;
+  int final_bits = 0;
+  int8_t final_pos[kMaxBits];
+  double flops_per_job = 0, bytes_per_job = 0;
+  int precision = 0;
+  double err_bound = 0;
+  int gemm_ops = 0;
+};
+
+struct PathData;  // defined in api
+AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, int>>& path,
+                           const std::vector<int>& sliced, const std::vector<char>& open_q,
+                           int precision);
+
+}  // namespace tn

@@ -1,0 +1,135 @@
+"""tn_amplitudes on the GPU against the state-vector oracle (O1) and the
+closed forms it is pinned to.
+
+Tolerance (complex64 contraction, FP64 accumulation): with r the oracle
+amplitude and n the qubit count, max |a - r| / max(|r|, 2^(-n/2)) <= 1e-5 and
+||a - r|| / ||r|| <= 1e-5.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import statevector as sv
+from workloads import (grid_random_circuit, cat_circuit, ghz_circuit, qft_circuit,
+                       random_bitstrings)
+from tests.helpers import floored_rel, l2_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def check_amps(got, ref, n, tol=1e-5):
+    fl = 2.0 ** (-n / 2)
+    e1 = floored_rel(got, ref, fl)
+    e2 = l2_rel(got, ref)
+    assert e1 <= tol and e2 <= tol, (e1, e2)
+    return e1, e2
+
+
+def amps(n, ops, bits, precision="fp32", budget=0.0, use_graph=False, algo="greedy", **kw):
+    import paper_2104_10523_amd as tn
+    net = tn.tn_build_network(n, ops)
+    bits = np.asarray(bits, dtype=np.int8)
+    if bits.ndim == 1:
+        bits = bits[None]
+    open_mask = (bits[0] < 0).astype(np.int8)
+    path = tn.tn_find_path(net, algo, mem_budget_bytes=budget, open_mask=open_mask, **kw)
+    out, rep = tn.tn_amplitudes(net, path, bits, precision=precision, use_graph=use_graph)
+    return out.cpu().numpy(), rep, path
+
+
+def test_c1_all_open(gpu, workspace):
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    got, rep, _ = amps(n, ops, [-1] * n)
+    ref = sv.simulate(n, ops).reshape(-1)
+    check_amps(got[0], ref, n)
+    assert rep.nonfinite == 0
+    assert abs(np.sum(np.abs(got[0]) ** 2) - 1) < 1e-6
+
+
+def test_c1_all_zeros_and_random_bitstrings(gpu, workspace):
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    psi = sv.simulate(n, ops).reshape(-1)
+    bits = np.vstack([np.zeros((1, n), np.int8), random_bitstrings(63, n, 99)])
+    got, rep, _ = amps(n, ops, bits)
+    idx = [int("".join(map(str, b)), 2) for b in bits]
+    check_amps(got[:, 0], psi[idx], n)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_slicing_invariance(gpu, workspace, use_graph):
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    bits = random_bitstrings(4, n, 5)
+    full, _, p0 = amps(n, ops, bits)
+    assert p0.cost.n_sliced == 0
+    budget = 8 * p0.cost.peak_elems / 16
+    sl, rep, p1 = amps(n, ops, bits, budget=budget, use_graph=use_graph)
+    assert p1.cost.n_sliced >= 3
+    assert 8 * p1.cost.peak_elems <= budget
+    psi = sv.simulate(n, ops).reshape(-1)
+    idx = [int("".join(map(str, b)), 2) for b in bits]
+    check_amps(full[:, 0], psi[idx], n)
+    check_amps(sl[:, 0], psi[idx], n)
+
+
+def test_marginal_slice_open_subset(gpu, workspace):
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    psi = sv.simulate(n, ops)
+    rng = np.random.default_rng(3)
+    bits = rng.integers(0, 2, size=n).astype(np.int8)
+    bits[[1, 5, 6]] = -1
+    got, _, _ = amps(n, ops, bits)
+    ref = sv.slice_of(psi, bits)
+    check_amps(got[0], ref, n)
+
+
+def test_cat_60_qubit_marginal_slice(gpu, workspace):
+    """Sec. 4.4: 60-qubit cat state, qubits 2 and 47 open."""
+    n, ops = cat_circuit(60)
+    r = 1 / math.sqrt(2)
+    for fill, expect in ((0, [r, 0, 0, 0]), (1, [0, 0, 0, r])):
+        bits = np.full(n, fill, np.int8)
+        bits[2] = bits[47] = -1
+        got, _, _ = amps(n, ops, bits)
+        assert np.allclose(got[0], expect, atol=1e-6)
+    bits = np.zeros(n, np.int8)
+    bits[10] = 1
+    bits[2] = bits[47] = -1
+    got, _, _ = amps(n, ops, bits)
+    assert np.allclose(got[0], 0, atol=1e-7)
+
+
+def test_ghz_and_qft(gpu, workspace):
+    n, ops = ghz_circuit(14)
+    got, _, _ = amps(n, ops, [-1] * n)
+    ref = np.zeros(1 << n, complex)
+    ref[0] = ref[-1] = 1 / math.sqrt(2)
+    check_amps(got[0], ref, n)
+    n, x = 8, 77
+    n, ops = qft_circuit(n, x)
+    got, _, _ = amps(n, ops, [-1] * n)
+    y = np.arange(1 << n)
+    ref = np.exp(2j * np.pi * x * y / (1 << n)) / math.sqrt(1 << n)
+    check_amps(got[0], ref, n)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6", "auto"])
+def test_precisions_c1(gpu, workspace, precision):
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    got, rep, _ = amps(n, ops, [-1] * n, precision=precision)
+    ref = sv.simulate(n, ops).reshape(-1)
+    check_amps(got[0], ref, n, tol=1e-5 if precision != "bf16x3" else 1e-4)
+
+
+def test_bits_errors(gpu, workspace):
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    net = tn.tn_build_network(n, ops)
+    path = tn.tn_find_path(net, "greedy")
+    with pytest.raises(tn.TnError, match="BITS"):
+        tn.tn_amplitudes(net, path, np.full((1, n), 2, np.int8))
+    with pytest.raises(tn.TnError, match="BITS"):
+        b = np.zeros((1, n), np.int8)
+        b[0, 3] = -1
+        tn.tn_amplitudes(net, path, b)

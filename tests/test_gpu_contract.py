@@ -1,0 +1,128 @@
+"""tn_contract_pair on the GPU against the complex128 einsum oracle (O2).
+
+Label sets are drawn at random: batch, contracted (K), free (M, N) and
+summed-out labels in shuffled orders, so every kernel path is exercised:
+bit-addressed small-operand apply, permute + MFMA GEMM (FP32, BF16x3,
+BF16x6), split-K, dot, outer product, scalar output, pure permutation and
+ragged tiles.
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+from oracle.contract import contract_pair as oracle_pair
+from workloads import random_complex
+from tests.helpers import l2_rel, floored_rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 2e-6, "bf16x6": 2e-6, "bf16x3": 2e-5}
+
+
+def make_case(seed, nb=0, nm=0, nk=0, nn=0, da=0, db=0, wide=None, shuffle=True):
+    rng = np.random.default_rng(seed)
+    labels = list(range(100, 100 + nb + nm + nk + nn + da + db))
+    rng.shuffle(labels)
+    it = iter(labels)
+    L = {k: [next(it) for _ in range(c)] for k, c in
+         (("b", nb), ("m", nm), ("k", nk), ("n", nn), ("da", da), ("db", db))}
+    ext = {l: 2 for l in labels}
+    if wide:
+        for l in L["k"][:1] + L["m"][:1]:
+            ext[l] = wide
+    la = L["b"] + L["m"] + L["k"] + L["da"]
+    lb = L["b"] + L["k"] + L["n"] + L["db"]
+    lc = L["b"] + L["m"] + L["n"]
+    if shuffle:
+        la = list(rng.permutation(la)) if la else la
+        lb = list(rng.permutation(lb)) if lb else lb
+        lc = list(rng.permutation(lc)) if lc else lc
+    la, lb, lc = [int(x) for x in la], [int(x) for x in lb], [int(x) for x in lc]
+    A = random_complex([ext[l] for l in la], seed + 1, dtype=np.complex64)
+    B = random_complex([ext[l] for l in lb], seed + 2, dtype=np.complex64)
+    return A, la, B, lb, lc, [ext[l] for l in lc]
+
+
+def run(A, la, B, lb, lc, shape_c, precision):
+    import torch
+    import paper_2104_10523_amd as tn
+    dA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    dC = torch.full(shape_c, complex(float("nan"), 0), dtype=torch.complex64, device="cuda")
+    tn.tn_contract_pair(dA, la, dB, lb, dC, lc, precision)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+CASES = [
+    # (name, kwargs)
+    ("apply_k1", dict(nm=14, nk=1, nn=2)),
+    ("apply_k2_n2", dict(nm=16, nk=2, nn=2)),
+    ("apply_k4_n4", dict(nm=12, nk=4, nn=4)),
+    ("apply_k6_n0", dict(nm=10, nk=6, nn=0)),
+    ("gemm_square", dict(nm=9, nk=7, nn=8)),
+    ("gemm_ragged_small_mn", dict(nm=5, nk=6, nn=5)),
+    ("gemm_n16", dict(nm=11, nk=7, nn=4 + 1)),
+    ("gemm_n32", dict(nm=10, nk=8, nn=5)),
+    ("gemm_splitk", dict(nm=6, nk=14, nn=6)),
+    ("gemm_batch", dict(nb=3, nm=7, nk=6, nn=6)),
+    ("gemm_wide_extents", dict(nm=5, nk=3, nn=6, wide=8)),
+    ("outer_product", dict(nm=8, nk=0, nn=6)),
+    ("dot", dict(nk=16)),
+    ("dot_batch", dict(nb=2, nk=12)),
+    ("scalar_times_tensor", dict(nm=10)),
+    ("sum_out_a", dict(nm=8, nk=3, nn=6, da=2)),
+    ("sum_out_b_apply", dict(nm=12, nk=2, nn=2, db=1)),
+    ("rank0_all", dict()),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_contract_pair(gpu, workspace, name, kw, precision):
+    seed = zlib.crc32(f"{name}/{precision}".encode()) % 10000
+    A, la, B, lb, lc, shape_c = make_case(seed, **kw)
+    print(f"case {name} prec {precision} A{A.shape} B{B.shape} la={la} lb={lb} lc={lc}", flush=True)
+    got = run(A, la, B, lb, lc, shape_c, precision)
+    ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+    assert np.all(np.isfinite(got))
+    err = l2_rel(got, ref)
+    assert err <= TOL[precision], (name, precision, err)
+
+
+def test_contract_pair_unshuffled_orders(gpu, workspace):
+    """Operands already in GEMM order (no permutation kernels)."""
+    A, la, B, lb, lc, shape_c = make_case(7, nm=8, nk=6, nn=7, shuffle=False)
+    got = run(A, la, B, lb, lc, shape_c, "fp32")
+    ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+    assert l2_rel(got, ref) <= 2e-6
+
+
+def test_contract_pair_large_mfma(gpu, workspace):
+    """A contraction large enough to span many MFMA tiles, all precisions;
+    checked on 4096 sampled output entries computed one by one."""
+    A, la, B, lb, lc, shape_c = make_case(11, nm=12, nk=9, nn=11)
+    ref_full = None
+    for prec in ("fp32", "bf16x3", "bf16x6"):
+        got = run(A, la, B, lb, lc, shape_c, prec)
+        if ref_full is None:
+            ref_full = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+        assert l2_rel(got, ref_full) <= TOL[prec], prec
+        assert floored_rel(got, ref_full, 1e-3 * np.abs(ref_full).max()) <= 100 * TOL[prec]
+
+
+def test_contract_pair_errors(gpu, workspace):
+    import torch
+    import paper_2104_10523_amd as tn
+    a = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
+    b = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
+    c = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
+    with pytest.raises(tn.TnError, match="MODES"):
+        tn.tn_contract_pair(a, [1, 1], b, [1, 2], c, [1, 2])
+    with pytest.raises(tn.TnError, match="MODES"):
+        tn.tn_contract_pair(a, [1, 2], b, [2, 3], c, [1, 9])
+    c3 = torch.zeros((3, 2), dtype=torch.complex64, device="cuda")
+    with pytest.raises(tn.TnError, match="EXTENT"):
+        tn.tn_contract_pair(a, [1, 2], b, [2, 3], c3, [1, 3])

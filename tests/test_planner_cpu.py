@@ -1,0 +1,179 @@
+"""Host-side checks of the native library (no GPU needed): the C ABI loads
+and exports every declared entry point; the library's circuit-to-network
+mapping, greedy and randomised-greedy paths, cost model and slicer agree
+exactly with the oracle's independent implementation; host-side errors map
+to the documented status codes."""
+
+import ctypes
+import math
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_2104_10523_amd as tn
+from oracle.network import build_network
+from oracle.paths import greedy_path, path_stats, random_greedy_path, slice_path
+from workloads import Op, grid_random_circuit, chain_random_circuit, cat_circuit, qft_circuit
+
+HEADER = Path(__file__).resolve().parent.parent / "include" / "tn.h"
+
+
+def declared_functions():
+    txt = HEADER.read_text()
+    return sorted(set(re.findall(r"^\s*(?:tn_status|const char\*)\s+(tn_\w+)\s*\(", txt, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(str(tn._native.LIB_PATH))
+    names = declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(tn._native.SIGNATURES)
+
+
+def test_version_and_last_error():
+    assert b"gfx950" in tn.lib().tn_version()
+
+
+def _oracle_leaves(onet, open_q=()):
+    outs = {onet.out_label[q] for q in range(onet.n_qubits) if q not in open_q}
+    opened = {onet.out_label[q] for q in open_q}
+    leaves = [[l for l in ls if l not in outs] for ls in onet.labels]
+    return leaves, onet.extents(), opened
+
+
+CIRCUITS = [
+    ("c1_3x4x8", lambda: grid_random_circuit(3, 4, 8, 1)),
+    ("grid_4x5x10", lambda: grid_random_circuit(4, 5, 10, 3)),
+    ("chain_10x6", lambda: chain_random_circuit(10, 6, 5)),
+    ("cat_16", lambda: cat_circuit(16)),
+    ("qft_6", lambda: qft_circuit(6, 13)),
+    ("lone_wires", lambda: (4, [Op("h", (0,)), Op("sqrt_x", (3,)), Op("cz", (0, 1))])),
+]
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS, ids=[c[0] for c in CIRCUITS])
+def test_network_matches_oracle(name, make):
+    n, ops = make()
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    info = lnet.info()
+    assert (info.n_qubits, info.n_tensors, info.n_labels) == (n, len(onet.tensors), onet.n_labels)
+    assert lnet.output_labels() == onet.out_label
+    for i in range(info.n_tensors):
+        T, labels = lnet.tensor(i)
+        assert labels == onet.labels[i]
+        assert np.abs(T - onet.tensors[i]).max() <= 1e-15
+
+
+@pytest.mark.parametrize("name,make", CIRCUITS, ids=[c[0] for c in CIRCUITS])
+def test_greedy_path_and_cost_match_oracle(name, make):
+    n, ops = make()
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    for open_q in ((), (0, n - 1)):
+        mask = [1 if q in open_q else 0 for q in range(n)]
+        leaves, ext, opened = _oracle_leaves(onet, open_q)
+        p = tn.tn_find_path(lnet, "greedy", open_mask=mask)
+        po = greedy_path(leaves, ext, opened)
+        st = path_stats(leaves, ext, po, opened)
+        assert p.pairs == po
+        assert p.cost.flops_per_slice == st["flops"]
+        assert p.cost.peak_elems == st["peak"]
+
+
+def test_random_greedy_matches_oracle():
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    for seed, T in ((1, 1.0), (77, 0.5)):
+        p = tn.tn_find_path(lnet, "random_greedy", trials=6, seed=seed, temperature=T)
+        po = random_greedy_path(leaves, ext, opened, seed=seed, trials=6, temperature=T)
+        assert p.pairs == po
+
+
+def test_slicing_matches_oracle_and_meets_budget():
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    po = greedy_path(leaves, ext, opened)
+    peak = path_stats(leaves, ext, po, opened)["peak"]
+    for div in (4, 64):
+        budget = 8 * peak / div
+        p = tn.tn_find_path(lnet, "greedy", mem_budget_bytes=budget)
+        so = slice_path(leaves, ext, po, opened, budget)
+        assert p.sliced == so
+        assert 8 * p.cost.peak_elems <= budget
+        st = path_stats(leaves, ext, po, opened, so)
+        assert p.cost.total_flops == st["total_flops"] and p.cost.n_slices == 2 ** len(so)
+
+
+def test_c2_network_path_cost():
+    """49-qubit 7x7 grid, 14 cycles of fSim: greedy path and slicing to a
+    256 GiB budget, identical on both sides."""
+    n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim")
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    assert lnet.info().n_tensors == 294
+    leaves, ext, opened = _oracle_leaves(onet)
+    p = tn.tn_find_path(lnet, "greedy", mem_budget_bytes=256 * 2 ** 30)
+    po = greedy_path(leaves, ext, opened)
+    assert p.pairs == po
+    assert 8 * p.cost.peak_elems <= 256 * 2 ** 30
+    so = slice_path(leaves, ext, po, opened, 256 * 2 ** 30)
+    assert p.sliced == so
+
+
+def test_path_from_pairs_validates():
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    lnet = tn.tn_build_network(n, ops)
+    p = tn.tn_find_path(lnet, "greedy")
+    q = tn.tn_path_from_pairs(lnet, p.pairs)
+    assert q.cost.flops_per_slice == p.cost.flops_per_slice
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_path_from_pairs(lnet, p.pairs[:-1])
+    bad = list(p.pairs)
+    bad[-1] = (0, 1)
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_path_from_pairs(lnet, bad)
+
+
+def test_host_error_codes():
+    with pytest.raises(tn.TnError, match="GATE"):
+        tn.tn_build_network(2, [Op("cz", (0, 2))])
+    with pytest.raises(tn.TnError, match="GATE"):
+        tn.tn_build_network(2, [Op("cz", (1, 1))])
+    with pytest.raises(tn.TnError, match="GATE"):
+        tn.tn_build_network(2, [Op("depol1", (0,), (0.1,))])
+    with pytest.raises(tn.TnError, match="GATE"):
+        tn.tn_build_network(1, [Op(99, (0,))])
+    with pytest.raises(tn.TnError, match="GATE"):
+        tn.tn_build_network(2, [Op("custom2", (0, 1), (np.ones((4, 4)),))])
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_build_network(0, [])
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    lnet = tn.tn_build_network(n, ops)
+    with pytest.raises(tn.TnError, match="BUDGET"):
+        tn.tn_find_path(lnet, "greedy", mem_budget_bytes=8.0)
+    with pytest.raises(tn.TnError, match="STATE"):
+        tn.tn_find_path(lnet, "learned")
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_find_path(lnet, "random_greedy", temperature=0.0)
+
+
+def test_custom_gates_match_named():
+    from oracle.gates import gate_matrix
+    n = 3
+    ops_named = [Op("h", (0,)), Op("fsim", (0, 2), (0.4, 0.9)), Op("sqrt_w", (1,)), Op("cx", (1, 2))]
+    ops_custom = [Op("custom1", (0,), (gate_matrix("h"),)),
+                  Op("custom2", (0, 2), (gate_matrix("fsim", (0.4, 0.9)),)),
+                  Op("custom1", (1,), (gate_matrix("sqrt_w"),)), Op("cx", (1, 2))]
+    a = tn.tn_build_network(n, ops_named)
+    b = tn.tn_build_network(n, ops_custom)
+    for i in range(a.info().n_tensors):
+        assert np.abs(a.tensor(i)[0] - b.tensor(i)[0]).max() <= 1e-15
