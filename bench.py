@@ -1,0 +1,226 @@
+"""Benchmark: amplitudes of the 49-qubit 7x7 random grid circuit (14 cycles,
+fSim(pi/2, pi/6)) on one MI355X.
+
+Workload: 64 seeded uniform bit-strings; the contraction path is the best of
+greedy and 32 randomised-greedy trials; indices are sliced so that the live
+set of one slice fits the memory budget.  One *step* is one job of the hot
+path: one bit-string x one slice, from the leaf gather through every
+pairwise contraction to the FP64 accumulation of the amplitude.  The whole
+job (64 bit-strings x 2^k slices) cannot run in minutes, so `value` is the
+whole-job amplitude rate extrapolated from the timed steps (every slice has
+the same shapes): amplitudes/s = 1 / (2^k x seconds per step).
+
+The dominant kernel is the complex MFMA GEMM; its roofline entry is
+computed from HIP events around every op of the timed steps.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+PEAKS = {"bf16x3": 2.5e15, "bf16x6": 2.5e15, "fp32": 157.3e12}
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp32", "auto"])
+    ap.add_argument("--compare-fp32", type=int, default=1, help="also time FP32 steps")
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rows", type=int, default=7)
+    ap.add_argument("--cols", type=int, default=7)
+    ap.add_argument("--cycles", type=int, default=14)
+    return ap.parse_args()
+
+
+def make_workload(a):
+    import paper_2104_10523_amd as tn
+    from workloads import grid_random_circuit, random_bitstrings
+    n, ops = grid_random_circuit(a.rows, a.cols, a.cycles, 2, two_qubit="fsim")
+    bits = random_bitstrings(64, n, 12345)
+    net = tn.tn_build_network(n, ops)
+    t0 = time.time()
+    path = tn.tn_find_path(net, "random_greedy", trials=32, seed=1, temperature=0.5,
+                           mem_budget_bytes=a.budget_gib * 2 ** 30)
+    t_path = time.time() - t0
+    return n, ops, bits, net, path, t_path
+
+
+def plan_ops(net, path, precision):
+    import ctypes as C
+    import paper_2104_10523_amd as tn
+    from paper_2104_10523_amd._native import TnPlanInfo, PREC
+    info = TnPlanInfo()
+    tn._native.check(tn.lib().tn_amplitudes_plan_info(net.h, path.h, PREC[precision], C.byref(info)))
+    N = info.n_ops
+    kind = (C.c_int32 * N)()
+    fl = (C.c_double * N)()
+    by = (C.c_double * N)()
+    mnkb = (C.c_int64 * (4 * N))()
+    tn._native.check(tn.lib().tn_amplitudes_plan_ops(net.h, path.h, PREC[precision], kind, fl, by, mnkb))
+    return info, np.array(kind), np.array(fl), np.array(by), np.array(mnkb).reshape(N, 4)
+
+
+def time_steps(net, path, bits, precision, jobs, stream):
+    """Run each (bit-string, slice) job once with per-op events; returns the
+    wall time of every job (device events) and the per-op seconds summed."""
+    import ctypes as C
+    import torch
+    import paper_2104_10523_amd as tn
+    from paper_2104_10523_amd._native import TnExecOpts, TnReport, PREC
+    info, kind, fl, by, mnkb = plan_ops(net, path, precision)
+    op_sec = np.zeros(info.n_ops)
+    per_job = []
+    out = torch.zeros((1, 1), dtype=torch.complex128, device="cuda")
+    for (b, s) in jobs:
+        buf = np.zeros(info.n_ops)
+        o = TnExecOpts(PREC[precision], 0, int(s), 1, 0, 1,
+                       buf.ctypes.data_as(C.POINTER(C.c_double)))
+        rep = TnReport()
+        bb = np.ascontiguousarray(bits[b:b + 1])
+        tn._native.check(tn.lib().tn_amplitudes(net.h, path.h, bb.ctypes.data_as(C.POINTER(C.c_int8)), 1,
+                                                C.byref(o), C.c_void_p(out.data_ptr()), C.byref(rep),
+                                                C.c_void_p(stream.cuda_stream)))
+        per_job.append(rep.seconds)
+        op_sec += buf
+        if rep.nonfinite:
+            raise RuntimeError("non-finite amplitude")
+    return np.array(per_job), op_sec, (info, kind, fl, by, mnkb)
+
+
+def cpu_baseline(path_pairs, net_py, budget_s):
+    """The oracle (numpy einsum, complex128) timed on the workload's own
+    pairwise contractions, largest first among those whose tensors fit in
+    2^25 entries, until budget_s of CPU time; returns flops/s."""
+    from oracle.contract import contract_pair
+    from oracle.paths import path_stats
+    from workloads import random_complex
+    leaves, ext, open_l, sliced = net_py
+    st = path_stats(leaves, ext, path_pairs, open_l, sliced)
+    steps = []
+    for (a, b, c) in st["steps"]:
+        if max(len(a), len(b), len(c)) <= 25:
+            steps.append((8.0 * 2 ** len(a | b), sorted(a), sorted(b), sorted(c)))
+    steps.sort(key=lambda x: -x[0])
+    done_f, done_t = 0.0, 0.0
+    for k, (f, la, lb, lc) in enumerate(steps):
+        A = random_complex([2] * len(la), k)
+        B = random_complex([2] * len(lb), k + 1)
+        t0 = time.perf_counter()
+        contract_pair(A, la, B, lb, lc)
+        done_t += time.perf_counter() - t0
+        done_f += f
+        if done_t >= budget_s:
+            break
+    return done_f / done_t, done_t, done_f
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2104_10523_amd as tn
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n, ops, bits, net, path, t_path = make_workload(a)
+    ns = path.cost.n_slices
+    need = max(tn.tn_amplitudes_workspace(net, path, 1, p) for p in ("fp32", a.precision))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    tn.tn_set_workspace(ws)
+    rng = np.random.default_rng(7)
+    total = a.warmup + a.steps
+    jobs = [(int(rng.integers(0, 64)), int(rng.integers(0, int(ns)))) for _ in range(total)]
+    print(f"# workload 7x7x14 fSim: slices 2^{path.cost.n_sliced}, per-slice flops 2^{math.log2(path.cost.flops_per_slice):.2f}, "
+          f"workspace {need / 2**30:.1f} GiB, path search {t_path:.1f}s", file=sys.stderr, flush=True)
+    # warmup
+    time_steps(net, path, bits, a.precision, jobs[:a.warmup], stream)
+    print("# warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_job, op_sec, (info, kind, fl, by, mnkb) = time_steps(net, path, bits, a.precision, jobs[a.warmup:], stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T = float(per_job.mean())
+    flops_job = float(fl.sum())
+    amps_per_s = 1.0 / (ns * T)
+    # dominant kernel: the large complex GEMMs (one MFMA launch each)
+    big = (kind == 2) & (fl >= 1e12)
+    g_flops = float(fl[big].sum()) * a.steps
+    g_time = float(op_sec[big].sum())
+    g_bytes = float(by[big].sum()) * a.steps
+    peak = PEAKS[a.precision] if a.precision in PEAKS else PEAKS["bf16x3"]
+    achieved = g_flops / g_time if g_time > 0 else 0.0
+    t_by_kind = {k: float(op_sec[kind == i].sum()) / a.steps
+                 for i, k in enumerate(("apply", "permute", "gemm", "dot"))}
+    print(f"# per step {T:.3f}s (wall {wall / a.steps:.3f}s); time by kind {t_by_kind}", file=sys.stderr, flush=True)
+    fp32 = None
+    if a.compare_fp32 and a.precision != "fp32":
+        pj, os32, (_, k32, f32, _, _) = time_steps(net, path, bits, "fp32", jobs[a.warmup:a.warmup + 1], stream)
+        b32 = (k32 == 2) & (f32 >= 1e12)
+        fp32 = {"seconds_per_step": float(pj.mean()),
+                "amplitudes_per_s": 1.0 / (ns * float(pj.mean())),
+                "gemm_tflops": float(f32[b32].sum()) / float(os32[b32].sum()) / 1e12,
+                "speedup_of_split": float(pj.mean()) / T}
+        print(f"# fp32 step {pj.mean():.3f}s", file=sys.stderr, flush=True)
+    cpu = None
+    if not a.no_cpu:
+        from oracle.network import build_network
+        onet = build_network(n, ops)
+        outs = set(onet.out_label)
+        leaves = [[l for l in ls if l not in outs] for ls in onet.labels]
+        rate, secs, f = cpu_baseline(path.pairs, (leaves, onet.extents(), set(), path.sliced), a.cpu_seconds)
+        cpu = {"value": 1.0 / (ns * flops_job / rate), "unit": "amplitudes/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle complex128 einsum on this workload's largest pairwise contractions with "
+                         f"<= 2^25-entry tensors ({f:.3g} flops in {secs:.1f}s, {rate / 1e9:.2f} GFLOP/s), "
+                         f"extrapolated to {flops_job:.3g} flops per step x 2^{path.cost.n_sliced} slices"}
+    line = {
+        "metric": "amplitudes/s + complex TFLOP/s, 49q depth-14 grid; split-BF16 vs FP32 @1e-5 err",
+        "value": amps_per_s,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": T * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16x3-split c64, fp32 accumulate", "bf16x6": "bf16x6-split c64, fp32 accumulate",
+                  "fp32": "c64 fp32", "auto": "c64 auto"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{a.rows}x{a.cols} grid random circuit, {a.cycles} cycles, fSim(pi/2,pi/6), "
+                               f"64 bit-strings, randomised-greedy path, 2^{path.cost.n_sliced} slices "
+                               f"({a.budget_gib:g} GiB budget); value extrapolated from timed slices",
+                   "qubits": n, "bitstrings": 64, "slices": ns,
+                   "flops_per_step": flops_job, "flops_per_amplitude": flops_job * ns,
+                   "complex_tflops": flops_job / T / 1e12, "precision": a.precision},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "gemm_mfma_kernel<128,64,16,2,2," + a.precision + ">",
+                     "launches": int(big.sum()) * a.steps,
+                     "algorithmic_bytes_per_launch": g_bytes / max(1, int(big.sum()) * a.steps)},
+        "fp32_comparison": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -232,12 +232,18 @@ typedef struct {
 
 typedef struct {
   int32_t precision;          /* TN_PREC_*                                  */
-  int32_t use_graph;          /* 1: capture one job as a hipGraph, replay   */
+  int32_t use_graph;          /* 1: capture one job as a hipGraph (on a     */
+                              /* library-owned stream) and replay it per    */
+                              /* job on `stream`                            */
   int64_t slice_begin;        /* first slice of the range to run            */
   int64_t slice_count;        /* number of slices; -1 = all                 */
   int32_t accumulate;         /* 1: add into `out`; 0: overwrite            */
   int32_t sync;               /* 1: wait for the stream before returning    */
                               /* (fills seconds / nonfinite)                */
+  double* op_seconds;         /* NULL, or host array of tn_plan_info.n_ops: */
+                              /* per-op device time summed over jobs (HIP   */
+                              /* events around every op; implies sync, no   */
+                              /* graph)                                     */
 } tn_exec_opts;
 
 /* Amplitudes <x|U|0..0> for n_bs bit-strings (host int8 array n_bs x
@@ -253,6 +259,25 @@ tn_status tn_amplitudes(const tn_network* n, const tn_path* p,
                         const int8_t* bits, int64_t n_bs,
                         const tn_exec_opts* opts, void* out, tn_report* rep,
                         void* stream);
+
+/* Summary of the kernel sequence of one job (one bit-string, one slice). */
+enum { TN_OP_APPLY = 0, TN_OP_PERMUTE = 1, TN_OP_GEMM = 2, TN_OP_DOT = 3 };
+typedef struct {
+  int32_t n_ops;              /* ops per job (plus gather and accumulate)   */
+  int32_t n_by_kind[4];       /* indexed by TN_OP_*                         */
+  double flops_by_kind[4];    /* algorithmic flops per job                  */
+  double bytes_by_kind[4];    /* algorithmic HBM bytes per job              */
+  double workspace_bytes;     /* tn_amplitudes_workspace for n_bs = 1       */
+  double err_bound;           /* a-priori relative error estimate           */
+} tn_plan_info;
+tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p,
+                                  int32_t precision, tn_plan_info* info);
+/* Per-op detail (arrays of n_ops, any may be NULL): kind (TN_OP_*),
+ * algorithmic flops and bytes, and GEMM shape m, n, k, batch (1 for other
+ * kinds; for APPLY: rows, 2^#N, 2^#K). */
+tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p,
+                                 int32_t precision, int32_t* kind,
+                                 double* flops, double* bytes, int64_t* mnkb);
 
 /* Workspace bytes tn_amplitudes needs for this path, n_bs bit-strings and
  * precision (job control words, bit-strings, gathered leaves, intermediates

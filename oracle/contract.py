@@ -63,6 +63,22 @@ def contract_pair(A, la, B, lb, lc) -> np.ndarray:
     return np.einsum(spec, np.asarray(A, dtype=np.complex128), np.asarray(B, dtype=np.complex128))
 
 
+def contract_entries(A, la, B, lb, lc, index_list) -> np.ndarray:
+    """Selected entries C[idx] of contract_pair(A, la, B, lb, lc), each
+    computed on its own: fix the output labels, then sum the product over
+    every remaining label (einsum of the two fixed sub-tensors)."""
+    _check(la, lb, lc)
+    out = np.empty(len(index_list), dtype=np.complex128)
+    for t, idx in enumerate(index_list):
+        env = dict(zip(lc, idx))
+        sa = tuple(env[l] if l in env else slice(None) for l in la)
+        sb = tuple(env[l] if l in env else slice(None) for l in lb)
+        ra = [l for l in la if l not in env]
+        rb = [l for l in lb if l not in env]
+        out[t] = complex(contract_pair(np.asarray(A)[sa], ra, np.asarray(B)[sb], rb, []))
+    return out
+
+
 def result_labels(la, lb, others: List[Sequence[int]], keep: Sequence[int]) -> List[int]:
     """Labels the product of A and B keeps: those still used by another live
     tensor or listed in ``keep`` (open output legs); order = A's then B's."""

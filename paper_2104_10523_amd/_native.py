@@ -63,7 +63,14 @@ class TnReport(C.Structure):
 
 class TnExecOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("use_graph", C.c_int32), ("slice_begin", C.c_int64),
-                ("slice_count", C.c_int64), ("accumulate", C.c_int32), ("sync", C.c_int32)]
+                ("slice_count", C.c_int64), ("accumulate", C.c_int32), ("sync", C.c_int32),
+                ("op_seconds", C.POINTER(C.c_double))]
+
+
+class TnPlanInfo(C.Structure):
+    _fields_ = [("n_ops", C.c_int32), ("n_by_kind", C.c_int32 * 4),
+                ("flops_by_kind", C.c_double * 4), ("bytes_by_kind", C.c_double * 4),
+                ("workspace_bytes", C.c_double), ("err_bound", C.c_double)]
 
 
 P = C.c_void_p
@@ -89,6 +96,8 @@ SIGNATURES = {
                                C.POINTER(TnTensor), PI32, I32, P]),
     "tn_amplitudes": (I32, [P, P, PI8, I64, C.POINTER(TnExecOpts), P, C.POINTER(TnReport), P]),
     "tn_amplitudes_workspace": (I32, [P, P, I64, I32, C.POINTER(C.c_size_t)]),
+    "tn_amplitudes_plan_info": (I32, [P, P, I32, C.POINTER(TnPlanInfo)]),
+    "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),

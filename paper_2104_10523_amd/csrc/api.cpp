@@ -373,7 +373,7 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
     auto* n = const_cast<tn_network*>(n_);
     auto* p = const_cast<tn_path*>(p_);
     TN_REQUIRE(n && p && bits && out && n_bs >= 1, TN_ERR_ARG, "bad argument");
-    tn_exec_opts o{TN_PREC_FP32, 0, 0, -1, 0, 0};
+    tn_exec_opts o{TN_PREC_FP32, 0, 0, -1, 0, 0, nullptr};
     if (opts) o = *opts;
     TN_REQUIRE(o.precision >= TN_PREC_FP32 && o.precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
     const int nq = n->net.n_qubits;
@@ -419,6 +419,12 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
       launch_accumulate(bufs[P.final_buf] + P.final_off, static_cast<double2*>(out), P.final_bits,
                         P.final_pos, dctl, o.accumulate, s);
     };
+    const bool profile = o.op_seconds != nullptr;
+    if (profile) {
+      o.sync = 1;
+      o.use_graph = 0;
+      for (size_t k = 0; k < P.ops.size(); ++k) o.op_seconds[k] = 0.0;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (o.sync) {
       TN_HIP(hipEventCreate(&e0));
@@ -426,25 +432,70 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
       TN_HIP(hipEventRecord(e0, s));
     }
     if (o.use_graph) {
+      // capture on a library-owned stream (the legacy default stream cannot
+      // be captured), ordered after the caller's stream by an event
+      hipStream_t cs = nullptr;
+      hipEvent_t dep = nullptr;
       hipGraph_t g = nullptr;
       hipGraphExec_t ge = nullptr;
-      TN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      TN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      auto cleanup = [&]() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (dep) (void)hipEventDestroy(dep);
+        (void)hipStreamDestroy(cs);
+      };
       try {
-        launch_advance_job(dctl, s);
-        one_job();
+        TN_HIP(hipEventCreateWithFlags(&dep, hipEventDisableTiming));
+        TN_HIP(hipEventRecord(dep, s));
+        TN_HIP(hipStreamWaitEvent(cs, dep, 0));
+        TN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        hipStream_t keep = s;
+        s = cs;
+        try {
+          launch_advance_job(dctl, s);
+          one_job();
+        } catch (...) {
+          s = keep;
+          hipGraph_t dummy = nullptr;
+          (void)hipStreamEndCapture(cs, &dummy);
+          if (dummy) (void)hipGraphDestroy(dummy);
+          throw;
+        }
+        s = keep;
+        TN_HIP(hipStreamEndCapture(cs, &g));
+        TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        launch_set_job(dctl, -1, s);
+        for (int64_t j = 0; j < jobs; ++j) TN_HIP(hipGraphLaunch(ge, s));
+        TN_HIP(hipStreamSynchronize(s));
       } catch (...) {
-        hipGraph_t dummy = nullptr;
-        (void)hipStreamEndCapture(s, &dummy);
-        if (dummy) (void)hipGraphDestroy(dummy);
+        cleanup();
         throw;
       }
-      TN_HIP(hipStreamEndCapture(s, &g));
-      TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-      launch_set_job(dctl, -1, s);
-      for (int64_t j = 0; j < jobs; ++j) TN_HIP(hipGraphLaunch(ge, s));
-      TN_HIP(hipStreamSynchronize(s));
-      (void)hipGraphExecDestroy(ge);
-      (void)hipGraphDestroy(g);
+      cleanup();
+    } else if (profile) {
+      std::vector<hipEvent_t> ev(P.ops.size() + 1);
+      for (auto& e : ev) TN_HIP(hipEventCreate(&e));
+      for (int64_t j = 0; j < jobs; ++j) {
+        launch_set_job(dctl, j, s);
+        launch_gather_leaves(full, bufs[BUF_LEAF], reinterpret_cast<const LeafDesc*>(base + L.descs),
+                             int(P.leaves.size()), P.max_leaf_bits,
+                             reinterpret_cast<const int8_t*>(base + L.bits), nq, dctl, s);
+        TN_HIP(hipEventRecord(ev[0], s));
+        for (size_t k = 0; k < P.ops.size(); ++k) {
+          run_ops(std::vector<PlanOp>(P.ops.begin() + k, P.ops.begin() + k + 1), bufs, s);
+          TN_HIP(hipEventRecord(ev[k + 1], s));
+        }
+        launch_accumulate(bufs[P.final_buf] + P.final_off, static_cast<double2*>(out), P.final_bits,
+                          P.final_pos, dctl, o.accumulate, s);
+        TN_HIP(hipEventSynchronize(ev.back()));
+        for (size_t k = 0; k < P.ops.size(); ++k) {
+          float t = 0.f;
+          TN_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+          o.op_seconds[k] += t * 1e-3;
+        }
+      }
+      for (auto& e : ev) (void)hipEventDestroy(e);
     } else {
       for (int64_t j = 0; j < jobs; ++j) {
         launch_set_job(dctl, j, s);
@@ -473,6 +524,54 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
       rep->precision = o.precision;
       rep->nonfinite = flag;
       rep->err_bound = P.err_bound;
+    }
+  });
+}
+
+tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p, int32_t precision,
+                                  tn_plan_info* info) {
+  return guarded([&] {
+    TN_REQUIRE(n && p && info, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
+    std::memset(info, 0, sizeof(*info));
+    info->n_ops = int32_t(plan->ops.size());
+    for (const PlanOp& op : plan->ops) {
+      info->n_by_kind[op.kind]++;
+      info->flops_by_kind[op.kind] += op.flops;
+      info->bytes_by_kind[op.kind] += op.bytes;
+    }
+    info->workspace_bytes = double(ws_layout(*plan, 1).total);
+    info->err_bound = plan->err_bound;
+  });
+}
+
+tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t precision,
+                                 int32_t* kind, double* flops, double* bytes, int64_t* mnkb) {
+  return guarded([&] {
+    TN_REQUIRE(n && p, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
+    for (size_t k = 0; k < plan->ops.size(); ++k) {
+      const PlanOp& op = plan->ops[k];
+      if (kind) kind[k] = op.kind;
+      if (flops) flops[k] = op.flops;
+      if (bytes) bytes[k] = op.bytes;
+      if (mnkb) {
+        int64_t* r = mnkb + 4 * k;
+        r[0] = r[1] = r[2] = r[3] = 1;
+        if (op.kind == OP_GEMM) {
+          r[0] = op.gm.M; r[1] = op.gm.N; r[2] = op.gm.K; r[3] = op.gm.batch;
+        } else if (op.kind == OP_APPLY) {
+          r[0] = int64_t(1) << (op.ap.a_bits - op.ap.nk);
+          r[1] = int64_t(1) << op.ap.nn;
+          r[2] = int64_t(1) << op.ap.nk;
+        } else if (op.kind == OP_DOT) {
+          r[2] = op.dot_k; r[3] = op.dot_batch;
+        } else {
+          r[0] = int64_t(1) << op.pm.nb;
+        }
+      }
     }
   });
 }

@@ -32,11 +32,49 @@ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 static int grid_cap() { return 256 * 16; }
 
+// ------------------------------------------------------- bfloat16 helpers
+
+// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_float(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Split a complex value into NP bfloat16 parts, each packed (re | im << 16):
+// part p holds the rounding of what parts 0..p-1 left over.
+template <int NP>
+__device__ __forceinline__ void split_c(float2 v, uint32_t* w) {
+  float r = v.x, i = v.y;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const uint32_t hr = bf16_bits(r), hi = bf16_bits(i);
+    w[p] = hr | (hi << 16);
+    r -= bf16_to_float(hr);
+    i -= bf16_to_float(hi);
+  }
+}
+
+// NP = 0 writes complex64; NP = 2 / 3 writes NP planes of packed bf16 words
+// (plane p at out + p * plane).
+template <int NP>
+__device__ __forceinline__ void put(void* out, int64_t plane, int64_t idx, float2 v) {
+  if constexpr (NP == 0) {
+    static_cast<float2*>(out)[idx] = v;
+  } else {
+    uint32_t w[NP];
+    split_c<NP>(v, w);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) static_cast<uint32_t*>(out)[p * plane + idx] = w[p];
+  }
+}
+
 // ------------------------------------------------------------------ permute
 
 struct PermArgs {
   int tb, rb;
   int64_t n_tiles;
+  int64_t plane;
   int8_t tpos[10];
   int8_t opos[10];
   int8_t map[10];
@@ -44,9 +82,9 @@ struct PermArgs {
   int8_t r_out[kMaxBits];
 };
 
+template <int NP>
 __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __restrict__ in,
-                                                            float2* __restrict__ out,
-                                                            PermArgs P) {
+                                                            void* __restrict__ out, PermArgs P) {
   __shared__ int64_t s_in_lo[32], s_in_hi[32], s_out_lo[32], s_out_hi[32];
   __shared__ int s_l_lo[32], s_l_hi[32];
   __shared__ float2 tile[1024 + 32];
@@ -86,7 +124,7 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
     __syncthreads();
     for (int f = t; f < tsize; f += 256) {
       const int e = s_l_lo[f & 31] | s_l_hi[f >> 5];
-      out[ob + s_out_lo[f & 31] + s_out_hi[f >> 5]] = tile[e + (e >> 5)];
+      put<NP>(out, P.plane, ob + s_out_lo[f & 31] + s_out_hi[f >> 5], tile[e + (e >> 5)]);
     }
     __syncthreads();
   }
@@ -94,23 +132,29 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
 
 struct PermSimpleArgs {
   int nb;
+  int identity;
+  int64_t plane;
   int8_t src[kMaxBits];
 };
 
+template <int NP>
 __global__ __launch_bounds__(256) void permute_simple_kernel(const float2* __restrict__ in,
-                                                             float2* __restrict__ out,
+                                                             void* __restrict__ out,
                                                              PermSimpleArgs P, int64_t n) {
   for (int64_t o = int64_t(blockIdx.x) * 256 + threadIdx.x; o < n; o += int64_t(gridDim.x) * 256) {
-    int64_t off = 0;
-    for (int j = 0; j < P.nb; ++j)
-      if (P.src[j] >= 0 && ((o >> j) & 1)) off |= int64_t(1) << P.src[j];
-    out[o] = in[off];
+    int64_t off = o;
+    if (!P.identity) {
+      off = 0;
+      for (int j = 0; j < P.nb; ++j)
+        if (P.src[j] >= 0 && ((o >> j) & 1)) off |= int64_t(1) << P.src[j];
+    }
+    put<NP>(out, P.plane, o, in[off]);
   }
 }
 
-void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t s) {
+template <int NP>
+static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d, hipStream_t s) {
   const int nb = d.nb;
-  TN_REQUIRE(nb >= 0 && nb <= 62, TN_ERR_UNSUPPORTED, "tensor too large to permute");
   const int64_t n = int64_t(1) << nb;
   bool is_perm = d.nb_in == nb;
   bool ident = true;
@@ -123,16 +167,19 @@ void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStre
     inv[d.src[j]] = j;
     if (d.src[j] != j) ident = false;
   }
-  if (is_perm && ident) {
+  if (is_perm && ident && NP == 0) {
     TN_HIP(hipMemcpyAsync(out, in, size_t(n) * sizeof(float2), hipMemcpyDeviceToDevice, s));
     return;
   }
-  if (!is_perm || nb < 6) {
+  if (!is_perm || ident || nb < 6) {
     PermSimpleArgs P;
+    std::memset(&P, 0, sizeof(P));
     P.nb = nb;
+    P.identity = is_perm && ident;
+    P.plane = n;
     for (int j = 0; j < kMaxBits; ++j) P.src[j] = j < nb ? d.src[j] : -1;
-    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
-    permute_simple_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, n);
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap() * 2);
+    permute_simple_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, n);
     TN_HIP(hipGetLastError());
     return;
   }
@@ -150,6 +197,7 @@ void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStre
   PermArgs P;
   std::memset(&P, 0, sizeof(P));
   P.tb = cnt;
+  P.plane = n;
   std::vector<int> tpos, opos;
   for (int i = 0; i < nb; ++i)
     if (inT[i]) tpos.push_back(i);
@@ -171,8 +219,18 @@ void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStre
   P.rb = rb;
   P.n_tiles = int64_t(1) << rb;
   const int64_t blocks = std::min<int64_t>(P.n_tiles, 256 * 32);
-  permute_tiled_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P);
+  permute_tiled_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P);
   TN_HIP(hipGetLastError());
+}
+
+void launch_permute(const float2* in, void* out, const PermuteDesc& d, hipStream_t s) {
+  TN_REQUIRE(d.nb >= 0 && d.nb <= 62, TN_ERR_UNSUPPORTED, "tensor too large to permute");
+  switch (d.np) {
+    case 0: launch_permute_np<0>(in, out, d, s); break;
+    case 2: launch_permute_np<2>(in, out, d, s); break;
+    case 3: launch_permute_np<3>(in, out, d, s); break;
+    default: throw Error(TN_ERR_ARG, "internal: bad plane count");
+  }
 }
 
 // -------------------------------------------------------------- apply_small
@@ -278,26 +336,6 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Round-to-nearest-even float -> bfloat16 bits (finite inputs).
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ float bf16_to_float(uint32_t h) { return __uint_as_float(h << 16); }
-
-// Split a complex value into NP bfloat16 parts, each packed (re | im << 16).
-template <int NP>
-__device__ __forceinline__ void split_c(float2 v, uint32_t* w) {
-  float r = v.x, i = v.y;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const uint32_t hr = bf16_bits(r), hi = bf16_bits(i);
-    w[p] = hr | (hi << 16);
-    r -= bf16_to_float(hr);
-    i -= bf16_to_float(hi);
-  }
-}
 
 struct GemmArgs {
   int64_t M, N, K;
@@ -500,6 +538,176 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
       }
 }
 
+// Packed-plane complex GEMM for the split precisions.  Operands arrive as NP
+// bf16 planes (from the permute/split pass) with k fastest, so a K tile is
+// copied global -> LDS with 16-byte loads and no conversion; LDS is double
+// buffered (one barrier per K tile).  Each wave owns TM x TN MFMA tiles of
+// 32 rows x 16 complex columns; a K step of 8 complex values is one
+// v_mfma_f32_32x32x16_bf16 per product pair.
+struct PackedArgs {
+  int64_t M, N, K;
+  int64_t kchunk;
+  int ksplit;
+  int tiles_m, tiles_n;
+  int64_t plane_a, plane_b;
+};
+
+template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+__global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
+                                                          const uint32_t* __restrict__ Bp,
+                                                          float2* __restrict__ C, PackedArgs P) {
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 16;
+  static_assert(TM >= 1 && TN >= 1 && BK % 8 == 0, "bad tile");
+  constexpr int LDK = BK + 4;                       // words per LDS row (16-byte aligned)
+  constexpr int A_WORDS = NP * BM * LDK, B_WORDS = NP * BN * LDK;
+  constexpr int STAGE = A_WORDS + B_WORDS;
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+  constexpr int KQ = BK / 4;                        // uint4 per row per plane
+  constexpr int A_Q = NP * BM * KQ, B_Q = NP * BN * KQ;
+  constexpr int A_PER = (A_Q + 255) / 256, B_PER = (B_Q + 255) / 256;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+
+  const int nblk = gridDim.x;
+  int pid = blockIdx.x;
+  if ((nblk & 7) == 0) pid = (pid & 7) * (nblk >> 3) + (pid >> 3);
+  constexpr int GROUP = 8;
+  const int group_size = GROUP * P.tiles_n;
+  const int g = pid / group_size;
+  const int first_m = g * GROUP;
+  const int gm = min(P.tiles_m - first_m, GROUP);
+  const int tm_idx = first_m + (pid % group_size) % gm;
+  const int tn_idx = (pid % group_size) / gm;
+  const int64_t m0 = int64_t(tm_idx) * BM, n0 = int64_t(tn_idx) * BN;
+
+  const int zb = blockIdx.z;
+  const int ks = zb % P.ksplit;
+  const int64_t bidx = zb / P.ksplit;
+  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int64_t kend = min(P.K, kbeg + P.kchunk);
+  const uint32_t* Ab = Ap + bidx * P.M * P.K;
+  const uint32_t* Bb = Bp + bidx * P.N * P.K;
+
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  u32x4 ra[A_PER], rb[B_PER];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int q = tid + 256 * i;
+      const int p = q / (BM * KQ), rem = q % (BM * KQ);
+      const int r = rem / KQ, c = rem % KQ;
+      const int64_t m = m0 + r, k = k0 + 4 * c;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (q < A_Q && m < P.M && k < kend)
+        v = *reinterpret_cast<const u32x4*>(Ab + p * P.plane_a + m * P.K + k);
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int q = tid + 256 * i;
+      const int p = q / (BN * KQ), rem = q % (BN * KQ);
+      const int r = rem / KQ, c = rem % KQ;
+      const int64_t n = n0 + r, k = k0 + 4 * c;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (q < B_Q && n < P.N && k < kend)
+        v = *reinterpret_cast<const u32x4*>(Bb + p * P.plane_b + n * P.K + k);
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+    uint32_t* As = smem + buf * STAGE;
+    uint32_t* Bs = As + A_WORDS;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) {
+      const int q = tid + 256 * i;
+      if (q >= A_Q) break;
+      const int p = q / (BM * KQ), rem = q % (BM * KQ);
+      const int r = rem / KQ, c = rem % KQ;
+      *reinterpret_cast<u32x4*>(As + (p * BM + r) * LDK + 4 * c) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) {
+      const int q = tid + 256 * i;
+      if (q >= B_Q) break;
+      const int p = q / (BN * KQ), rem = q % (BN * KQ);
+      const int r = rem / KQ, c = rem % KQ;
+      *reinterpret_cast<u32x4*>(Bs + (p * BN + r) * LDK + 4 * c) = rb[i];
+    }
+  };
+
+  const int li = lane & 31, lh = lane >> 5;
+  const int bn_local = li >> 1, bt = li & 1;
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
+    const uint32_t* As = smem + buf * STAGE;
+    const uint32_t* Bs = As + A_WORDS;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 8) {
+      u32x4 av[NP][TM], bv[NP][TN];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          av[p][i] = *reinterpret_cast<const u32x4*>(As + (p * BM + wm0 + i * 32 + li) * LDK + kk + 4 * lh);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          u32x4 w = *reinterpret_cast<const u32x4*>(Bs + (p * BN + wn0 + j * 16 + bn_local) * LDK + kk + 4 * lh);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) w[q] = bt == 0 ? (w[q] ^ 0x80000000u) : ((w[q] >> 16) | (w[q] << 16));
+          bv[p][j] = w;
+        }
+      }
+      // product pairs (pa, pb) with pa + pb < NP, smallest first; the tile
+      // loops are innermost so consecutive MFMAs use independent accumulators
+#pragma unroll
+      for (int s2 = NP - 1; s2 >= 0; --s2)
+#pragma unroll
+        for (int pa = 0; pa <= s2; ++pa) {
+          const int pb = s2 - pa;
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]),
+                  acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  float* Cf = reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t m = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int64_t n = n0 + wn0 + j * 16 + bn_local;
+        if (m < P.M && n < P.N) Cf[(m * P.N + n) * 2 + bt] = acc[i][j][r];
+      }
+}
+
 __global__ __launch_bounds__(256) void reduce_splitk_kernel(const float2* __restrict__ part,
                                                             float2* __restrict__ C, int ksplit,
                                                             int64_t n) {
@@ -535,13 +743,6 @@ int pick_ksplit(const GemmDesc& g, const TileCfg& t, int64_t* kchunk) {
 }
 }  // namespace
 
-size_t gemm_workspace_bytes(const GemmDesc& g) {
-  const TileCfg t = pick_tile(g);
-  int64_t kchunk;
-  const int ks = pick_ksplit(g, t, &kchunk);
-  return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
-}
-
 template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 static void launch_gemm_cfg(const float2* A, const float2* B, float2* C, const GemmArgs& P,
                             int64_t batch, hipStream_t s) {
@@ -557,8 +758,102 @@ static void launch_gemm_prec(const float2* A, const float2* B, float2* C, const 
   else launch_gemm_cfg<128, 64, BK, 2, 2, PREC>(A, B, C, P, batch, s);
 }
 
+namespace {
+struct PackedCfg {
+  int bm, bn, bk;
+};
+PackedCfg pick_packed(const GemmDesc& g) {
+  const int bk = g.precision == TN_PREC_BF16X6 ? 16 : 32;
+  if (g.N <= 16) return {256, 16, bk};
+  if (g.N <= 32) return {128, 32, bk};
+  if (g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22)) return {256, 128, 16};
+  return {128, 64, bk};
+}
+}  // namespace
+
+template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
+                              int64_t batch, hipStream_t s) {
+  constexpr int LDK = BK + 4;
+  constexpr size_t lds = size_t(2) * NP * (BM + BN) * LDK * sizeof(uint32_t);
+  static bool attr_set = false;
+  if (!attr_set) {
+    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    attr_set = true;
+  }
+  dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
+  gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, 256, lds, s>>>(A, B, C, P);
+}
+
+template <int NP, int BK>
+static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
+                             int64_t batch, int bn, hipStream_t s) {
+  if (bn == 16) launch_packed_cfg<256, 16, BK, 4, 1, NP>(A, B, C, P, batch, s);
+  else if (bn == 32) launch_packed_cfg<128, 32, BK, 4, 1, NP>(A, B, C, P, batch, s);
+  else if (bn == 128) launch_packed_cfg<256, 128, 16, 2, 2, NP>(A, B, C, P, batch, s);
+  else launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s);
+}
+
+static int packed_ksplit(const GemmDesc& g, const PackedCfg& t, int64_t* kchunk) {
+  const int64_t tiles = ceil_div(g.M, t.bm) * ceil_div(g.N, t.bn) * g.batch;
+  int ks = 1;
+  const int64_t ksteps = ceil_div(g.K, t.bk);
+  while (tiles * ks < 1024 && ksteps / (ks * 2) >= 8 && ks < 256) ks *= 2;
+  *kchunk = ceil_div(ksteps, ks) * t.bk;
+  return int(ceil_div(g.K, *kchunk));
+}
+
+size_t gemm_workspace_bytes(const GemmDesc& g) {
+  if (g.packed) {
+    int64_t kchunk;
+    const int ks = packed_ksplit(g, pick_packed(g), &kchunk);
+    return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
+  }
+  const TileCfg t = pick_tile(g);
+  int64_t kchunk;
+  const int ks = pick_ksplit(g, t, &kchunk);
+  return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
+}
+
+static void launch_gemm_packed(const uint32_t* A, const uint32_t* B, float2* C, const GemmDesc& g,
+                               void* work, hipStream_t s) {
+  TN_REQUIRE(g.K % 4 == 0, TN_ERR_ARG, "internal: packed GEMM needs K % 4 == 0");
+  const PackedCfg t = pick_packed(g);
+  PackedArgs P;
+  P.M = g.M;
+  P.N = g.N;
+  P.K = g.K;
+  P.plane_a = g.plane_a;
+  P.plane_b = g.plane_b;
+  P.ksplit = packed_ksplit(g, t, &P.kchunk);
+  P.tiles_m = int(ceil_div(g.M, t.bm));
+  P.tiles_n = int(ceil_div(g.N, t.bn));
+  TN_REQUIRE(int64_t(P.tiles_m) * P.tiles_n < (int64_t(1) << 31) && g.batch * P.ksplit <= 65535,
+             TN_ERR_UNSUPPORTED, "GEMM grid too large");
+  float2* out = C;
+  if (P.ksplit > 1) {
+    TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "split-K GEMM needs workspace");
+    out = static_cast<float2*>(work);
+  }
+  if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16>(A, B, out, P, g.batch, t.bn, s);
+  else launch_packed_np<2, 32>(A, B, out, P, g.batch, t.bn, s);
+  TN_HIP(hipGetLastError());
+  if (P.ksplit > 1) {
+    const int64_t n = g.batch * g.M * g.N;
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
+    reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, P.ksplit, n);
+    TN_HIP(hipGetLastError());
+  }
+}
+
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
                  hipStream_t s) {
+  if (g.packed) {
+    launch_gemm_packed(reinterpret_cast<const uint32_t*>(A), reinterpret_cast<const uint32_t*>(B), C,
+                       g, work, s);
+    return;
+  }
   TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1, TN_ERR_ARG, "bad GEMM shape");
   TN_REQUIRE(g.batch <= 65535, TN_ERR_UNSUPPORTED, "GEMM batch too large");
   const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision

@@ -13,12 +13,15 @@ constexpr int kMaxBits = 64;
 
 // Bit permutation out[o] = in[gather(o)]: output bit j takes input bit src[j];
 // src[j] == -1 broadcasts (stride 0).  `nb` output bits; `nb_in` input bits.
+// np = 2 or 3 additionally splits every entry into np bfloat16 parts and
+// writes np planes of packed (re | im << 16) words, plane p at out + p * 2^nb.
 struct PermuteDesc {
   int nb = 0;
   int nb_in = 0;
+  int np = 0;
   int8_t src[kMaxBits];
 };
-void launch_permute(const float2* in, float2* out, const PermuteDesc& d, hipStream_t s);
+void launch_permute(const float2* in, void* out, const PermuteDesc& d, hipStream_t s);
 
 // C[m * 2^nn + n] = sum_k A[expand(m) + kscat(k)] * B[bscat(k, n)]
 //   A: `a_bits` bits; K bits of A at positions kpos (ascending), others are M.
@@ -42,10 +45,15 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 
 // Complex GEMM C[b][m][n] = sum_k A[b](m,k) * B[b](k,n), contiguous operands.
 // transA = 0: A[b][m][k]; 1: A[b][k][m].  transB = 0: B[b][k][n]; 1: B[b][n][k].
+// packed = 1: A and B are bf16 planes from launch_permute (np = 2 for
+// BF16X3, 3 for BF16X6) in the layouts [b][M][K] and [b][N][K] (k fastest);
+// plane_a / plane_b are the plane strides in words; K must be a multiple of 4.
 struct GemmDesc {
   int64_t M = 1, N = 1, K = 1, batch = 1;
   int transA = 0, transB = 0;
   int precision = 0;       // TN_PREC_FP32 / BF16X3 / BF16X6
+  int packed = 0;
+  int64_t plane_a = 0, plane_b = 0;
 };
 // Workspace needed for split-K partials (bytes); 0 when no split is used.
 size_t gemm_workspace_bytes(const GemmDesc& g);

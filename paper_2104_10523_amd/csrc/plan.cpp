@@ -74,13 +74,16 @@ std::vector<int> order_in(const std::vector<int>& layout, const std::set<int>& s
 
 double p2(size_t bits) { return std::ldexp(1.0, int(bits)); }
 
+// np > 0: the output is np planes of packed bfloat16 parts (for the split
+// GEMMs) instead of complex64.
 TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
                   std::vector<PlanOp>& ops, std::vector<int64_t>* scratch, int out_buf = -1,
-                  int64_t out_off = 0) {
+                  int64_t out_off = 0, int np = 0) {
   PlanOp op;
   op.kind = OP_PERMUTE;
   op.pm.nb = int(target.size());
   op.pm.nb_in = int(in.labels.size());
+  op.pm.np = np;
   TN_REQUIRE(op.pm.nb <= kMaxBits && op.pm.nb_in <= kMaxBits, TN_ERR_UNSUPPORTED, "rank > 64");
   for (int j = 0; j < op.pm.nb; ++j)
     op.pm.src[j] = int8_t(pos_of(in.labels, target[op.pm.nb - 1 - j]));
@@ -91,14 +94,15 @@ TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
     out.off = out_off;
   } else {
     out.buf = BUF_WORK;
-    out.off = arena.alloc(int64_t(1) << op.pm.nb);
+    const int64_t elems = int64_t(1) << op.pm.nb;
+    out.off = arena.alloc(np ? (elems * np + 1) / 2 : elems);
     scratch->push_back(out.off);
   }
   op.a_buf = in.buf;
   op.a_off = in.off;
   op.c_buf = out.buf;
   op.c_off = out.off;
-  op.bytes = 8.0 * (p2(op.pm.nb) + p2(op.pm.nb_in));
+  op.bytes = 8.0 * p2(op.pm.nb_in) + (np ? 4.0 * np : 8.0) * p2(op.pm.nb);
   ops.push_back(op);
   return out;
 }
@@ -291,7 +295,16 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   auto lowest = [](const TRef& T) { return T.labels.empty() ? -1 : T.labels.back(); };
   int transA = 0, transB = 0;
   TRef Ap = A, Bp = B;
-  if (Mn == 1 && Nn == 1) {
+  const int prec = resolve_precision(precision, Mn, Nn, Kn);
+  const bool packed = (prec == TN_PREC_BF16X3 || prec == TN_PREC_BF16X6) && Kn % 4 == 0 &&
+                      !(Mn == 1 && Nn == 1);
+  const int np = prec == TN_PREC_BF16X6 ? 3 : 2;
+  if (packed) {
+    Ap = emit_permute(A, cat({b_o, m_o, k_o}), arena, ops, scratch, -1, 0, np);
+    Bp = emit_permute(B, cat({b_o, n_o, k_o}), arena, ops, scratch, -1, 0, np);
+    transA = 0;
+    transB = 1;
+  } else if (Mn == 1 && Nn == 1) {
     const auto fa = cat({b_o, k_o});
     if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
     if (B.labels != fa) Bp = emit_permute(B, fa, arena, ops, scratch);
@@ -342,7 +355,10 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.gm.batch = Bn;
     op.gm.transA = transA;
     op.gm.transB = transB;
-    op.gm.precision = resolve_precision(precision, Mn, Nn, Kn);
+    op.gm.precision = prec;
+    op.gm.packed = packed ? 1 : 0;
+    op.gm.plane_a = Bn * Mn * Kn;
+    op.gm.plane_b = Bn * Nn * Kn;
     const size_t wb = gemm_workspace_bytes(op.gm);
     if (wb > 0) {
       op.work_off = arena.alloc(int64_t((wb + 7) / 8));

@@ -101,16 +101,23 @@ def test_contract_pair_unshuffled_orders(gpu, workspace):
 
 
 def test_contract_pair_large_mfma(gpu, workspace):
-    """A contraction large enough to span many MFMA tiles, all precisions;
-    checked on 4096 sampled output entries computed one by one."""
+    """A contraction spanning many MFMA tiles (M = 2^12, N = 2^11, K = 2^9),
+    all precisions, on 2048 sampled output entries that the oracle computes
+    one by one."""
+    from oracle.contract import contract_entries
     A, la, B, lb, lc, shape_c = make_case(11, nm=12, nk=9, nn=11)
-    ref_full = None
+    rng = np.random.default_rng(5)
+    idx = [tuple(int(rng.integers(0, e)) for e in shape_c) for _ in range(2048)]
+    ref = contract_entries(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc, idx)
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
     for prec in ("fp32", "bf16x3", "bf16x6"):
         got = run(A, la, B, lb, lc, shape_c, prec)
-        if ref_full is None:
-            ref_full = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
-        assert l2_rel(got, ref_full) <= TOL[prec], prec
-        assert floored_rel(got, ref_full, 1e-3 * np.abs(ref_full).max()) <= 100 * TOL[prec]
+        g = np.array([got[i] for i in idx])
+        e2 = l2_rel(g, ref)
+        ef = floored_rel(g, ref, 0.1 * rms)
+        print(f"large {prec}: l2 {e2:.2e} floored {ef:.2e}", flush=True)
+        assert e2 <= TOL[prec], (prec, e2)
+        assert ef <= 20 * TOL[prec], (prec, ef)
 
 
 def test_contract_pair_errors(gpu, workspace):

@@ -254,3 +254,14 @@ def test_splitmix64_reference_values():
     # published SplitMix64 outputs for seed 0 (first three draws)
     g = SplitMix64(0)
     assert [g.next_u64() for _ in range(3)] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_contract_entries_match_full():
+    from oracle.contract import contract_entries
+    A = random_complex([2, 3, 2, 2], 1)
+    B = random_complex([2, 2, 4], 2)
+    la, lb, lc = [0, 1, 2, 3], [2, 0, 4], [4, 1, 3]
+    full = contract_pair(A, la, B, lb, lc)
+    idx = [(0, 0, 0), (3, 2, 1), (1, 1, 0)]
+    got = contract_entries(A, la, B, lb, lc, idx)
+    assert np.abs(got - np.array([full[i] for i in idx])).max() <= 1e-14
