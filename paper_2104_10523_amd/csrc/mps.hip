@@ -1,0 +1,697 @@
+// Matrix product states (Sec. 3.2): one-qubit gates absorbed into sites;
+// two-qubit gates by merge -> SVD -> truncate -> update.
+//
+// Site tensors are complex64 (chi_l, 2, chi_r) in library-owned device
+// memory.  The two-site tensor theta is formed by the complex MFMA GEMM; the
+// gate is mixed in while theta is converted to FP64; the SVD is one-sided
+// Jacobi in FP64 (parallel column-pair rounds, one workgroup per pair, a
+// whole sweep replayed as a hipGraph until no rotation exceeds the
+// tolerance); the orthogonality centre is moved by FP64 Householder QR.
+// Truncation keeps s / s_max > cutoff, at most chi_max values, renormalised
+// to unit norm; S is absorbed toward the side the centre came from.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+#include "gates.hpp"
+#include "kernels.hpp"
+
+namespace tn {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+struct Mat4 {
+  double2 g[16];
+};
+struct Mat2 {
+  double2 g[4];
+};
+
+__global__ void gate1_kernel(float2* __restrict__ A, int chil, int chir, Mat2 G) {
+  const int64_t n = int64_t(chil) * chir;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t l = i / chir, r = i % chir;
+    const float2 a0 = A[(l * 2 + 0) * chir + r], a1 = A[(l * 2 + 1) * chir + r];
+    const double2 x0 = make_double2(a0.x, a0.y), x1 = make_double2(a1.x, a1.y);
+    const double2 y0 = cadd(cmul(G.g[0], x0), cmul(G.g[1], x1));
+    const double2 y1 = cadd(cmul(G.g[2], x0), cmul(G.g[3], x1));
+    A[(l * 2 + 0) * chir + r] = make_float2(float(y0.x), float(y0.y));
+    A[(l * 2 + 1) * chir + r] = make_float2(float(y1.x), float(y1.y));
+  }
+}
+
+// theta[(l,s1),(s2,r)] (complex64, from the GEMM) -> gate-mixed FP64 matrix
+// M[(l,t1),(t2,r)], stored column-major as W: if !trans, W column j = M[:, j]
+// (mm = 2 chil rows); else W column j = conj(M[j, :]) (mm = 2 chir rows).
+__global__ void mix_kernel(const float2* __restrict__ theta, double2* __restrict__ W, int chil, int chir,
+                           Mat4 G, int trans) {
+  const int64_t rows = 2 * int64_t(chil), cols = 2 * int64_t(chir);
+  const int64_t n = rows * cols;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t row = i / cols, col = i % cols;
+    const int64_t l = row >> 1, t1 = row & 1, t2 = col / chir, r = col % chir;
+    double2 acc = make_double2(0, 0);
+    for (int s1 = 0; s1 < 2; ++s1)
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const float2 th = theta[(l * 2 + s1) * cols + s2 * chir + r];
+        acc = cadd(acc, cmul(G.g[(t1 * 2 + t2) * 4 + s1 * 2 + s2], make_double2(th.x, th.y)));
+      }
+    if (!trans) W[col * rows + row] = acc;
+    else W[row * cols + col] = make_double2(acc.x, -acc.y);
+  }
+}
+
+__global__ void eye_kernel(double2* __restrict__ V, int nn, int* flag) {
+  const int64_t n = int64_t(nn) * nn;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    V[i] = make_double2((i / nn) == (i % nn) ? 1.0 : 0.0, 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 0;
+}
+
+__global__ void flag_reset_kernel(int* flag) { *flag = 0; }
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0;
+  const int nw = blockDim.x >> 6;
+  for (int k = 0; k < nw; ++k) t += red[k];
+  return t;
+}
+
+// One round of the parallel (circle-method) ordering: block k rotates the
+// column pair (p, q) of W (mm x nn, column-major) and of V (nn x nn).
+__global__ __launch_bounds__(256) void jacobi_round_kernel(double2* __restrict__ W, double2* __restrict__ V,
+                                                           int mm, int nn, int npad, int round, double tol,
+                                                           int* flag) {
+  __shared__ double red[3][8];
+  const int k = blockIdx.x;
+  auto idx = [&](int i) { return i == 0 ? 0 : ((i - 1 + round) % (npad - 1)) + 1; };
+  int p = idx(k), q = idx(npad - 1 - k);
+  if (p > q) { const int t = p; p = q; q = t; }
+  if (q >= nn) return;  // pair with the padding column
+  double2* wp = W + int64_t(p) * mm;
+  double2* wq = W + int64_t(q) * mm;
+  double al = 0, be = 0, gr = 0, gi = 0;
+  for (int i = threadIdx.x; i < mm; i += blockDim.x) {
+    const double2 a = wp[i], b = wq[i];
+    al += a.x * a.x + a.y * a.y;
+    be += b.x * b.x + b.y * b.y;
+    gr += a.x * b.x + a.y * b.y;
+    gi += a.x * b.y - a.y * b.x;
+  }
+  al = block_sum(al, red[0]);
+  be = block_sum(be, red[1]);
+  gr = block_sum(gr, red[2]);
+  __syncthreads();
+  gi = block_sum(gi, red[0]);
+  const double g = sqrt(gr * gr + gi * gi);
+  if (!(g > tol * sqrt(al * be)) || g == 0.0) return;
+  if (threadIdx.x == 0) *flag = 1;
+  const double zeta = (be - al) / (2.0 * g);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  const double2 e = make_double2(gr / g, gi / g);               // e^{i phi}
+  const double2 sp = make_double2(s * e.x, s * e.y);             // s e^{i phi}
+  const double2 sm = make_double2(s * e.x, -s * e.y);            // s e^{-i phi}
+  for (int i = threadIdx.x; i < mm; i += blockDim.x) {
+    const double2 a = wp[i], b = wq[i];
+    const double2 sb = cmul(sm, b), sa = cmul(sp, a);
+    wp[i] = make_double2(c * a.x - sb.x, c * a.y - sb.y);
+    wq[i] = make_double2(sa.x + c * b.x, sa.y + c * b.y);
+  }
+  double2* vp = V + int64_t(p) * nn;
+  double2* vq = V + int64_t(q) * nn;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const double2 a = vp[i], b = vq[i];
+    const double2 sb = cmul(sm, b), sa = cmul(sp, a);
+    vp[i] = make_double2(c * a.x - sb.x, c * a.y - sb.y);
+    vq[i] = make_double2(sa.x + c * b.x, sa.y + c * b.y);
+  }
+}
+
+__global__ __launch_bounds__(256) void colnorm_kernel(const double2* __restrict__ W, int mm, double* S) {
+  __shared__ double red[8];
+  const double2* w = W + int64_t(blockIdx.x) * mm;
+  double a = 0;
+  for (int i = threadIdx.x; i < mm; i += blockDim.x) a += w[i].x * w[i].x + w[i].y * w[i].y;
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) S[blockIdx.x] = sqrt(a);
+}
+
+// New sites from the factorisation.  U column k (m = 2 chil entries) and Vh
+// row k (2 chir entries) for kept index order[k]:
+//   !trans: U[:,k] = W[:,j] / s_j,   Vh[k,:] = conj(V[:, j])^T
+//    trans: U[:,k] = V[:, j],         Vh[k,:] = conj(W[:, j])^T / s_j
+// right: A_i = U, A_{i+1} = S Vh; left: A_i = U S, A_{i+1} = Vh (S scaled).
+__global__ void write_sites_kernel(const double2* __restrict__ W, const double2* __restrict__ V,
+                                   const double* __restrict__ S, const int* __restrict__ order, int keep,
+                                   double scale, int chil, int chir, int mm, int nn, int trans, int right,
+                                   float2* __restrict__ Ai, float2* __restrict__ Aj) {
+  const int64_t nu = int64_t(2) * chil * keep, nv = int64_t(keep) * 2 * chir;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nu + nv; i += int64_t(gridDim.x) * blockDim.x) {
+    if (i < nu) {
+      const int64_t row = i / keep, k = i % keep;   // A_i[(l,s), k]
+      const int j = order[k];
+      const double sj = S[j];
+      double2 u;
+      if (!trans) {
+        const double2 w = W[int64_t(j) * mm + row];
+        u = sj > 0 ? make_double2(w.x / sj, w.y / sj) : make_double2(0, 0);
+      } else {
+        u = V[int64_t(j) * nn + row];
+      }
+      if (!right) u = make_double2(u.x * sj * scale, u.y * sj * scale);
+      Ai[row * keep + k] = make_float2(float(u.x), float(u.y));
+    } else {
+      const int64_t t = i - nu;
+      const int64_t k = t / (2 * chir), col = t % (2 * chir);   // A_{i+1}[k, (s,r)]
+      const int j = order[k];
+      const double sj = S[j];
+      double2 v;
+      if (!trans) {
+        const double2 x = V[int64_t(j) * nn + col];
+        v = make_double2(x.x, -x.y);
+      } else {
+        const double2 w = W[int64_t(j) * mm + col];
+        v = sj > 0 ? make_double2(w.x / sj, -w.y / sj) : make_double2(0, 0);
+      }
+      if (right) v = make_double2(v.x * sj * scale, v.y * sj * scale);
+      Aj[k * 2 * chir + col] = make_float2(float(v.x), float(v.y));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- QR
+
+// X (m x n, row-major, FP64) from a site: !adj: X[(l,s), r] = A[l,s,r]
+// (m = 2 chil, n = chir); adj: X = (A as chil x 2chir)^dagger (m = 2 chir,
+// n = chil).
+__global__ void site_to_x_kernel(const float2* __restrict__ A, double2* __restrict__ X, int chil, int chir,
+                                 int adj) {
+  const int64_t n = int64_t(chil) * 2 * chir;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const float2 a = A[i];
+    if (!adj) {
+      X[i] = make_double2(a.x, a.y);
+    } else {
+      const int64_t l = i / (2 * chir), c = i % (2 * chir);
+      X[c * chil + l] = make_double2(a.x, -a.y);
+    }
+  }
+}
+
+// Householder QR of X (m x n row-major, in place) in one workgroup; writes
+// R (k x n, k = min(m, n)) and the reflectors' scalars to tau (k entries).
+__global__ __launch_bounds__(1024) void householder_kernel(double2* __restrict__ X, int m, int n,
+                                                           double2* __restrict__ R, double2* __restrict__ tau) {
+  __shared__ double red[16];
+  __shared__ double2 s_alpha;
+  __shared__ double s_beta, s_vnorm2;
+  const int k = min(m, n);
+  for (int j = 0; j < k; ++j) {
+    double ss = 0;
+    for (int i = j + threadIdx.x; i < m; i += blockDim.x) {
+      const double2 x = X[int64_t(i) * n + j];
+      ss += x.x * x.x + x.y * x.y;
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+      const double2 alpha = X[int64_t(j) * n + j];
+      const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+      const double nrm = sqrt(ss);
+      // beta = -e^{i arg alpha} ||x||; v = x - beta e_1
+      const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
+      const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+      s_alpha = make_double2(alpha.x - beta.x, alpha.y - beta.y);  // v[0]
+      // |v|^2 = |x|^2 - |alpha|^2 + |alpha - beta|^2
+      s_vnorm2 = ss - an * an + s_alpha.x * s_alpha.x + s_alpha.y * s_alpha.y;
+      s_beta = nrm;
+      X[int64_t(j) * n + j] = s_alpha;
+      R[int64_t(j) * n + j] = beta;
+      tau[j] = make_double2(s_vnorm2 > 0 ? 2.0 / s_vnorm2 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const double t2 = s_vnorm2 > 0 ? 2.0 / s_vnorm2 : 0.0;
+    // apply H = I - t2 v v^dagger to columns c > j: one wave per column
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int c = j + 1 + wave; c < n; c += nw) {
+      double dr = 0, di = 0;  // v^dagger x_c
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 v = X[int64_t(i) * n + j], x = X[int64_t(i) * n + c];
+        dr += v.x * x.x + v.y * x.y;
+        di += v.x * x.y - v.y * x.x;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        dr += __shfl_xor(dr, o);
+        di += __shfl_xor(di, o);
+      }
+      const double2 f = make_double2(t2 * dr, t2 * di);
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 v = X[int64_t(i) * n + j];
+        double2 x = X[int64_t(i) * n + c];
+        const double2 fv = cmul(v, f);
+        x.x -= fv.x;
+        x.y -= fv.y;
+        X[int64_t(i) * n + c] = x;
+      }
+      if (lane == 0) {
+        // row j of R after the reflection (read once all lanes updated it)
+      }
+    }
+    __syncthreads();
+    for (int c = j + 1 + threadIdx.x; c < n; c += blockDim.x) R[int64_t(j) * n + c] = X[int64_t(j) * n + c];
+    for (int c = threadIdx.x; c < j; c += blockDim.x) R[int64_t(j) * n + c] = make_double2(0, 0);
+    __syncthreads();
+  }
+}
+
+// Q (m x k, row-major) = H_0 ... H_{k-1} [I; 0], one workgroup.
+__global__ __launch_bounds__(1024) void form_q_kernel(const double2* __restrict__ X, int m, int n,
+                                                      const double2* __restrict__ tau, double2* __restrict__ Q) {
+  const int k = min(m, n);
+  for (int64_t i = threadIdx.x; i < int64_t(m) * k; i += blockDim.x)
+    Q[i] = make_double2((i / k) == (i % k) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int j = k - 1; j >= 0; --j) {
+    const double t2 = tau[j].x;
+    for (int c = j + wave; c < k; c += nw) {
+      double dr = 0, di = 0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 v = X[int64_t(i) * n + j], q = Q[int64_t(i) * k + c];
+        dr += v.x * q.x + v.y * q.y;
+        di += v.x * q.y - v.y * q.x;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        dr += __shfl_xor(dr, o);
+        di += __shfl_xor(di, o);
+      }
+      const double2 f = make_double2(t2 * dr, t2 * di);
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 fv = cmul(X[int64_t(i) * n + j], f);
+        double2 q = Q[int64_t(i) * k + c];
+        q.x -= fv.x;
+        q.y -= fv.y;
+        Q[int64_t(i) * k + c] = q;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Write Q back as the site: !adj: A[(l,s), k] = Q; adj: A = Q^dagger
+// (k x 2chir) -> A[k, (s,r)].
+__global__ void q_to_site_kernel(const double2* __restrict__ Q, float2* __restrict__ A, int m, int k, int adj) {
+  const int64_t n = int64_t(m) * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = i / k, c = i % k;
+    const double2 q = Q[i];
+    if (!adj) A[i] = make_float2(float(q.x), float(q.y));
+    else A[c * m + r] = make_float2(float(q.x), float(-q.y));
+  }
+}
+
+// Neighbour update.  right: B'[k, (s,r)] = sum_c R[k, c] B[c, (s,r)]
+// (B rows = chir_old); left: B'[(l,s), k] = sum_c B[(l,s), c] conj(R[k, c]).
+__global__ void apply_r_kernel(const double2* __restrict__ R, int k, int nr, const float2* __restrict__ B,
+                               float2* __restrict__ Bout, int64_t other, int right) {
+  const int64_t n = int64_t(k) * other;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    double2 acc = make_double2(0, 0);
+    if (right) {
+      const int64_t kk = i / other, col = i % other;
+      for (int c = 0; c < nr; ++c) {
+        const float2 b = B[int64_t(c) * other + col];
+        acc = cadd(acc, cmul(R[kk * nr + c], make_double2(b.x, b.y)));
+      }
+      Bout[kk * other + col] = make_float2(float(acc.x), float(acc.y));
+    } else {
+      const int64_t row = i / k, kk = i % k;
+      for (int c = 0; c < nr; ++c) {
+        const float2 b = B[row * nr + c];
+        acc = cadd(acc, cmulc(R[kk * nr + c], make_double2(b.x, b.y)));
+      }
+      Bout[row * k + kk] = make_float2(float(acc.x), float(acc.y));
+    }
+  }
+}
+
+// <Z> of the centre site: sum |A[l,s,r]|^2 (1 - 2s) / sum |A|^2.
+__global__ __launch_bounds__(256) void site_z_kernel(const float2* __restrict__ A, int chil, int chir, double* out) {
+  __shared__ double red[8];
+  double z = 0, nn = 0;
+  const int64_t n = int64_t(chil) * 2 * chir;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float2 a = A[i];
+    const double p = double(a.x) * a.x + double(a.y) * a.y;
+    const int s = int((i / chir) & 1);
+    z += s ? -p : p;
+    nn += p;
+  }
+  z = block_sum(z, red);
+  __syncthreads();
+  nn = block_sum(nn, red);
+  if (threadIdx.x == 0) *out = nn > 0 ? z / nn : 0.0;
+}
+
+// Amplitudes: one workgroup per bit-string, v <- v A_i[:, b_i, :] in FP64.
+__global__ __launch_bounds__(256) void mps_amp_kernel(const float2* const* __restrict__ sites,
+                                                     const int* __restrict__ chi, int n_sites,
+                                                     const int8_t* __restrict__ bits, double2* __restrict__ out,
+                                                     int cmax) {
+  extern __shared__ double2 vbuf[];
+  double2* v = vbuf;
+  double2* w = vbuf + cmax;
+  const int8_t* b = bits + int64_t(blockIdx.x) * n_sites;
+  if (threadIdx.x == 0) v[0] = make_double2(1, 0);
+  __syncthreads();
+  int cl = 1;
+  for (int i = 0; i < n_sites; ++i) {
+    const int cr = i + 1 < n_sites ? chi[i] : 1;
+    const float2* A = sites[i];
+    const int s = b[i];
+    for (int r = threadIdx.x; r < cr; r += blockDim.x) {
+      double2 acc = make_double2(0, 0);
+      for (int l = 0; l < cl; ++l) {
+        const float2 a = A[(int64_t(l) * 2 + s) * cr + r];
+        acc = cadd(acc, cmul(v[l], make_double2(a.x, a.y)));
+      }
+      w[r] = acc;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < cr; r += blockDim.x) v[r] = w[r];
+    __syncthreads();
+    cl = cr;
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = v[0];
+}
+
+int grid_for(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096))); }
+
+}  // namespace
+}  // namespace tn
+
+using namespace tn;
+
+struct tn_mps {
+  int n = 0, cmax = 0, center = 0, dev = 0;
+  std::vector<int> chi;            // bond i between sites i and i+1
+  std::vector<float2*> site;       // capacity cmax * 2 * cmax each
+  float2* theta = nullptr;         // (2 cmax) x (2 cmax) complex64
+  float2* tmp = nullptr;           // site-sized scratch
+  double2 *W = nullptr, *V = nullptr, *X = nullptr, *Q = nullptr, *R = nullptr, *tau = nullptr;
+  double* S = nullptr;
+  double* zbuf = nullptr;
+  int* flag = nullptr;
+  int* order = nullptr;
+  void* gemm_work = nullptr;
+  size_t gemm_work_bytes = 0;
+  std::map<std::pair<int, int>, hipGraphExec_t> sweeps;   // (mm, nn) -> one Jacobi sweep
+  hipStream_t gstream = nullptr;
+
+  int chil(int i) const { return i == 0 ? 1 : chi[i - 1]; }
+  int chir(int i) const { return i == n - 1 ? 1 : chi[i]; }
+
+  ~tn_mps() {
+    for (auto& kv : sweeps) (void)hipGraphExecDestroy(kv.second);
+    for (float2* p : site) (void)hipFree(p);
+    for (void* p : {(void*)theta, (void*)tmp, (void*)W, (void*)V, (void*)X, (void*)Q, (void*)R, (void*)tau,
+                    (void*)S, (void*)zbuf, (void*)flag, (void*)order, gemm_work})
+      if (p) (void)hipFree(p);
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
+};
+
+namespace {
+
+void move_right(tn_mps* m, int c, hipStream_t s) {
+  const int cl = m->chil(c), cr = m->chir(c);
+  const int rows = 2 * cl, cols = cr, k = std::min(rows, cols);
+  site_to_x_kernel<<<grid_for(int64_t(cl) * 2 * cr), 256, 0, s>>>(m->site[c], m->X, cl, cr, 0);
+  householder_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->R, m->tau);
+  form_q_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->tau, m->Q);
+  q_to_site_kernel<<<grid_for(int64_t(rows) * k), 256, 0, s>>>(m->Q, m->site[c], rows, k, 0);
+  // next site: (cr, 2, cr2) -> (k, 2, cr2)
+  const int cr2 = m->chir(c + 1);
+  const int64_t other = int64_t(2) * cr2;
+  apply_r_kernel<<<grid_for(int64_t(k) * other), 256, 0, s>>>(m->R, k, cr, m->site[c + 1], m->tmp, other, 1);
+  TN_HIP(hipMemcpyAsync(m->site[c + 1], m->tmp, size_t(k) * other * sizeof(float2), hipMemcpyDeviceToDevice, s));
+  TN_HIP(hipGetLastError());
+  m->chi[c] = k;
+  m->center = c + 1;
+}
+
+void move_left(tn_mps* m, int c, hipStream_t s) {
+  const int cl = m->chil(c), cr = m->chir(c);
+  const int rows = 2 * cr, cols = cl, k = std::min(rows, cols);   // X = A^dagger
+  site_to_x_kernel<<<grid_for(int64_t(cl) * 2 * cr), 256, 0, s>>>(m->site[c], m->X, cl, cr, 1);
+  householder_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->R, m->tau);
+  form_q_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->tau, m->Q);
+  // A_c = Q^dagger : (k, 2 cr)
+  q_to_site_kernel<<<grid_for(int64_t(rows) * k), 256, 0, s>>>(m->Q, m->site[c], rows, k, 1);
+  // previous site (cl2, 2, cl) -> (cl2, 2, k): B R^dagger
+  const int cl2 = m->chil(c - 1);
+  const int64_t rowsb = int64_t(cl2) * 2;
+  apply_r_kernel<<<grid_for(rowsb * k), 256, 0, s>>>(m->R, k, cl, m->site[c - 1], m->tmp, rowsb, 0);
+  TN_HIP(hipMemcpyAsync(m->site[c - 1], m->tmp, size_t(rowsb) * k * sizeof(float2), hipMemcpyDeviceToDevice, s));
+  TN_HIP(hipGetLastError());
+  m->chi[c - 1] = k;
+  m->center = c - 1;
+}
+
+void move_center(tn_mps* m, int target, hipStream_t s) {
+  while (m->center < target) move_right(m, m->center, s);
+  while (m->center > target) move_left(m, m->center, s);
+}
+
+// One Jacobi sweep (npad - 1 rounds) on (mm, nn), captured once.
+hipGraphExec_t sweep_graph(tn_mps* m, int mm, int nn) {
+  auto key = std::make_pair(mm, nn);
+  auto it = m->sweeps.find(key);
+  if (it != m->sweeps.end()) return it->second;
+  const int npad = nn + (nn & 1);
+  // rotations below this relative size are rounding noise of the m-term dot products
+  const double tol = 2.3e-16 * double(std::max(mm, 8));
+  if (!m->gstream) TN_HIP(hipStreamCreateWithFlags(&m->gstream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  TN_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
+  flag_reset_kernel<<<1, 1, 0, m->gstream>>>(m->flag);
+  for (int r = 0; r < npad - 1; ++r)
+    jacobi_round_kernel<<<npad / 2, 256, 0, m->gstream>>>(m->W, m->V, mm, nn, npad, r, tol, m->flag);
+  const hipError_t e = hipStreamEndCapture(m->gstream, &g);
+  TN_REQUIRE(e == hipSuccess, TN_ERR_DEVICE, "graph capture of the Jacobi sweep failed");
+  TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(g);
+  m->sweeps[key] = ge;
+  return ge;
+}
+
+void read_mat(const double* gate, int d, double2* out) {
+  for (int i = 0; i < d * d; ++i) out[i] = make_double2(gate[2 * i], gate[2 * i + 1]);
+}
+
+}  // namespace
+
+extern "C" {
+
+tn_status tn_mps_create(int32_t n_sites, int32_t chi_max, void* stream, tn_mps** out) {
+  return guarded([&] {
+    TN_REQUIRE(out && n_sites >= 2 && n_sites <= 4096, TN_ERR_ARG, "n_sites must be 2..4096");
+    TN_REQUIRE(chi_max >= 1 && chi_max <= 1024, TN_ERR_ARG, "chi_max must be 1..1024");
+    auto m = std::make_unique<tn_mps>();
+    m->n = n_sites;
+    m->cmax = chi_max;
+    TN_HIP(hipGetDevice(&m->dev));
+    m->chi.assign(n_sites - 1, 1);
+    const size_t cap = size_t(chi_max) * 2 * chi_max;
+    const size_t big = size_t(2 * chi_max) * size_t(2 * chi_max);
+    for (int i = 0; i < n_sites; ++i) {
+      float2* p = nullptr;
+      TN_HIP(hipMalloc(&p, cap * sizeof(float2)));
+      m->site.push_back(p);
+      const float2 init[2] = {make_float2(1.f, 0.f), make_float2(0.f, 0.f)};
+      TN_HIP(hipMemcpy(p, init, sizeof(init), hipMemcpyHostToDevice));
+    }
+    TN_HIP(hipMalloc(&m->theta, big * sizeof(float2)));
+    TN_HIP(hipMalloc(&m->tmp, cap * sizeof(float2)));
+    TN_HIP(hipMalloc(&m->W, big * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->V, big * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->X, cap * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->Q, cap * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->R, cap * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->tau, size_t(2 * chi_max) * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->S, size_t(2 * chi_max) * sizeof(double)));
+    TN_HIP(hipMalloc(&m->zbuf, size_t(n_sites) * sizeof(double)));
+    TN_HIP(hipMalloc(&m->flag, 256));
+    TN_HIP(hipMalloc(&m->order, size_t(2 * chi_max) * sizeof(int)));
+    m->gemm_work_bytes = size_t(64) << 20;
+    TN_HIP(hipMalloc(&m->gemm_work, m->gemm_work_bytes));
+    m->center = 0;
+    *out = m.release();
+  });
+}
+
+tn_status tn_mps_destroy(tn_mps* m) {
+  return guarded([&] { delete m; });
+}
+
+tn_status tn_mps_bond_dims(const tn_mps* m, int32_t* dims) {
+  return guarded([&] {
+    TN_REQUIRE(m && dims, TN_ERR_ARG, "null argument");
+    for (int i = 0; i < m->n - 1; ++i) dims[i] = m->chi[i];
+  });
+}
+
+tn_status tn_mps_apply_gate1(tn_mps* m, int32_t site, const double* gate, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(m && gate, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(site >= 0 && site < m->n, TN_ERR_SITE, "site out of range");
+    Mat2 G;
+    read_mat(gate, 2, G.g);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cl = m->chil(site), cr = m->chir(site);
+    gate1_kernel<<<grid_for(int64_t(cl) * cr), 256, 0, s>>>(m->site[site], cl, cr, G);
+    TN_HIP(hipGetLastError());
+  });
+}
+
+tn_status tn_mps_apply_gate(tn_mps* m, int32_t site, const double* gate, int32_t chi_max, double cutoff,
+                            double* discarded, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(m && gate, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(site >= 0 && site + 1 < m->n, TN_ERR_SITE, "site out of range (needs site + 1 < n)");
+    TN_REQUIRE(chi_max >= 1 && cutoff >= 0, TN_ERR_ARG, "chi_max must be >= 1 and cutoff >= 0");
+    chi_max = std::min(chi_max, m->cmax);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool right = m->center <= site;
+    move_center(m, right ? site : site + 1, s);
+    const int cl = m->chil(site), cm = m->chi[site], cr = m->chir(site + 1);
+    // theta = A_i (2cl x cm) . A_{i+1} (cm x 2cr) on the complex MFMA GEMM
+    GemmDesc g;
+    g.M = 2 * cl;
+    g.N = 2 * cr;
+    g.K = cm;
+    g.precision = TN_PREC_FP32;
+    TN_REQUIRE(gemm_workspace_bytes(g) <= m->gemm_work_bytes, TN_ERR_WORKSPACE, "MPS GEMM scratch too small");
+    launch_gemm(m->site[site], m->site[site + 1], m->theta, g, m->gemm_work, s);
+    Mat4 G;
+    read_mat(gate, 4, G.g);
+    const int rows = 2 * cl, cols = 2 * cr;
+    const int trans = cols > rows ? 1 : 0;
+    const int mm = trans ? cols : rows, nn = trans ? rows : cols;
+    mix_kernel<<<grid_for(int64_t(rows) * cols), 256, 0, s>>>(m->theta, m->W, cl, cr, G, trans);
+    eye_kernel<<<grid_for(int64_t(nn) * nn), 256, 0, s>>>(m->V, nn, m->flag);
+    TN_HIP(hipGetLastError());
+    // Jacobi sweeps until no pair needed a rotation (at most 60 sweeps)
+    hipGraphExec_t ge = sweep_graph(m, mm, nn);
+    hipEvent_t ev = nullptr;
+    TN_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    TN_HIP(hipEventRecord(ev, s));
+    TN_HIP(hipStreamWaitEvent(m->gstream, ev, 0));
+    int sweeps = 0, flag = 1;
+    while (flag && sweeps < 60) {
+      TN_HIP(hipGraphLaunch(ge, m->gstream));
+      TN_HIP(hipMemcpyAsync(&flag, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->gstream));
+      TN_HIP(hipStreamSynchronize(m->gstream));
+      ++sweeps;
+    }
+    colnorm_kernel<<<nn, 256, 0, m->gstream>>>(m->W, mm, m->S);
+    std::vector<double> S(nn);
+    TN_HIP(hipMemcpyAsync(S.data(), m->S, nn * sizeof(double), hipMemcpyDeviceToHost, m->gstream));
+    TN_HIP(hipStreamSynchronize(m->gstream));
+    // truncation on the host: descending order, ties by index
+    std::vector<int> order(nn);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return S[a] > S[b]; });
+    const double smax = S[order[0]];
+    int keep = 0;
+    for (int k = 0; k < nn; ++k)
+      if (smax > 0 && S[order[k]] > cutoff * smax) ++keep;
+    keep = std::max(1, std::min(keep, chi_max));
+    double total = 0, kept = 0;
+    for (int k = 0; k < nn; ++k) {
+      total += S[order[k]] * S[order[k]];
+      if (k < keep) kept += S[order[k]] * S[order[k]];
+    }
+    if (discarded) *discarded = total > 0 ? (total - kept) / total : 0.0;
+    const double scale = kept > 0 ? 1.0 / std::sqrt(kept) : 1.0;
+    TN_HIP(hipMemcpyAsync(m->order, order.data(), keep * sizeof(int), hipMemcpyHostToDevice, m->gstream));
+    const int64_t tot = int64_t(2) * cl * keep + int64_t(keep) * 2 * cr;
+    write_sites_kernel<<<grid_for(tot), 256, 0, m->gstream>>>(m->W, m->V, m->S, m->order, keep, scale, cl, cr,
+                                                              mm, nn, trans, right ? 1 : 0, m->site[site],
+                                                              m->site[site + 1]);
+    TN_HIP(hipGetLastError());
+    TN_HIP(hipEventRecord(ev, m->gstream));
+    TN_HIP(hipStreamWaitEvent(s, ev, 0));
+    TN_HIP(hipStreamSynchronize(s));
+    (void)hipEventDestroy(ev);
+    m->chi[site] = keep;
+    m->center = right ? site + 1 : site;
+  });
+}
+
+tn_status tn_mps_expect_z(tn_mps* m, double* out, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(m && out, TN_ERR_ARG, "null argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    move_center(m, 0, s);
+    for (int i = 0; i < m->n; ++i) {
+      if (i > 0) move_right(m, i - 1, s);
+      site_z_kernel<<<1, 256, 0, s>>>(m->site[i], m->chil(i), m->chir(i), m->zbuf + i);
+    }
+    TN_HIP(hipGetLastError());
+    TN_HIP(hipMemcpyAsync(out, m->zbuf, m->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    TN_HIP(hipStreamSynchronize(s));
+  });
+}
+
+tn_status tn_mps_amplitudes(tn_mps* m, const int8_t* bits, int64_t n_bs, double* out, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(m && bits && out && n_bs >= 1, TN_ERR_ARG, "bad argument");
+    for (int64_t i = 0; i < n_bs * m->n; ++i)
+      TN_REQUIRE(bits[i] == 0 || bits[i] == 1, TN_ERR_BITS, "MPS amplitudes need 0/1 bits");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nb = size_t(n_bs) * m->n;
+    int8_t* dbits = nullptr;
+    double2* dout = nullptr;
+    float2** dsites = nullptr;
+    int* dchi = nullptr;
+    TN_HIP(hipMalloc(&dbits, nb));
+    TN_HIP(hipMalloc(&dout, n_bs * sizeof(double2)));
+    TN_HIP(hipMalloc(&dsites, m->n * sizeof(float2*)));
+    TN_HIP(hipMalloc(&dchi, std::max(1, m->n - 1) * sizeof(int)));
+    TN_HIP(hipMemcpyAsync(dbits, bits, nb, hipMemcpyHostToDevice, s));
+    TN_HIP(hipMemcpyAsync(dsites, m->site.data(), m->n * sizeof(float2*), hipMemcpyHostToDevice, s));
+    TN_HIP(hipMemcpyAsync(dchi, m->chi.data(), (m->n - 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    mps_amp_kernel<<<unsigned(n_bs), 256, 2 * m->cmax * sizeof(double2), s>>>(dsites, dchi, m->n, dbits, dout,
+                                                                              m->cmax);
+    TN_HIP(hipGetLastError());
+    TN_HIP(hipMemcpyAsync(out, dout, n_bs * sizeof(double2), hipMemcpyDeviceToHost, s));
+    TN_HIP(hipStreamSynchronize(s));
+    (void)hipFree(dbits);
+    (void)hipFree(dout);
+    (void)hipFree(dsites);
+    (void)hipFree(dchi);
+  });
+}
+
+}  // extern "C"
