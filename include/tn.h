@@ -142,7 +142,10 @@ typedef struct {
   double mem_budget_bytes;    /* slice until 8*peak <= budget; <= 0: never  */
   const int8_t* open_mask;    /* n_qubits entries, 1 = output leg stays     */
                               /* open; NULL = every leg projected           */
-  const tn_model* model;      /* TN_PATH_LEARNED: trained scorer            */
+  const tn_model* model;      /* TN_PATH_LEARNED: trained scorer; the path  */
+                              /* takes the highest-scoring candidate each   */
+                              /* step and falls back to greedy when greedy  */
+                              /* is cheaper (flops, then peak)              */
 } tn_path_opts;
 
 typedef struct {
@@ -174,6 +177,66 @@ tn_status tn_path_from_pairs(const tn_network* n, const tn_path_opts* o,
  * NULL. */
 tn_status tn_path_get(const tn_path* p, int32_t* pairs, int32_t* sliced_labels);
 tn_status tn_path_destroy(tn_path* p);
+
+/* ---------------------------------------------------------------------- */
+/* Learned contraction-order scorer (path quality vs search time, Sec. 4.3)*/
+/* ---------------------------------------------------------------------- */
+
+/* A message-passing network over the candidate pairwise contractions of a
+ * path-search state (nodes; two candidates are neighbours when they share a
+ * tensor).  16 features per candidate (log sizes of A, B, C and A u B,
+ * shared labels, the greedy score and its offset from the best, live-tensor
+ * and candidate counts, tensor degrees, outer-product flag, constant 1).
+ *   h0 = relu(X W0 + b0); h_l = relu(h Ws_l + mean_nbrs(h) Wn_l + b_l),
+ *   l = 1..L; score = relu(h_L Wh + bh) . wo + bo.
+ * Parameters, in this order, row-major: W0 (16 x H), b0 (H), then per layer
+ * Ws (H x H), Wn (H x H), b (H), then Wh (H x H), bh (H), wo (H), bo (1).
+ * Trained by imitation of teacher paths: loss = logsumexp(scores) -
+ * score[teacher choice] per state; Adam.  Forward, backward and Adam run in
+ * hand-written FP32 kernels on the GPU. */
+
+/* H in 1..256, L in 0..8.  Parameters start at zero: set them with
+ * tn_model_set_params.  Errors: TN_ERR_ARG, TN_ERR_NOMEM, TN_ERR_DEVICE. */
+tn_status tn_model_create(int32_t hidden, int32_t layers, tn_model** out);
+tn_status tn_model_destroy(tn_model* m);
+tn_status tn_model_n_params(const tn_model* m, int64_t* n);
+/* Host FP64 arrays of n_params values (converted to / from FP32). */
+tn_status tn_model_set_params(tn_model* m, const double* theta);
+tn_status tn_model_get_params(const tn_model* m, double* theta);
+
+/* Features and line-graph neighbours of the state reached after applying the
+ * first n_prefix steps of `pairs` to network n (open legs per open_mask,
+ * NULL = all projected).  Outputs (any may be NULL): *n_cands; cand
+ * (2 * n_cands ints, SSA ids); X (n_cands x 16 doubles); nbr_ptr
+ * (n_cands + 1); nbr_idx (nbr_ptr[n_cands] ints, ascending per node).
+ * Call with NULL arrays first to learn n_cands and the neighbour count
+ * (*n_nbr).  Host only. */
+tn_status tn_model_state_features(const tn_network* n, const int8_t* open_mask,
+                                  const int32_t* pairs, int32_t n_prefix,
+                                  int32_t* n_cands, int32_t* n_nbr,
+                                  int32_t* cand, double* X, int32_t* nbr_ptr,
+                                  int32_t* nbr_idx);
+
+/* Loss and gradient (n_params doubles) of one state on the GPU: features X
+ * (n_cands x 16 doubles, host), CSR neighbours, teacher choice `label`.
+ * Synchronises. */
+tn_status tn_model_loss_grad(tn_model* m, int32_t n_cands, const double* X,
+                             const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                             int32_t label, double* loss, double* grad,
+                             double* scores, void* stream);
+
+/* Append every `stride`-th state of the teacher path `pairs` (n_steps, a
+ * path for network n) to the model's training set.  Host only. */
+tn_status tn_model_add_teacher(tn_model* m, const tn_network* n,
+                               const int8_t* open_mask, const int32_t* pairs,
+                               int32_t n_steps, int32_t stride);
+/* Adam (beta 0.9 / 0.999, eps 1e-8) over the training set: `epochs` passes
+ * in SplitMix64-shuffled mini-batches of `batch` states.  *loss_first and
+ * *loss_last (may be NULL) receive the mean loss of the first and last
+ * epoch.  Synchronises.  Errors: TN_ERR_STATE (empty training set). */
+tn_status tn_model_train(tn_model* m, int32_t epochs, int32_t batch,
+                         double lr, uint64_t seed, double* loss_first,
+                         double* loss_last, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Pairwise contraction (Sec. 3.1; Table 2 is dominated by it)            */

@@ -289,3 +289,97 @@ def tn_run_trajectories(circuits, traj_per_circ: int, uniforms, stream=None):
                                     z.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep),
                                     C.c_void_p(_stream_ptr(stream))))
     return z, rep
+
+
+class Model:
+    """Learned contraction-order scorer (see include/tn.h)."""
+
+    def __init__(self, hidden: int = 128, layers: int = 4):
+        h = C.c_void_p()
+        check(lib().tn_model_create(int(hidden), int(layers), C.byref(h)))
+        self.h = h
+        self.hidden, self.layers = hidden, layers
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().tn_model_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    @property
+    def n_params(self) -> int:
+        n = C.c_int64()
+        check(lib().tn_model_n_params(self.h, C.byref(n)))
+        return n.value
+
+    def set_params(self, theta) -> None:
+        t = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        assert t.size == self.n_params
+        check(lib().tn_model_set_params(self.h, t.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def get_params(self) -> np.ndarray:
+        t = np.zeros(self.n_params)
+        check(lib().tn_model_get_params(self.h, t.ctypes.data_as(C.POINTER(C.c_double))))
+        return t
+
+    def loss_grad(self, X, nbrs, label, stream=None):
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+        nc = X.shape[0]
+        ptr = np.zeros(nc + 1, dtype=np.int32)
+        for k, nb in enumerate(nbrs):
+            ptr[k + 1] = ptr[k] + len(nb)
+        idx = np.array([j for nb in nbrs for j in nb] or [0], dtype=np.int32)
+        loss = C.c_double()
+        grad = np.zeros(self.n_params)
+        scores = np.zeros(nc)
+        check(lib().tn_model_loss_grad(self.h, nc, X.ctypes.data_as(C.POINTER(C.c_double)),
+                                       ptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                       idx.ctypes.data_as(C.POINTER(C.c_int32)), int(label), C.byref(loss),
+                                       grad.ctypes.data_as(C.POINTER(C.c_double)),
+                                       scores.ctypes.data_as(C.POINTER(C.c_double)),
+                                       C.c_void_p(_stream_ptr(stream))))
+        return loss.value, grad, scores
+
+    def add_teacher(self, net: Network, pairs, stride: int = 1, open_mask=None) -> None:
+        flat = (C.c_int32 * (2 * len(pairs)))(*[int(x) for p in pairs for x in p])
+        om = None if open_mask is None else np.ascontiguousarray(np.asarray(open_mask, dtype=np.int8))
+        check(lib().tn_model_add_teacher(self.h, net.h, None if om is None else om.ctypes.data_as(C.POINTER(C.c_int8)),
+                                         flat, len(pairs), int(stride)))
+
+    def train(self, epochs: int, batch: int = 16, lr: float = 1e-3, seed: int = 0, stream=None):
+        lf, ll = C.c_double(), C.c_double()
+        check(lib().tn_model_train(self.h, int(epochs), int(batch), float(lr), int(seed), C.byref(lf),
+                                   C.byref(ll), C.c_void_p(_stream_ptr(stream))))
+        return lf.value, ll.value
+
+
+def tn_model_state_features(net: Network, pairs, n_prefix: int, open_mask=None):
+    """(candidates, X, neighbour lists) of the state after n_prefix steps."""
+    flat = (C.c_int32 * max(2 * len(pairs), 1))(*[int(x) for p in pairs for x in p])
+    om = None if open_mask is None else np.ascontiguousarray(np.asarray(open_mask, dtype=np.int8))
+    omp = None if om is None else om.ctypes.data_as(C.POINTER(C.c_int8))
+    nc, nn = C.c_int32(), C.c_int32()
+    check(lib().tn_model_state_features(net.h, omp, flat, int(n_prefix), C.byref(nc), C.byref(nn),
+                                        None, None, None, None))
+    cand = np.zeros(2 * nc.value, dtype=np.int32)
+    X = np.zeros((nc.value, 16))
+    ptr = np.zeros(nc.value + 1, dtype=np.int32)
+    idx = np.zeros(max(nn.value, 1), dtype=np.int32)
+    check(lib().tn_model_state_features(net.h, omp, flat, int(n_prefix), C.byref(nc), C.byref(nn),
+                                        cand.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        X.ctypes.data_as(C.POINTER(C.c_double)),
+                                        ptr.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        idx.ctypes.data_as(C.POINTER(C.c_int32))))
+    nbrs = [list(idx[ptr[k]:ptr[k + 1]]) for k in range(nc.value)]
+    return [tuple(cand[2 * k:2 * k + 2]) for k in range(nc.value)], X, nbrs
+
+
+def tn_find_path_learned(net: Network, model: Model, mem_budget_bytes: float = 0.0, open_mask=None) -> Path:
+    o, _keep = _path_opts(net.n_qubits, "learned", 0, 0, 1.0, mem_budget_bytes, open_mask)
+    o.model = model.h
+    h = C.c_void_p()
+    cost = TnPathCost()
+    check(lib().tn_find_path(net.h, C.byref(o), C.byref(h), C.byref(cost)))
+    return Path(h.value, cost)

@@ -107,6 +107,15 @@ SIGNATURES = {
     "tn_mps_amplitudes": (I32, [P, PI8, I64, PD, P]),
     "tn_run_trajectories": (I32, [C.POINTER(C.POINTER(TnCircuit)), I32, I32, PD, I64, PD,
                                   C.POINTER(TnReport), P]),
+    "tn_model_create": (I32, [I32, I32, PP]),
+    "tn_model_destroy": (I32, [P]),
+    "tn_model_n_params": (I32, [P, C.POINTER(C.c_int64)]),
+    "tn_model_set_params": (I32, [P, PD]),
+    "tn_model_get_params": (I32, [P, PD]),
+    "tn_model_state_features": (I32, [P, PI8, PI32, I32, PI32, PI32, PI32, PD, PI32, PI32]),
+    "tn_model_loss_grad": (I32, [P, I32, PD, PI32, PI32, I32, PD, PD, PD, P]),
+    "tn_model_add_teacher": (I32, [P, P, PI8, PI32, I32, I32]),
+    "tn_model_train": (I32, [P, I32, I32, D, U64, PD, PD, P]),
 }
 
 _lib = None

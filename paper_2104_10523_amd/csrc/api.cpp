@@ -58,50 +58,9 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 using namespace tn;
 
-struct tn_network {
-  Network net;
-  std::mutex mu;
-  std::map<int, float2*> dev_full;  // per device: all leaves, complex64
-  ~tn_network() {
-    for (auto& kv : dev_full) {
-      int cur = 0;
-      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
-        (void)hipFree(kv.second);
-        (void)hipSetDevice(cur);
-      }
-    }
-  }
-};
-
-struct tn_path {
-  std::vector<std::pair<int, int>> pairs;
-  std::vector<int> sliced;
-  std::vector<char> open_q;
-  tn_path_cost cost;
-  std::mutex mu;
-  std::map<int, std::shared_ptr<AmpPlan>> plans;  // by precision
-};
+#include "handles.hpp"
 
 namespace {
-
-PathProblem make_problem(const Network& net, const std::vector<char>& open_q) {
-  PathProblem pr;
-  pr.ext.assign(net.n_labels, 2.0);
-  pr.open.assign(net.n_labels, 0);
-  std::vector<char> proj(net.n_labels, 0);
-  for (int q = 0; q < net.n_qubits; ++q) {
-    if (open_q[q]) pr.open[net.out_label[q]] = 1;
-    else proj[net.out_label[q]] = 1;
-  }
-  for (const auto& t : net.tensors) {
-    std::vector<int> s;
-    for (int l : t.labels)
-      if (!proj[l]) s.push_back(l);
-    std::sort(s.begin(), s.end());
-    pr.leaves.push_back(s);
-  }
-  return pr;
-}
 
 std::vector<char> read_open(const Network& net, const int8_t* mask) {
   std::vector<char> o(net.n_qubits, 0);
@@ -279,7 +238,10 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
       pairs = random_greedy_path(pr, o->seed, o->trials, o->temperature);
     } else {
       TN_REQUIRE(o->model != nullptr, TN_ERR_STATE, "learned path needs a model");
-      throw Error(TN_ERR_UNSUPPORTED, "learned path search is not available");
+      int used = TN_PATH_GREEDY;
+      pairs = learned_path_with_fallback(o->model, pr, &used);
+      *out = finish_path(n->net, o, std::move(pairs), used, cost);
+      return;
     }
     *out = finish_path(n->net, o, std::move(pairs), algo, cost);
   });

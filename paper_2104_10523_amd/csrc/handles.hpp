@@ -1,0 +1,43 @@
+// Opaque handle types of the C ABI, shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "network.hpp"
+#include "plan.hpp"
+
+struct tn_network {
+  tn::Network net;
+  std::mutex mu;
+  std::map<int, float2*> dev_full;  // per device: all leaves, complex64
+  ~tn_network() {
+    for (auto& kv : dev_full) {
+      int cur = 0;
+      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
+        (void)hipFree(kv.second);
+        (void)hipSetDevice(cur);
+      }
+    }
+  }
+};
+
+struct tn_path {
+  std::vector<std::pair<int, int>> pairs;
+  std::vector<int> sliced;
+  std::vector<char> open_q;
+  tn_path_cost cost;
+  std::mutex mu;
+  std::map<int, std::shared_ptr<tn::AmpPlan>> plans;  // by precision
+};
+
+
+namespace tn {
+// Learned path with greedy fallback (defined with the scorer).
+std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* m, const PathProblem& pr,
+                                                            int* algo_used);
+}  // namespace tn

@@ -553,7 +553,7 @@ struct PackedArgs {
 };
 
 template <int BM, int BN, int BK, int WGM, int WGN, int NP>
-__global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
+__global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
                                                           const uint32_t* __restrict__ Bp,
                                                           float2* __restrict__ C, PackedArgs P) {
   constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -565,7 +565,8 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __rest
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
   constexpr int KQ = BK / 4;                        // uint4 per row per plane
   constexpr int A_Q = NP * BM * KQ, B_Q = NP * BN * KQ;
-  constexpr int A_PER = (A_Q + 255) / 256, B_PER = (B_Q + 255) / 256;
+  constexpr int NT = WGM * WGN * 64;
+  constexpr int A_PER = (A_Q + NT - 1) / NT, B_PER = (B_Q + NT - 1) / NT;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __rest
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < A_PER; ++i) {
-      const int q = tid + 256 * i;
+      const int q = tid + NT * i;
       const int p = q / (BM * KQ), rem = q % (BM * KQ);
       const int r = rem / KQ, c = rem % KQ;
       const int64_t m = m0 + r, k = k0 + 4 * c;
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __rest
     }
 #pragma unroll
     for (int i = 0; i < B_PER; ++i) {
-      const int q = tid + 256 * i;
+      const int q = tid + NT * i;
       const int p = q / (BN * KQ), rem = q % (BN * KQ);
       const int r = rem / KQ, c = rem % KQ;
       const int64_t n = n0 + r, k = k0 + 4 * c;
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __rest
     uint32_t* Bs = As + A_WORDS;
 #pragma unroll
     for (int i = 0; i < A_PER; ++i) {
-      const int q = tid + 256 * i;
+      const int q = tid + NT * i;
       if (q >= A_Q) break;
       const int p = q / (BM * KQ), rem = q % (BM * KQ);
       const int r = rem / KQ, c = rem % KQ;
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(const uint32_t* __rest
     }
 #pragma unroll
     for (int i = 0; i < B_PER; ++i) {
-      const int q = tid + 256 * i;
+      const int q = tid + NT * i;
       if (q >= B_Q) break;
       const int p = q / (BN * KQ), rem = q % (BN * KQ);
       const int r = rem / KQ, c = rem % KQ;
@@ -766,7 +767,8 @@ PackedCfg pick_packed(const GemmDesc& g) {
   const int bk = g.precision == TN_PREC_BF16X6 ? 16 : 32;
   if (g.N <= 16) return {256, 16, bk};
   if (g.N <= 32) return {128, 32, bk};
-  if (g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22)) return {256, 128, 16};
+  if (g.precision == TN_PREC_BF16X3 && g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22))
+    return {256, 128, 16};
   return {128, 64, bk};
 }
 }  // namespace
@@ -776,6 +778,7 @@ static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, c
                               int64_t batch, hipStream_t s) {
   constexpr int LDK = BK + 4;
   constexpr size_t lds = size_t(2) * NP * (BM + BN) * LDK * sizeof(uint32_t);
+  static_assert(lds <= 160 * 1024, "LDS tile exceeds the 160 KB of a CU");
   static bool attr_set = false;
   if (!attr_set) {
     TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP>),
@@ -783,7 +786,7 @@ static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, c
     attr_set = true;
   }
   dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
-  gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, 256, lds, s>>>(A, B, C, P);
+  gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
 }
 
 template <int NP, int BK>
@@ -791,7 +794,7 @@ static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, co
                              int64_t batch, int bn, hipStream_t s) {
   if (bn == 16) launch_packed_cfg<256, 16, BK, 4, 1, NP>(A, B, C, P, batch, s);
   else if (bn == 32) launch_packed_cfg<128, 32, BK, 4, 1, NP>(A, B, C, P, batch, s);
-  else if (bn == 128) launch_packed_cfg<256, 128, 16, 2, 2, NP>(A, B, C, P, batch, s);
+  else if (bn == 128 && NP == 2) launch_packed_cfg<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s);
   else launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s);
 }
 

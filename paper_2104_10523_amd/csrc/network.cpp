@@ -101,92 +101,105 @@ double splitmix64_uniform(uint64_t* s) {
   return double(splitmix64_next(s) >> 11) * (1.0 / 9007199254740992.0);
 }
 
-namespace {
-
 using Set = std::vector<int>;  // sorted labels
 
-Set set_union(const Set& a, const Set& b) {
+std::vector<int> union_of(const Set& a, const Set& b) {
   Set r;
   r.reserve(a.size() + b.size());
   std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(r));
   return r;
 }
 
-double size_of(const Set& s, const std::vector<double>& ext) {
+double size_of_labels(const Set& s, const std::vector<double>& ext) {
   double v = 1.0;
   for (int l : s) v = v * ext[l];
   return v;
 }
 
-struct State {
-  const PathProblem& pr;
-  std::vector<Set> sets;     // by SSA id; empty + !alive when consumed
-  std::vector<char> alive;
-  std::vector<int> count;
-  int n_alive = 0;
-
-  State(const PathProblem& p, const std::vector<int>& sliced) : pr(p), count(p.ext.size(), 0) {
-    std::vector<char> cut(p.ext.size(), 0);
-    for (int l : sliced) cut[l] = 1;
-    for (const Set& s : p.leaves) {
-      Set t;
-      for (int l : s)
-        if (!cut[l]) t.push_back(l);
-      for (int l : t) count[l]++;
-      sets.push_back(std::move(t));
-      alive.push_back(1);
-      n_alive++;
-    }
-  }
-
-  Set result(int i, int j) const {
-    const Set &a = sets[i], &b = sets[j];
-    Set u = set_union(a, b), c;
-    for (int l : u) {
-      const int in_a = std::binary_search(a.begin(), a.end(), l);
-      const int in_b = std::binary_search(b.begin(), b.end(), l);
-      if (pr.open[l] || count[l] - in_a - in_b > 0) c.push_back(l);
-    }
-    return c;
-  }
-
-  int merge(int i, int j) {
-    Set c = result(i, j);
-    for (int l : sets[i]) count[l]--;
-    for (int l : sets[j]) count[l]--;
-    for (int l : c) count[l]++;
-    sets[i].clear();
-    sets[j].clear();
-    alive[i] = alive[j] = 0;
-    sets.push_back(std::move(c));
-    alive.push_back(1);
-    n_alive--;
-    return int(sets.size()) - 1;
-  }
-
-  std::vector<std::pair<int, int>> candidates() const {
-    std::vector<std::vector<int>> by_label(pr.ext.size());
-    for (size_t i = 0; i < sets.size(); ++i)
-      if (alive[i])
-        for (int l : sets[i]) by_label[l].push_back(int(i));
-    std::vector<std::pair<int, int>> pairs;
-    for (const auto& ids : by_label)
-      for (size_t x = 0; x < ids.size(); ++x)
-        for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
-    if (pairs.empty()) {
-      std::vector<int> ids;
-      for (size_t i = 0; i < sets.size(); ++i)
-        if (alive[i]) ids.push_back(int(i));
-      for (size_t x = 0; x < ids.size(); ++x)
-        for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
-    }
-    std::sort(pairs.begin(), pairs.end());
-    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-    return pairs;
-  }
-};
-
+namespace {
+inline Set set_union(const Set& a, const Set& b) { return union_of(a, b); }
+inline double size_of(const Set& s, const std::vector<double>& ext) { return size_of_labels(s, ext); }
+using State = PathState;
 }  // namespace
+
+PathState::PathState(const PathProblem& p, const std::vector<int>& sliced) : pr(p), count(p.ext.size(), 0) {
+  std::vector<char> cut(p.ext.size(), 0);
+  for (int l : sliced) cut[l] = 1;
+  for (const Set& s : p.leaves) {
+    Set t;
+    for (int l : s)
+      if (!cut[l]) t.push_back(l);
+    for (int l : t) count[l]++;
+    sets.push_back(std::move(t));
+    alive.push_back(1);
+    n_alive++;
+  }
+}
+
+Set PathState::result(int i, int j) const {
+  const Set &a = sets[i], &b = sets[j];
+  Set u = set_union(a, b), c;
+  for (int l : u) {
+    const int in_a = std::binary_search(a.begin(), a.end(), l);
+    const int in_b = std::binary_search(b.begin(), b.end(), l);
+    if (pr.open[l] || count[l] - in_a - in_b > 0) c.push_back(l);
+  }
+  return c;
+}
+
+int PathState::merge(int i, int j) {
+  Set c = result(i, j);
+  for (int l : sets[i]) count[l]--;
+  for (int l : sets[j]) count[l]--;
+  for (int l : c) count[l]++;
+  sets[i].clear();
+  sets[j].clear();
+  alive[i] = alive[j] = 0;
+  sets.push_back(std::move(c));
+  alive.push_back(1);
+  n_alive--;
+  return int(sets.size()) - 1;
+}
+
+std::vector<std::pair<int, int>> PathState::candidates() const {
+  std::vector<std::vector<int>> by_label(pr.ext.size());
+  for (size_t i = 0; i < sets.size(); ++i)
+    if (alive[i])
+      for (int l : sets[i]) by_label[l].push_back(int(i));
+  std::vector<std::pair<int, int>> pairs;
+  for (const auto& ids : by_label)
+    for (size_t x = 0; x < ids.size(); ++x)
+      for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
+  if (pairs.empty()) {
+    std::vector<int> ids;
+    for (size_t i = 0; i < sets.size(); ++i)
+      if (alive[i]) ids.push_back(int(i));
+    for (size_t x = 0; x < ids.size(); ++x)
+      for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
+  }
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  return pairs;
+}
+
+PathProblem make_problem(const Network& net, const std::vector<char>& open_q) {
+  PathProblem pr;
+  pr.ext.assign(net.n_labels, 2.0);
+  pr.open.assign(net.n_labels, 0);
+  std::vector<char> proj(net.n_labels, 0);
+  for (int q = 0; q < net.n_qubits; ++q) {
+    if (open_q[q]) pr.open[net.out_label[q]] = 1;
+    else proj[net.out_label[q]] = 1;
+  }
+  for (const auto& t : net.tensors) {
+    std::vector<int> s;
+    for (int l : t.labels)
+      if (!proj[l]) s.push_back(l);
+    std::sort(s.begin(), s.end());
+    pr.leaves.push_back(s);
+  }
+  return pr;
+}
 
 std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng,
                                              double temperature) {

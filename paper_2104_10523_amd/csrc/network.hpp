@@ -48,6 +48,25 @@ struct PathProblem {
   std::vector<char> open;      // per label: 1 = open output
 };
 
+// Live tensors of a path search: label sets by SSA id, label reference
+// counts, and the candidate pairs of the next step.
+struct PathState {
+  const PathProblem& pr;
+  std::vector<std::vector<int>> sets;   // sorted labels; cleared when consumed
+  std::vector<char> alive;
+  std::vector<int> count;
+  int n_alive = 0;
+  PathState(const PathProblem& p, const std::vector<int>& sliced);
+  std::vector<int> result(int i, int j) const;
+  int merge(int i, int j);
+  std::vector<std::pair<int, int>> candidates() const;
+};
+
+double size_of_labels(const std::vector<int>& s, const std::vector<double>& ext);
+std::vector<int> union_of(const std::vector<int>& a, const std::vector<int>& b);
+// Path problem of a network: projected output labels removed, open ones kept.
+PathProblem make_problem(const Network& net, const std::vector<char>& open_q);
+
 std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng_state,
                                              double temperature);
 std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,

@@ -177,3 +177,24 @@ def test_custom_gates_match_named():
     b = tn.tn_build_network(n, ops_custom)
     for i in range(a.info().n_tensors):
         assert np.abs(a.tensor(i)[0] - b.tensor(i)[0]).max() <= 1e-15
+
+
+def test_scorer_features_match_oracle():
+    """The native featurizer of the learned path search equals the oracle's
+    (O7) at several states along a path."""
+    from oracle import gnn
+    from oracle.paths import _State
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    path = greedy_path(leaves, ext, opened)
+    st = _State(leaves, opened, ())
+    for t, step in enumerate(path[:-1]):
+        if t % 5 == 0:
+            cand, X, nbrs = tn.tn_model_state_features(lnet, path, t)
+            ocand, oX, onbrs = gnn.candidates_and_features(st, ext, len(leaves))
+            assert cand == ocand
+            assert np.abs(X - oX).max() <= 1e-15
+            assert [list(map(int, a)) for a in nbrs] == onbrs
+        st.merge(*step)

@@ -22,4 +22,5 @@ from .data import (  # noqa: F401
     random_bitstrings,
     random_complex,
     trajectory_uniforms,
+    scorer_init,
 )

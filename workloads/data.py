@@ -31,3 +31,19 @@ def trajectory_uniforms(n_traj: int, n_events: int, seed: int) -> np.ndarray:
     """
     rng = np.random.default_rng(seed)
     return rng.random(size=(n_traj, max(n_events, 1)))
+
+
+def scorer_init(n_params_by_shape, seed: int) -> np.ndarray:
+    """Initial parameters of the contraction-order scorer: each weight matrix
+    (fan_in, fan_out) drawn N(0, 2 / fan_in), biases zero; flattened in the
+    given order.  ``n_params_by_shape`` is a list of (name, shape)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shp in n_params_by_shape:
+        if len(shp) == 2:
+            out.append(rng.standard_normal(shp).reshape(-1) * np.sqrt(2.0 / shp[0]))
+        elif name == "wo":
+            out.append(rng.standard_normal(shp) * np.sqrt(1.0 / shp[0]))
+        else:
+            out.append(np.zeros(shp))
+    return np.concatenate(out).astype(np.float64)
