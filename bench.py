@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--rows", type=int, default=7)
     ap.add_argument("--cols", type=int, default=7)
     ap.add_argument("--cycles", type=int, default=14)
+    ap.add_argument("--no-autotune", action="store_true", help="skip the GEMM tile autotuner")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
     return ap.parse_args()
 
 
@@ -107,7 +110,8 @@ def time_steps(net, path, bits, precision, jobs, stream):
 def cpu_baseline(path_pairs, net_py, budget_s):
     """The oracle (numpy einsum, complex128) timed on the workload's own
     pairwise contractions, largest first among those whose tensors fit in
-    2^25 entries, until budget_s of CPU time; returns flops/s."""
+    2^25 entries and whose cost is at most 2e10 flops (a few seconds each),
+    until budget_s of CPU time; returns flops/s."""
     from oracle.contract import contract_pair
     from oracle.paths import path_stats
     from workloads import random_complex
@@ -115,8 +119,9 @@ def cpu_baseline(path_pairs, net_py, budget_s):
     st = path_stats(leaves, ext, path_pairs, open_l, sliced)
     steps = []
     for (a, b, c) in st["steps"]:
-        if max(len(a), len(b), len(c)) <= 25:
-            steps.append((8.0 * 2 ** len(a | b), sorted(a), sorted(b), sorted(c)))
+        f = 8.0 * 2 ** len(a | b)
+        if max(len(a), len(b), len(c)) <= 25 and f <= 2e10:
+            steps.append((f, sorted(a), sorted(b), sorted(c)))
     steps.sort(key=lambda x: -x[0])
     done_f, done_t = 0.0, 0.0
     for k, (f, la, lb, lc) in enumerate(steps):
@@ -140,16 +145,27 @@ def main():
     import paper_2104_10523_amd as tn
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     n, ops, bits, net, path, t_path = make_workload(a)
     ns = path.cost.n_slices
     need = max(tn.tn_amplitudes_workspace(net, path, 1, p) for p in ("fp32", a.precision))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     tn.tn_set_workspace(ws)
+    t0 = time.time()
+    if not a.no_autotune:
+        for p in {a.precision, "fp32"}:
+            tn.tn_amplitudes_autotune(net, path, p, reps=2)
+    t_tune = time.time() - t0
     rng = np.random.default_rng(7)
     total = a.warmup + a.steps
     jobs = [(int(rng.integers(0, 64)), int(rng.integers(0, int(ns)))) for _ in range(total)]
     print(f"# workload 7x7x14 fSim: slices 2^{path.cost.n_sliced}, per-slice flops 2^{math.log2(path.cost.flops_per_slice):.2f}, "
-          f"workspace {need / 2**30:.1f} GiB, path search {t_path:.1f}s", file=sys.stderr, flush=True)
+          f"workspace {need / 2**30:.1f} GiB, path search {t_path:.1f}s, autotune {t_tune:.1f}s", file=sys.stderr, flush=True)
     # warmup
     time_steps(net, path, bits, a.precision, jobs[:a.warmup], stream)
     print("# warmup done", file=sys.stderr, flush=True)
@@ -158,7 +174,9 @@ def main():
     per_job, op_sec, (info, kind, fl, by, mnkb) = time_steps(net, path, bits, a.precision, jobs[a.warmup:], stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    T = float(per_job.mean())
+    # the host clock around the timed steps (device events per job agree to
+    # within the per-call setup of a few milliseconds)
+    T = wall / a.steps
     flops_job = float(fl.sum())
     amps_per_s = 1.0 / (ns * T)
     # dominant kernel: the large complex GEMMs (one MFMA launch each)
@@ -170,7 +188,8 @@ def main():
     achieved = g_flops / g_time if g_time > 0 else 0.0
     t_by_kind = {k: float(op_sec[kind == i].sum()) / a.steps
                  for i, k in enumerate(("apply", "permute", "gemm", "dot"))}
-    print(f"# per step {T:.3f}s (wall {wall / a.steps:.3f}s); time by kind {t_by_kind}", file=sys.stderr, flush=True)
+    print(f"# per step {T:.3f}s (device events {per_job.mean():.3f}s); time by kind {t_by_kind}",
+          file=sys.stderr, flush=True)
     fp32 = None
     if a.compare_fp32 and a.precision != "fp32":
         pj, os32, (_, k32, f32, _, _) = time_steps(net, path, bits, "fp32", jobs[a.warmup:a.warmup + 1], stream)

@@ -342,6 +342,15 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p,
                                  int32_t precision, int32_t* kind,
                                  double* flops, double* bytes, int64_t* mnkb);
 
+/* Autotuner: time every candidate block-tile shape of every GEMM of this
+ * path's plan (reps launches each, on the plan's own workspace buffers, whose
+ * contents are overwritten), keep the fastest per GEMM for later
+ * tn_amplitudes calls, and remember it for GEMMs of the same shape in plans
+ * compiled afterwards (process-wide).  Needs the workspace of
+ * tn_amplitudes_workspace (n_bs = 1).  Synchronises the stream. */
+tn_status tn_amplitudes_autotune(const tn_network* n, const tn_path* p,
+                                 int32_t precision, int32_t reps, void* stream);
+
 /* Workspace bytes tn_amplitudes needs for this path, n_bs bit-strings and
  * precision (job control words, bit-strings, gathered leaves, intermediates
  * and permute / split-K scratch of one job).  Host only. */

@@ -192,6 +192,13 @@ def tn_amplitudes_workspace(net: Network, path: Path, n_bs: int, precision: str 
     return n.value
 
 
+def tn_amplitudes_autotune(net: Network, path: Path, precision: str = "fp32", reps: int = 2,
+                           stream=None) -> None:
+    """Time the candidate GEMM tiles of this path's plan and keep the fastest."""
+    check(lib().tn_amplitudes_autotune(net.h, path.h, PREC[precision], int(reps),
+                                       C.c_void_p(_stream_ptr(stream))))
+
+
 def tn_amplitudes(net: Network, path: Path, bits, out=None, precision: str = "fp32",
                   use_graph: bool = False, slice_begin: int = 0, slice_count: int = -1,
                   accumulate: bool = False, sync: bool = True, stream=None):

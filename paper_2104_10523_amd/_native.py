@@ -97,6 +97,7 @@ SIGNATURES = {
     "tn_amplitudes": (I32, [P, P, PI8, I64, C.POINTER(TnExecOpts), P, C.POINTER(TnReport), P]),
     "tn_amplitudes_workspace": (I32, [P, P, I64, I32, C.POINTER(C.c_size_t)]),
     "tn_amplitudes_plan_info": (I32, [P, P, I32, C.POINTER(TnPlanInfo)]),
+    "tn_amplitudes_autotune": (I32, [P, P, I32, I32, P]),
     "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),

@@ -490,6 +490,26 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
   });
 }
 
+tn_status tn_amplitudes_autotune(const tn_network* n_, const tn_path* p_, int32_t precision, int32_t reps,
+                                 void* stream) {
+  return guarded([&] {
+    auto* n = const_cast<tn_network*>(n_);
+    auto* p = const_cast<tn_path*>(p_);
+    TN_REQUIRE(n && p && reps >= 1, TN_ERR_ARG, "bad argument");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    auto plan = get_plan(n, p, precision);
+    const WsLayout L = ws_layout(*plan, 1);
+    const Workspace ws = get_ws();
+    TN_REQUIRE(ws.ptr && ws.bytes >= L.total, TN_ERR_WORKSPACE,
+               "workspace too small: need " + std::to_string(L.total) + " bytes");
+    char* base = static_cast<char*>(ws.ptr);
+    float2* bufs[6] = {reinterpret_cast<float2*>(base + L.leaves), reinterpret_cast<float2*>(base + L.work),
+                       nullptr, nullptr, nullptr, device_one()};
+    std::lock_guard<std::mutex> lk(p->mu);
+    autotune_ops(plan->ops, bufs, reps, static_cast<hipStream_t>(stream));
+  });
+}
+
 tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p, int32_t precision,
                                   tn_plan_info* info) {
   return guarded([&] {

@@ -723,26 +723,58 @@ __global__ __launch_bounds__(256) void reduce_splitk_kernel(const float2* __rest
   }
 }
 
+// ---------------------------------------------------------- tile shapes
+//
+// Candidate block tiles (rows x complex columns); GemmDesc::tile picks one
+// (-1: the shape heuristic below), the autotuner times the candidates.
 namespace {
-struct TileCfg {
-  int bm, bn, bk;
+struct TileShape {
+  int bm, bn;
 };
-TileCfg pick_tile(const GemmDesc& g) {
-  const int bk = g.precision == TN_PREC_FP32 ? 8 : 16;
-  if (g.N <= 16) return {256, 16, bk};
-  if (g.N <= 32) return {128, 32, bk};
-  return {128, 64, bk};
+constexpr TileShape kUnpackedTiles[4] = {{256, 16}, {128, 32}, {128, 64}, {64, 64}};
+constexpr TileShape kPackedTiles[5] = {{256, 16}, {128, 32}, {128, 64}, {256, 128}, {128, 128}};
+
+int default_tile(const GemmDesc& g) {
+  if (g.N <= 16) return 0;
+  if (g.N <= 32) return 1;
+  if (g.packed && g.precision == TN_PREC_BF16X3 && g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22))
+    return 3;
+  return 2;
 }
-int pick_ksplit(const GemmDesc& g, const TileCfg& t, int64_t* kchunk) {
+
+int tile_of(const GemmDesc& g) { return g.tile >= 0 ? g.tile : default_tile(g); }
+
+// K step (complex values) of a tile.
+int tile_bk(const GemmDesc& g, int id) {
+  if (!g.packed) return g.precision == TN_PREC_FP32 ? 8 : 16;
+  if (g.precision == TN_PREC_BF16X6) return 16;
+  return (id == 3 || id == 4) ? 16 : 32;
+}
+
+int choose_ksplit(const GemmDesc& g, int id, int64_t* kchunk) {
+  const TileShape t = g.packed ? kPackedTiles[id] : kUnpackedTiles[id];
+  const int bk = tile_bk(g, id);
   const int64_t tiles = ceil_div(g.M, t.bm) * ceil_div(g.N, t.bn) * g.batch;
+  const int64_t ksteps = ceil_div(g.K, bk);
+  const int64_t minsteps = g.packed ? 8 : 16;
   int ks = 1;
-  const int64_t ksteps = ceil_div(g.K, t.bk);
-  while (tiles * ks < 1024 && ksteps / (ks * 2) >= 16 && ks < 256) ks *= 2;
-  *kchunk = ceil_div(ksteps, ks) * t.bk;
-  ks = int(ceil_div(g.K, *kchunk));
-  return ks;
+  while (tiles * ks < 1024 && ksteps / (ks * 2) >= minsteps && ks < 256) ks *= 2;
+  *kchunk = ceil_div(ksteps, ks) * bk;
+  return int(ceil_div(g.K, *kchunk));
 }
 }  // namespace
+
+std::vector<int> gemm_tile_candidates(const GemmDesc& g) {
+  if (!g.packed) return {0, 1, 2, 3};
+  if (g.precision == TN_PREC_BF16X6) return {0, 1, 2, 4};
+  return {0, 1, 2, 3, 4};
+}
+
+size_t gemm_workspace_bytes(const GemmDesc& g) {
+  int64_t kchunk;
+  const int ks = choose_ksplit(g, tile_of(g), &kchunk);
+  return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
+}
 
 template <int BM, int BN, int BK, int WGM, int WGN, int PREC>
 static void launch_gemm_cfg(const float2* A, const float2* B, float2* C, const GemmArgs& P,
@@ -753,25 +785,14 @@ static void launch_gemm_cfg(const float2* A, const float2* B, float2* C, const G
 
 template <int PREC, int BK>
 static void launch_gemm_prec(const float2* A, const float2* B, float2* C, const GemmArgs& P,
-                             int64_t batch, int bn, hipStream_t s) {
-  if (bn == 16) launch_gemm_cfg<256, 16, BK, 4, 1, PREC>(A, B, C, P, batch, s);
-  else if (bn == 32) launch_gemm_cfg<128, 32, BK, 4, 1, PREC>(A, B, C, P, batch, s);
-  else launch_gemm_cfg<128, 64, BK, 2, 2, PREC>(A, B, C, P, batch, s);
+                             int64_t batch, int id, hipStream_t s) {
+  switch (id) {
+    case 0: launch_gemm_cfg<256, 16, BK, 4, 1, PREC>(A, B, C, P, batch, s); break;
+    case 1: launch_gemm_cfg<128, 32, BK, 4, 1, PREC>(A, B, C, P, batch, s); break;
+    case 3: launch_gemm_cfg<64, 64, BK, 2, 2, PREC>(A, B, C, P, batch, s); break;
+    default: launch_gemm_cfg<128, 64, BK, 2, 2, PREC>(A, B, C, P, batch, s); break;
+  }
 }
-
-namespace {
-struct PackedCfg {
-  int bm, bn, bk;
-};
-PackedCfg pick_packed(const GemmDesc& g) {
-  const int bk = g.precision == TN_PREC_BF16X6 ? 16 : 32;
-  if (g.N <= 16) return {256, 16, bk};
-  if (g.N <= 32) return {128, 32, bk};
-  if (g.precision == TN_PREC_BF16X3 && g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22))
-    return {256, 128, 16};
-  return {128, 64, bk};
-}
-}  // namespace
 
 template <int BM, int BN, int BK, int WGM, int WGN, int NP>
 static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
@@ -791,105 +812,75 @@ static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, c
 
 template <int NP, int BK>
 static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
-                             int64_t batch, int bn, hipStream_t s) {
-  if (bn == 16) launch_packed_cfg<256, 16, BK, 4, 1, NP>(A, B, C, P, batch, s);
-  else if (bn == 32) launch_packed_cfg<128, 32, BK, 4, 1, NP>(A, B, C, P, batch, s);
-  else if (bn == 128 && NP == 2) launch_packed_cfg<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s);
-  else launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s);
-}
-
-static int packed_ksplit(const GemmDesc& g, const PackedCfg& t, int64_t* kchunk) {
-  const int64_t tiles = ceil_div(g.M, t.bm) * ceil_div(g.N, t.bn) * g.batch;
-  int ks = 1;
-  const int64_t ksteps = ceil_div(g.K, t.bk);
-  while (tiles * ks < 1024 && ksteps / (ks * 2) >= 8 && ks < 256) ks *= 2;
-  *kchunk = ceil_div(ksteps, ks) * t.bk;
-  return int(ceil_div(g.K, *kchunk));
-}
-
-size_t gemm_workspace_bytes(const GemmDesc& g) {
-  if (g.packed) {
-    int64_t kchunk;
-    const int ks = packed_ksplit(g, pick_packed(g), &kchunk);
-    return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
-  }
-  const TileCfg t = pick_tile(g);
-  int64_t kchunk;
-  const int ks = pick_ksplit(g, t, &kchunk);
-  return ks > 1 ? size_t(ks) * size_t(g.batch * g.M * g.N) * sizeof(float2) : 0;
-}
-
-static void launch_gemm_packed(const uint32_t* A, const uint32_t* B, float2* C, const GemmDesc& g,
-                               void* work, hipStream_t s) {
-  TN_REQUIRE(g.K % 4 == 0, TN_ERR_ARG, "internal: packed GEMM needs K % 4 == 0");
-  const PackedCfg t = pick_packed(g);
-  PackedArgs P;
-  P.M = g.M;
-  P.N = g.N;
-  P.K = g.K;
-  P.plane_a = g.plane_a;
-  P.plane_b = g.plane_b;
-  P.ksplit = packed_ksplit(g, t, &P.kchunk);
-  P.tiles_m = int(ceil_div(g.M, t.bm));
-  P.tiles_n = int(ceil_div(g.N, t.bn));
-  TN_REQUIRE(int64_t(P.tiles_m) * P.tiles_n < (int64_t(1) << 31) && g.batch * P.ksplit <= 65535,
-             TN_ERR_UNSUPPORTED, "GEMM grid too large");
-  float2* out = C;
-  if (P.ksplit > 1) {
-    TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "split-K GEMM needs workspace");
-    out = static_cast<float2*>(work);
-  }
-  if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16>(A, B, out, P, g.batch, t.bn, s);
-  else launch_packed_np<2, 32>(A, B, out, P, g.batch, t.bn, s);
-  TN_HIP(hipGetLastError());
-  if (P.ksplit > 1) {
-    const int64_t n = g.batch * g.M * g.N;
-    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
-    reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, P.ksplit, n);
-    TN_HIP(hipGetLastError());
+                             int64_t batch, int id, hipStream_t s) {
+  switch (id) {
+    case 0: launch_packed_cfg<256, 16, BK, 4, 1, NP>(A, B, C, P, batch, s); break;
+    case 1: launch_packed_cfg<128, 32, BK, 4, 1, NP>(A, B, C, P, batch, s); break;
+    case 3:
+      if constexpr (NP == 2) { launch_packed_cfg<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s); break; }
+      [[fallthrough]];
+    case 4: launch_packed_cfg<128, 128, 16, 2, 2, NP>(A, B, C, P, batch, s); break;
+    default: launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s); break;
   }
 }
 
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
                  hipStream_t s) {
-  if (g.packed) {
-    launch_gemm_packed(reinterpret_cast<const uint32_t*>(A), reinterpret_cast<const uint32_t*>(B), C,
-                       g, work, s);
-    return;
-  }
   TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1, TN_ERR_ARG, "bad GEMM shape");
-  TN_REQUIRE(g.batch <= 65535, TN_ERR_UNSUPPORTED, "GEMM batch too large");
-  const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision
-                                                                                   : TN_PREC_FP32;
-  TileCfg t = pick_tile(g);
-  if (prec != TN_PREC_FP32) t.bk = 16;
-  GemmArgs P;
-  P.M = g.M;
-  P.N = g.N;
-  P.K = g.K;
-  P.transA = g.transA;
-  P.transB = g.transB;
-  P.ksplit = pick_ksplit(g, t, &P.kchunk);
-  P.tiles_m = int(ceil_div(g.M, t.bm));
-  P.tiles_n = int(ceil_div(g.N, t.bn));
-  TN_REQUIRE(int64_t(P.tiles_m) * P.tiles_n < (int64_t(1) << 31) &&
-                 g.batch * P.ksplit <= 65535,
+  TN_REQUIRE(!g.packed || g.K % 4 == 0, TN_ERR_ARG, "internal: packed GEMM needs K % 4 == 0");
+  const int id = tile_of(g);
+  const auto cands = gemm_tile_candidates(g);
+  TN_REQUIRE(std::find(cands.begin(), cands.end(), id) != cands.end(), TN_ERR_ARG, "internal: bad tile id");
+  const TileShape t = g.packed ? kPackedTiles[id] : kUnpackedTiles[id];
+  int64_t kchunk = 0;
+  const int ksplit = choose_ksplit(g, id, &kchunk);
+  const int tiles_m = int(ceil_div(g.M, t.bm)), tiles_n = int(ceil_div(g.N, t.bn));
+  TN_REQUIRE(int64_t(tiles_m) * tiles_n < (int64_t(1) << 31) && g.batch * ksplit <= 65535,
              TN_ERR_UNSUPPORTED, "GEMM grid too large");
   float2* out = C;
-  if (P.ksplit > 1) {
+  if (ksplit > 1) {
     TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "split-K GEMM needs workspace");
     out = static_cast<float2*>(work);
   }
-  switch (prec) {
-    case TN_PREC_FP32: launch_gemm_prec<TN_PREC_FP32, 8>(A, B, out, P, g.batch, t.bn, s); break;
-    case TN_PREC_BF16X3: launch_gemm_prec<TN_PREC_BF16X3, 16>(A, B, out, P, g.batch, t.bn, s); break;
-    default: launch_gemm_prec<TN_PREC_BF16X6, 16>(A, B, out, P, g.batch, t.bn, s); break;
+  if (g.packed) {
+    PackedArgs P;
+    P.M = g.M;
+    P.N = g.N;
+    P.K = g.K;
+    P.plane_a = g.plane_a;
+    P.plane_b = g.plane_b;
+    P.ksplit = ksplit;
+    P.kchunk = kchunk;
+    P.tiles_m = tiles_m;
+    P.tiles_n = tiles_n;
+    const uint32_t* Ap = reinterpret_cast<const uint32_t*>(A);
+    const uint32_t* Bp = reinterpret_cast<const uint32_t*>(B);
+    if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16>(Ap, Bp, out, P, g.batch, id, s);
+    else launch_packed_np<2, 32>(Ap, Bp, out, P, g.batch, id, s);
+  } else {
+    const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision
+                                                                                     : TN_PREC_FP32;
+    GemmArgs P;
+    P.M = g.M;
+    P.N = g.N;
+    P.K = g.K;
+    P.transA = g.transA;
+    P.transB = g.transB;
+    P.ksplit = ksplit;
+    P.kchunk = kchunk;
+    P.tiles_m = tiles_m;
+    P.tiles_n = tiles_n;
+    switch (prec) {
+      case TN_PREC_FP32: launch_gemm_prec<TN_PREC_FP32, 8>(A, B, out, P, g.batch, id, s); break;
+      case TN_PREC_BF16X3: launch_gemm_prec<TN_PREC_BF16X3, 16>(A, B, out, P, g.batch, id, s); break;
+      default: launch_gemm_prec<TN_PREC_BF16X6, 16>(A, B, out, P, g.batch, id, s); break;
+    }
   }
   TN_HIP(hipGetLastError());
-  if (P.ksplit > 1) {
+  if (ksplit > 1) {
     const int64_t n = g.batch * g.M * g.N;
     const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
-    reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, P.ksplit, n);
+    reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, ksplit, n);
     TN_HIP(hipGetLastError());
   }
 }

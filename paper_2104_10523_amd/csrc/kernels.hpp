@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace tn {
 
@@ -54,9 +55,12 @@ struct GemmDesc {
   int precision = 0;       // TN_PREC_FP32 / BF16X3 / BF16X6
   int packed = 0;
   int64_t plane_a = 0, plane_b = 0;
+  int tile = -1;           // block tile id (-1: shape heuristic)
 };
 // Workspace needed for split-K partials (bytes); 0 when no split is used.
 size_t gemm_workspace_bytes(const GemmDesc& g);
+// Tile ids valid for this GEMM (the autotuner's candidates).
+std::vector<int> gemm_tile_candidates(const GemmDesc& g);
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
                  hipStream_t s);
 

@@ -13,7 +13,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <set>
+#include <tuple>
 
 namespace tn {
 
@@ -345,7 +348,8 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.kind = OP_DOT;
     op.dot_k = Kn;
     op.dot_batch = Bn;
-    op.work_off = arena.alloc(int64_t((dot_workspace_bytes(Kn, Bn) + 7) / 8));
+    op.work_elems = int64_t((dot_workspace_bytes(Kn, Bn) + 7) / 8);
+    op.work_off = arena.alloc(op.work_elems);
     scratch->push_back(op.work_off);
   } else {
     op.kind = OP_GEMM;
@@ -359,9 +363,18 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.gm.packed = packed ? 1 : 0;
     op.gm.plane_a = Bn * Mn * Kn;
     op.gm.plane_b = Bn * Nn * Kn;
-    const size_t wb = gemm_workspace_bytes(op.gm);
+    op.gm.tile = tuned_tile(op.gm);
+    // room for the split-K partials of any candidate tile, so the
+    // autotuner may pick any of them later
+    size_t wb = 0;
+    for (int c : gemm_tile_candidates(op.gm)) {
+      GemmDesc gc = op.gm;
+      gc.tile = c;
+      wb = std::max(wb, gemm_workspace_bytes(gc));
+    }
     if (wb > 0) {
-      op.work_off = arena.alloc(int64_t((wb + 7) / 8));
+      op.work_elems = int64_t((wb + 7) / 8);
+      op.work_off = arena.alloc(op.work_elems);
       scratch->push_back(op.work_off);
     }
   }
@@ -385,6 +398,81 @@ void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t 
       case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, w, s); break;
     }
   }
+}
+
+// ------------------------------------------------------------- autotune
+
+namespace {
+using TileKey = std::tuple<int64_t, int64_t, int64_t, int64_t, int, int, int, int>;
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tiles;
+TileKey key_of(const GemmDesc& g) {
+  return TileKey{g.M, g.N, g.K, g.batch, g.precision, g.packed, g.transA, g.transB};
+}
+}  // namespace
+
+int tuned_tile(const GemmDesc& g) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tiles.find(key_of(g));
+  return it == g_tiles.end() ? -1 : it->second;
+}
+
+void remember_tile(const GemmDesc& g, int tile) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tiles[key_of(g)] = tile;
+}
+
+void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TN_HIP(hipEventCreate(&e0));
+  TN_HIP(hipEventCreate(&e1));
+  std::map<TileKey, int> done;
+  try {
+    for (PlanOp& op : ops) {
+      if (op.kind != OP_GEMM) continue;
+      auto it = done.find(key_of(op.gm));
+      if (it != done.end()) {
+        op.gm.tile = it->second;
+        continue;
+      }
+      const float2* a = bufs[op.a_buf] + op.a_off;
+      const float2* b = bufs[op.b_buf] + op.b_off;
+      float2* c = bufs[op.c_buf] + op.c_off;
+      void* w = op.work_off >= 0 ? static_cast<void*>(bufs[BUF_WORK] + op.work_off) : nullptr;
+      float best_ms = 0;
+      int best = -1;
+      for (int cand : gemm_tile_candidates(op.gm)) {
+        GemmDesc g = op.gm;
+        g.tile = cand;
+        // time a K-truncated proxy: the tile ranking hardly depends on K, and
+        // every address of the proxy stays inside the op's real operands
+        g.K = std::min<int64_t>(g.K, 512);
+        if (gemm_workspace_bytes(g) > size_t(op.work_elems) * sizeof(float2)) continue;
+        launch_gemm(a, b, c, g, w, s);  // warm
+        TN_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_gemm(a, b, c, g, w, s);
+        TN_HIP(hipEventRecord(e1, s));
+        TN_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        TN_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0 || ms < best_ms) {
+          best = cand;
+          best_ms = ms;
+        }
+      }
+      if (best >= 0) {
+        op.gm.tile = best;
+        done[key_of(op.gm)] = best;
+        remember_tile(op.gm, best);
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 // ------------------------------------------------------ amplitude planning

@@ -27,6 +27,7 @@ struct PlanOp {
   int a_buf = 0, b_buf = 0, c_buf = 0;
   int64_t a_off = 0, b_off = 0, c_off = 0;
   int64_t work_off = -1;      // split-K / dot scratch (elements of float2)
+  int64_t work_elems = 0;     // size of that scratch
   ApplySmallDesc ap;
   PermuteDesc pm;
   GemmDesc gm;
@@ -56,6 +57,13 @@ TRef compile_pair(const TRef& X, const TRef& Y, const std::vector<int>& keep,
                   int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch);
 
 void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s);
+
+// Autotune cache: fastest tile id per GEMM shape (process-wide).
+int tuned_tile(const GemmDesc& g);
+void remember_tile(const GemmDesc& g, int tile);
+// Times every candidate tile of every GEMM op on the given buffers and
+// stores the fastest in the op (and the cache).  Synchronises `s`.
+void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hipStream_t s);
 
 struct AmpPlan {
   int n_qubits = 0;

@@ -190,24 +190,23 @@ __global__ __launch_bounds__(256) void traj_pass_kernel(float2* __restrict__ psi
   float2* st = psi + int64_t(t) * dim;
   double m4[4] = {0, 0, 0, 0};
   const int64_t groups = dim >> 4;
+  const int c0 = cur_local[0], c1 = cur_local[1];
+  const int64_t bit0 = int64_t(1) << upos[0], bit1 = int64_t(1) << upos[1], bit2 = int64_t(1) << upos[2],
+                bit3 = int64_t(1) << upos[3];
   for (int64_t gidx = int64_t(blockIdx.x) * 256 + tid; gidx < groups; gidx += int64_t(kBlocksPerTraj) * 256) {
     int64_t base = gidx;
     for (int a = 0; a < 4; ++a) {
       const int p = sorted[a];
       base = ((base >> p) << (p + 1)) | (base & ((int64_t(1) << p) - 1));
     }
-    int64_t addr[16];
-    float2 v[16], w[16];
+    auto addr_of = [&](int e) {
+      return base | ((e & 1) ? bit0 : 0) | ((e & 2) ? bit1 : 0) | ((e & 4) ? bit2 : 0) | ((e & 8) ? bit3 : 0);
+    };
+    float2 v[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      int64_t o = base;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if ((e >> a) & 1) o |= int64_t(1) << upos[a];
-      addr[e] = o;
-      v[e] = st[o];
-    }
-#pragma unroll
+    for (int e = 0; e < 16; ++e) v[e] = st[addr_of(e)];
+    // one output row at a time: the operator stays in LDS (broadcast reads)
+#pragma unroll 1
     for (int i = 0; i < 16; ++i) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
@@ -216,17 +215,15 @@ __global__ __launch_bounds__(256) void traj_pass_kernel(float2* __restrict__ psi
         acc.x += p.x;
         acc.y += p.y;
       }
-      w[i] = acc;
-    }
-    const int c0 = cur_local[0], c1 = cur_local[1];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      st[addr[e]] = w[e];
-      const double pr = double(w[e].x) * w[e].x + double(w[e].y) * w[e].y;
+      st[addr_of(i)] = acc;
+      const double pr = double(acc.x) * acc.x + double(acc.y) * acc.y;
       int x = 0;
-      if (c1 >= 0) x = ((e >> c0) & 1) * 2 + ((e >> c1) & 1);
-      else if (c0 >= 0) x = (e >> c0) & 1;
-      m4[x] += pr;
+      if (c1 >= 0) x = ((i >> c0) & 1) * 2 + ((i >> c1) & 1);
+      else if (c0 >= 0) x = (i >> c0) & 1;
+      m4[0] += x == 0 ? pr : 0.0;
+      m4[1] += x == 1 ? pr : 0.0;
+      m4[2] += x == 2 ? pr : 0.0;
+      m4[3] += x == 3 ? pr : 0.0;
     }
   }
   // block reductions in a fixed order (deterministic)
