@@ -33,6 +33,39 @@ PEAKS = {"bf16x3": 2.5e15, "bf16x6": 2.5e15, "fp32": 157.3e12}
 HBM_PEAK = 8.0e12
 
 
+# tile id -> (BM, BN, BK, WGM, WGN) of the kernels in csrc/kernels.hip
+PACKED_TILES = {2: {0: (256, 16, 32, 4, 1), 1: (128, 32, 32, 4, 1), 2: (128, 64, 32, 2, 2),
+                    3: (256, 128, 16, 4, 2), 4: (128, 128, 16, 2, 2)},
+                3: {0: (256, 16, 16, 4, 1), 1: (128, 32, 16, 4, 1), 2: (128, 64, 16, 2, 2),
+                    4: (128, 128, 16, 2, 2)}}
+UNPACKED_TILES = {0: (256, 16), 1: (128, 32), 2: (128, 64), 3: (64, 64)}
+
+
+def kernel_name(precision, tile, packed):
+    if packed:
+        np_ = 3 if precision == "bf16x6" else 2
+        bm, bn, bk, wm, wn = PACKED_TILES[np_][tile]
+        return f"gemm_packed_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}>"
+    bm, bn = UNPACKED_TILES[tile]
+    bk = 8 if precision == "fp32" else 16
+    wm, wn = (2, 2) if bn >= 64 else (4, 1)
+    return f"gemm_mfma_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {precision}>"
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` on this workload from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    1 GiB copy).  None when no summary covers the kernel or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    src = hashlib.sha256((ROOT / "paper_2104_10523_amd" / "csrc" / "kernels.hip").read_bytes()).hexdigest()
+    for f in sorted((ROOT / "profiles").glob("*__hbm_traffic.txt")):
+        kv = dict(l.split(": ", 1) for l in f.read_text().splitlines() if ": " in l and not l.startswith(" "))
+        if kv.get("kernel") == kernel and kv.get("kernels_hip_sha256") == src:
+            return float(kv["traffic_bytes_per_launch"]), f.name
+    return None, None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,7 +79,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=7)
     ap.add_argument("--cols", type=int, default=7)
     ap.add_argument("--cycles", type=int, default=14)
-    ap.add_argument("--no-autotune", action="store_true", help="skip the GEMM tile autotuner")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the GEMM tile autotuner first (its proxy launches then appear in kernel traces)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
     return ap.parse_args()
@@ -75,9 +109,9 @@ def plan_ops(net, path, precision):
     kind = (C.c_int32 * N)()
     fl = (C.c_double * N)()
     by = (C.c_double * N)()
-    mnkb = (C.c_int64 * (4 * N))()
-    tn._native.check(tn.lib().tn_amplitudes_plan_ops(net.h, path.h, PREC[precision], kind, fl, by, mnkb))
-    return info, np.array(kind), np.array(fl), np.array(by), np.array(mnkb).reshape(N, 4)
+    shape = (C.c_int64 * (6 * N))()
+    tn._native.check(tn.lib().tn_amplitudes_plan_ops(net.h, path.h, PREC[precision], kind, fl, by, shape))
+    return info, np.array(kind), np.array(fl), np.array(by), np.array(shape).reshape(N, 6)
 
 
 def time_steps(net, path, bits, precision, jobs, stream):
@@ -87,9 +121,10 @@ def time_steps(net, path, bits, precision, jobs, stream):
     import torch
     import paper_2104_10523_amd as tn
     from paper_2104_10523_amd._native import TnExecOpts, TnReport, PREC
-    info, kind, fl, by, mnkb = plan_ops(net, path, precision)
+    info, kind, fl, by, shape = plan_ops(net, path, precision)
     op_sec = np.zeros(info.n_ops)
     per_job = []
+    amps = []
     out = torch.zeros((1, 1), dtype=torch.complex128, device="cuda")
     for (b, s) in jobs:
         buf = np.zeros(info.n_ops)
@@ -102,16 +137,17 @@ def time_steps(net, path, bits, precision, jobs, stream):
                                                 C.c_void_p(stream.cuda_stream)))
         per_job.append(rep.seconds)
         op_sec += buf
+        amps.append(complex(out.cpu().numpy()[0, 0]))
         if rep.nonfinite:
             raise RuntimeError("non-finite amplitude")
-    return np.array(per_job), op_sec, (info, kind, fl, by, mnkb)
+    return np.array(per_job), op_sec, (info, kind, fl, by, shape), np.array(amps)
 
 
 def cpu_baseline(path_pairs, net_py, budget_s):
     """The oracle (numpy einsum, complex128) timed on the workload's own
     pairwise contractions, largest first among those whose tensors fit in
     2^25 entries and whose cost is at most 2e10 flops (a few seconds each),
-    until budget_s of CPU time; returns flops/s."""
+    cycling through them until budget_s of CPU time; returns flops/s."""
     from oracle.contract import contract_pair
     from oracle.paths import path_stats
     from workloads import random_complex
@@ -123,16 +159,16 @@ def cpu_baseline(path_pairs, net_py, budget_s):
         if max(len(a), len(b), len(c)) <= 25 and f <= 2e10:
             steps.append((f, sorted(a), sorted(b), sorted(c)))
     steps.sort(key=lambda x: -x[0])
-    done_f, done_t = 0.0, 0.0
-    for k, (f, la, lb, lc) in enumerate(steps):
+    done_f, done_t, k = 0.0, 0.0, 0
+    while done_t < budget_s and steps:
+        f, la, lb, lc = steps[k % len(steps)]
         A = random_complex([2] * len(la), k)
         B = random_complex([2] * len(lb), k + 1)
         t0 = time.perf_counter()
         contract_pair(A, la, B, lb, lc)
         done_t += time.perf_counter() - t0
         done_f += f
-        if done_t >= budget_s:
-            break
+        k += 1
     return done_f / done_t, done_t, done_f
 
 
@@ -157,7 +193,7 @@ def main():
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     tn.tn_set_workspace(ws)
     t0 = time.time()
-    if not a.no_autotune:
+    if a.autotune:
         for p in {a.precision, "fp32"}:
             tn.tn_amplitudes_autotune(net, path, p, reps=2)
     t_tune = time.time() - t0
@@ -167,11 +203,13 @@ def main():
     print(f"# workload 7x7x14 fSim: slices 2^{path.cost.n_sliced}, per-slice flops 2^{math.log2(path.cost.flops_per_slice):.2f}, "
           f"workspace {need / 2**30:.1f} GiB, path search {t_path:.1f}s, autotune {t_tune:.1f}s", file=sys.stderr, flush=True)
     # warmup
-    time_steps(net, path, bits, a.precision, jobs[:a.warmup], stream)
+    if a.warmup:
+        time_steps(net, path, bits, a.precision, jobs[:a.warmup], stream)
     print("# warmup done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    per_job, op_sec, (info, kind, fl, by, mnkb) = time_steps(net, path, bits, a.precision, jobs[a.warmup:], stream)
+    per_job, op_sec, (info, kind, fl, by, shape), amps = time_steps(net, path, bits, a.precision,
+                                                                     jobs[a.warmup:], stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # the host clock around the timed steps (device events per job agree to
@@ -179,12 +217,17 @@ def main():
     T = wall / a.steps
     flops_job = float(fl.sum())
     amps_per_s = 1.0 / (ns * T)
-    # dominant kernel: the large complex GEMMs (one MFMA launch each)
-    big = (kind == 2) & (fl >= 1e12)
-    g_flops = float(fl[big].sum()) * a.steps
-    g_time = float(op_sec[big].sum())
-    g_bytes = float(by[big].sum()) * a.steps
+    # dominant kernel: the GEMM instantiation (tile shape) with the most time
+    names = {}
+    for k in np.nonzero(kind == 2)[0]:
+        names.setdefault(kernel_name(a.precision, int(shape[k, 4]), int(shape[k, 5])), []).append(k)
+    dom = max(names, key=lambda nm: op_sec[names[nm]].sum())
+    sel = np.array(names[dom])
+    g_flops = float(fl[sel].sum()) * a.steps
+    g_time = float(op_sec[sel].sum())
+    g_bytes = float(by[sel].sum()) * a.steps
     peak = PEAKS[a.precision] if a.precision in PEAKS else PEAKS["bf16x3"]
+    traffic, traffic_src = recorded_traffic(dom)
     achieved = g_flops / g_time if g_time > 0 else 0.0
     t_by_kind = {k: float(op_sec[kind == i].sum()) / a.steps
                  for i, k in enumerate(("apply", "permute", "gemm", "dot"))}
@@ -192,12 +235,14 @@ def main():
           file=sys.stderr, flush=True)
     fp32 = None
     if a.compare_fp32 and a.precision != "fp32":
-        pj, os32, (_, k32, f32, _, _) = time_steps(net, path, bits, "fp32", jobs[a.warmup:a.warmup + 1], stream)
-        b32 = (k32 == 2) & (f32 >= 1e12)
+        pj, os32, (_, k32, f32, _, _), a32 = time_steps(net, path, bits, "fp32", jobs[a.warmup:a.warmup + 1],
+                                                         stream)
+        b32 = k32 == 2
         fp32 = {"seconds_per_step": float(pj.mean()),
                 "amplitudes_per_s": 1.0 / (ns * float(pj.mean())),
                 "gemm_tflops": float(f32[b32].sum()) / float(os32[b32].sum()) / 1e12,
-                "speedup_of_split": float(pj.mean()) / T}
+                "speedup_of_split": float(pj.mean()) / T,
+                "slice_amplitude_rel_diff": float(abs(amps[0] - a32[0]) / max(abs(a32[0]), 1e-300))}
         print(f"# fp32 step {pj.mean():.3f}s", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
@@ -231,10 +276,13 @@ def main():
                    "flops_per_step": flops_job, "flops_per_amplitude": flops_job * ns,
                    "complex_tflops": flops_job / T / 1e12, "precision": a.precision},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "gemm_mfma_kernel<128,64,16,2,2," + a.precision + ">",
-                     "launches": int(big.sum()) * a.steps,
-                     "algorithmic_bytes_per_launch": g_bytes / max(1, int(big.sum()) * a.steps)},
+                     "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "bytes/launch", "traffic_source": traffic_src,
+                     "kernel": dom,
+                     "launches": int(len(sel)) * a.steps,
+                     "algorithmic_flops_per_launch": g_flops / max(1, int(len(sel)) * a.steps),
+                     "avg_launch_ms": 1e3 * g_time / max(1, int(len(sel)) * a.steps),
+                     "algorithmic_bytes_per_launch": g_bytes / max(1, int(len(sel)) * a.steps)},
         "fp32_comparison": fp32,
         "cpu_baseline": cpu,
     }

@@ -336,11 +336,12 @@ typedef struct {
 tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p,
                                   int32_t precision, tn_plan_info* info);
 /* Per-op detail (arrays of n_ops, any may be NULL): kind (TN_OP_*),
- * algorithmic flops and bytes, and GEMM shape m, n, k, batch (1 for other
- * kinds; for APPLY: rows, 2^#N, 2^#K). */
+ * algorithmic flops and bytes, and `shape`, 6 int64 per op: m, n, k, batch,
+ * block-tile id, packed flag for GEMMs (1 for other kinds, tile -1; for
+ * APPLY: rows, 2^#N, 2^#K). */
 tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p,
                                  int32_t precision, int32_t* kind,
-                                 double* flops, double* bytes, int64_t* mnkb);
+                                 double* flops, double* bytes, int64_t* shape);
 
 /* Autotuner: time every candidate block-tile shape of every GEMM of this
  * path's plan (reps launches each, on the plan's own workspace buffers, whose

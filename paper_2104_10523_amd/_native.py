@@ -98,7 +98,7 @@ SIGNATURES = {
     "tn_amplitudes_workspace": (I32, [P, P, I64, I32, C.POINTER(C.c_size_t)]),
     "tn_amplitudes_plan_info": (I32, [P, P, I32, C.POINTER(TnPlanInfo)]),
     "tn_amplitudes_autotune": (I32, [P, P, I32, I32, P]),
-    "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),
+    "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),  # shape: 6 per op
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),

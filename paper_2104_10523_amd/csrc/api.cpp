@@ -529,7 +529,7 @@ tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p, int32_t
 }
 
 tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t precision,
-                                 int32_t* kind, double* flops, double* bytes, int64_t* mnkb) {
+                                 int32_t* kind, double* flops, double* bytes, int64_t* shape) {
   return guarded([&] {
     TN_REQUIRE(n && p, TN_ERR_ARG, "null argument");
     TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
@@ -539,11 +539,15 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
       if (kind) kind[k] = op.kind;
       if (flops) flops[k] = op.flops;
       if (bytes) bytes[k] = op.bytes;
-      if (mnkb) {
-        int64_t* r = mnkb + 4 * k;
+      if (shape) {
+        int64_t* r = shape + 6 * k;
         r[0] = r[1] = r[2] = r[3] = 1;
+        r[4] = -1;
+        r[5] = 0;
         if (op.kind == OP_GEMM) {
           r[0] = op.gm.M; r[1] = op.gm.N; r[2] = op.gm.K; r[3] = op.gm.batch;
+          r[4] = gemm_tile_of(op.gm);
+          r[5] = op.gm.packed;
         } else if (op.kind == OP_APPLY) {
           r[0] = int64_t(1) << (op.ap.a_bits - op.ap.nk);
           r[1] = int64_t(1) << op.ap.nn;

@@ -764,6 +764,8 @@ int choose_ksplit(const GemmDesc& g, int id, int64_t* kchunk) {
 }
 }  // namespace
 
+int gemm_tile_of(const GemmDesc& g) { return tile_of(g); }
+
 std::vector<int> gemm_tile_candidates(const GemmDesc& g) {
   if (!g.packed) return {0, 1, 2, 3};
   if (g.precision == TN_PREC_BF16X6) return {0, 1, 2, 4};

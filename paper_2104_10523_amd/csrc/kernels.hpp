@@ -59,8 +59,10 @@ struct GemmDesc {
 };
 // Workspace needed for split-K partials (bytes); 0 when no split is used.
 size_t gemm_workspace_bytes(const GemmDesc& g);
-// Tile ids valid for this GEMM (the autotuner's candidates).
+// Tile ids valid for this GEMM (the autotuner's candidates), and the id a
+// launch uses (the heuristic when g.tile < 0).
 std::vector<int> gemm_tile_candidates(const GemmDesc& g);
+int gemm_tile_of(const GemmDesc& g);
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
                  hipStream_t s);
 

@@ -133,3 +133,19 @@ def test_bits_errors(gpu, workspace):
         b = np.zeros((1, n), np.int8)
         b[0, 3] = -1
         tn.tn_amplitudes(net, path, b)
+
+
+def test_autotuned_plan_keeps_parity(gpu, workspace):
+    """The tile autotuner only changes block shapes: amplitudes stay within
+    tolerance for every precision after tuning."""
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    net = tn.tn_build_network(n, ops)
+    path = tn.tn_find_path(net, "greedy", open_mask=[1] * 8 + [0] * 12)
+    bits = np.array([[-1] * 8 + [0, 1] * 6], np.int8)
+    psi = sv.simulate(n, ops)
+    ref = sv.slice_of(psi, bits[0])
+    for prec in ("fp32", "bf16x3"):
+        tn.tn_amplitudes_autotune(net, path, prec, reps=1)
+        got, _ = tn.tn_amplitudes(net, path, bits, precision=prec)
+        check_amps(got.cpu().numpy()[0], ref, n, tol=1e-5 if prec == "fp32" else 1e-4)
