@@ -458,6 +458,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
 
   const int li = lane & 31, lh = lane >> 5;
   const int bn_local = li >> 1, bt = li & 1;
+  // B entry of the real 2x2 block form, branch-free per lane: FP32 lanes
+  // pick re b (lh == bt) or im b and negate for (lh, bt) = (1, 0); packed
+  // words rotate (odd lanes: (im, re)) and flip the sign of im (even lanes)
+  const uint32_t sel_re = lh == bt ? 0xffffffffu : 0u, neg = (lh == 1 && bt == 0) ? 0x80000000u : 0u;
+  const uint32_t brot = bt ? 16u : 0u, bxor = bt ? 0u : 0x80000000u;
 
   if (kbeg < kend) load_tiles(kbeg);
   for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
@@ -475,8 +480,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int row = (wn0 + j * 16 + bn_local) * LDK + kk;
-          const float br = __uint_as_float(Bs[row * 2]), bi = __uint_as_float(Bs[row * 2 + 1]);
-          bv[j] = lh == 0 ? (bt == 0 ? br : bi) : (bt == 0 ? -bi : br);
+          const uint32_t br = Bs[row * 2], bi = Bs[row * 2 + 1];
+          bv[j] = __uint_as_float(((br & sel_re) | (bi & ~sel_re)) ^ neg);
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
           for (int j = 0; j < TN; ++j) {
             u32x4 w = *reinterpret_cast<const u32x4*>(&Bs[(p * BN + wn0 + j * 16 + bn_local) * LDK + kk + 4 * lh]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w[q] = bt == 0 ? (w[q] ^ 0x80000000u) : ((w[q] >> 16) | (w[q] << 16));
+            for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_alignbit(w[q], w[q], brot) ^ bxor;
             bv[p][j] = w;
           }
         }
@@ -544,13 +549,51 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
 // buffered (one barrier per K tile).  Each wave owns TM x TN MFMA tiles of
 // 32 rows x 16 complex columns; a K step of 8 complex values is one
 // v_mfma_f32_32x32x16_bf16 per product pair.
+//
+// Global loads are raw buffer loads on a descriptor per operand panel: rows
+// past M (N) and k past the chunk end fall outside the descriptor's range and
+// read as zero in hardware, so the K loop has no divergent branches.
 struct PackedArgs {
   int64_t M, N, K;
   int64_t kchunk;
   int ksplit;
   int tiles_m, tiles_n;
+  int regions;                 // 1: XCD region order (see packed_tile_of)
   int64_t plane_a, plane_b;
 };
+
+// Block -> output tile.  Workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b % 8).  With `regions`, the blocks of one XCD
+// walk 4 x 8-tile regions (the 32 tiles its CUs hold at once share 4 A and
+// 8 B panels in that XCD's L2), and the 8 XCDs take 8 neighbouring regions
+// (2 region rows x 4 region columns) so that the last-level cache sees the
+// panels they share.  Otherwise: each XCD takes a contiguous range of a
+// grouped (8 tile rows) order.
+__device__ inline void packed_tile_of(int b, int nblk, const PackedArgs& P, int& tm, int& tn) {
+  if (P.regions) {
+    const int x = b & 7, j = b >> 3;
+    const int g = (j >> 5) * 8 + x, w = j & 31;
+    const int RN = P.tiles_n >> 3;
+    const int rm = (g / (2 * RN)) * 2 + (g & 1);
+    const int rn = (g >> 1) % RN;
+    tm = rm * 4 + (w & 3);
+    tn = rn * 8 + (w >> 2);
+    return;
+  }
+  int pid = b;
+  if ((nblk & 7) == 0) pid = (pid & 7) * (nblk >> 3) + (pid >> 3);
+  constexpr int GROUP = 8;
+  const int group_size = GROUP * P.tiles_n;
+  const int first_m = (pid / group_size) * GROUP;
+  const int gm = min(P.tiles_m - first_m, GROUP);
+  tm = first_m + (pid % group_size) % gm;
+  tn = (pid % group_size) / gm;
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t panel_rsrc(const uint32_t* base, uint32_t bytes) {
+  // gfx9 raw buffer: stride 0, num_records in bytes, default dst_sel/format
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(base), 0, int(bytes), 0x00020000);
+}
 
 template <int BM, int BN, int BK, int WGM, int WGN, int NP>
 __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
@@ -564,24 +607,17 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   constexpr int STAGE = A_WORDS + B_WORDS;
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
   constexpr int KQ = BK / 4;                        // uint4 per row per plane
-  constexpr int A_Q = NP * BM * KQ, B_Q = NP * BN * KQ;
+  constexpr int AQ = BM * KQ, BQ = BN * KQ;         // uint4 per plane
   constexpr int NT = WGM * WGN * 64;
-  constexpr int A_PER = (A_Q + NT - 1) / NT, B_PER = (B_Q + NT - 1) / NT;
+  constexpr int A_PP = (AQ + NT - 1) / NT, B_PP = (BQ + NT - 1) / NT;  // per thread per plane
+  constexpr uint32_t OOB = 0x80000000u;             // beyond every panel's range
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
 
-  const int nblk = gridDim.x;
-  int pid = blockIdx.x;
-  if ((nblk & 7) == 0) pid = (pid & 7) * (nblk >> 3) + (pid >> 3);
-  constexpr int GROUP = 8;
-  const int group_size = GROUP * P.tiles_n;
-  const int g = pid / group_size;
-  const int first_m = g * GROUP;
-  const int gm = min(P.tiles_m - first_m, GROUP);
-  const int tm_idx = first_m + (pid % group_size) % gm;
-  const int tn_idx = (pid % group_size) / gm;
+  int tm_idx, tn_idx;
+  packed_tile_of(blockIdx.x, gridDim.x, P, tm_idx, tn_idx);
   const int64_t m0 = int64_t(tm_idx) * BM, n0 = int64_t(tn_idx) * BN;
 
   const int zb = blockIdx.z;
@@ -589,8 +625,34 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   const int64_t bidx = zb / P.ksplit;
   const int64_t kbeg = int64_t(ks) * P.kchunk;
   const int64_t kend = min(P.K, kbeg + P.kchunk);
-  const uint32_t* Ab = Ap + bidx * P.M * P.K;
-  const uint32_t* Bb = Bp + bidx * P.N * P.K;
+  const int klen = int(kend - kbeg);
+  const int64_t rows_a = min<int64_t>(BM, P.M - m0), rows_b = min<int64_t>(BN, P.N - n0);
+
+  // one descriptor per plane; its range ends after element (last row, kend)
+  __amdgpu_buffer_rsrc_t src_a[NP], src_b[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    src_a[p] = panel_rsrc(Ap + bidx * P.M * P.K + p * P.plane_a + m0 * P.K + kbeg,
+                          uint32_t(((rows_a - 1) * P.K + klen) * 4));
+    src_b[p] = panel_rsrc(Bp + bidx * P.N * P.K + p * P.plane_b + n0 * P.K + kbeg,
+                          uint32_t(((rows_b - 1) * P.K + klen) * 4));
+  }
+  // thread chunk i of a plane: row q / KQ, word column 4 (q % KQ), q = tid + NT i;
+  // byte offset of that chunk at the start of the K chunk
+  uint32_t off_a[A_PP], off_b[B_PP];
+  int col_a[A_PP], col_b[B_PP];
+#pragma unroll
+  for (int i = 0; i < A_PP; ++i) {
+    const int q = min(tid + NT * i, AQ - 1);
+    off_a[i] = uint32_t((int64_t(q / KQ) * P.K + 4 * (q % KQ)) * 4);
+    col_a[i] = 4 * (q % KQ);
+  }
+#pragma unroll
+  for (int i = 0; i < B_PP; ++i) {
+    const int q = min(tid + NT * i, BQ - 1);
+    off_b[i] = uint32_t((int64_t(q / KQ) * P.K + 4 * (q % KQ)) * 4);
+    col_b[i] = 4 * (q % KQ);
+  }
 
   floatx16 acc[TM][TN];
 #pragma unroll
@@ -600,63 +662,58 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  u32x4 ra[A_PER], rb[B_PER];
-  auto load = [&](int64_t k0) {
+  u32x4 ra[NP][A_PP], rb[NP][B_PP];
+  auto load = [&](int kl) {  // kl: word offset of the tile inside the K chunk
+    const uint32_t dk = uint32_t(kl) * 4;
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
-      const int q = tid + NT * i;
-      const int p = q / (BM * KQ), rem = q % (BM * KQ);
-      const int r = rem / KQ, c = rem % KQ;
-      const int64_t m = m0 + r, k = k0 + 4 * c;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (q < A_Q && m < P.M && k < kend)
-        v = *reinterpret_cast<const u32x4*>(Ab + p * P.plane_a + m * P.K + k);
-      ra[i] = v;
+    for (int i = 0; i < A_PP; ++i) {
+      const uint32_t off = kl + col_a[i] < klen ? off_a[i] + dk : OOB;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) ra[p][i] = __builtin_amdgcn_raw_buffer_load_b128(src_a[p], off, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < B_PER; ++i) {
-      const int q = tid + NT * i;
-      const int p = q / (BN * KQ), rem = q % (BN * KQ);
-      const int r = rem / KQ, c = rem % KQ;
-      const int64_t n = n0 + r, k = k0 + 4 * c;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (q < B_Q && n < P.N && k < kend)
-        v = *reinterpret_cast<const u32x4*>(Bb + p * P.plane_b + n * P.K + k);
-      rb[i] = v;
+    for (int i = 0; i < B_PP; ++i) {
+      const uint32_t off = kl + col_b[i] < klen ? off_b[i] + dk : OOB;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) rb[p][i] = __builtin_amdgcn_raw_buffer_load_b128(src_b[p], off, 0, 0);
     }
   };
   auto store = [&](int buf) {
     uint32_t* As = smem + buf * STAGE;
     uint32_t* Bs = As + A_WORDS;
 #pragma unroll
-    for (int i = 0; i < A_PER; ++i) {
+    for (int i = 0; i < A_PP; ++i) {
       const int q = tid + NT * i;
-      if (q >= A_Q) break;
-      const int p = q / (BM * KQ), rem = q % (BM * KQ);
-      const int r = rem / KQ, c = rem % KQ;
-      *reinterpret_cast<u32x4*>(As + (p * BM + r) * LDK + 4 * c) = ra[i];
+      if (AQ % NT != 0 && q >= AQ) break;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        *reinterpret_cast<u32x4*>(As + (p * BM + q / KQ) * LDK + 4 * (q % KQ)) = ra[p][i];
     }
 #pragma unroll
-    for (int i = 0; i < B_PER; ++i) {
+    for (int i = 0; i < B_PP; ++i) {
       const int q = tid + NT * i;
-      if (q >= B_Q) break;
-      const int p = q / (BN * KQ), rem = q % (BN * KQ);
-      const int r = rem / KQ, c = rem % KQ;
-      *reinterpret_cast<u32x4*>(Bs + (p * BN + r) * LDK + 4 * c) = rb[i];
+      if (BQ % NT != 0 && q >= BQ) break;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        *reinterpret_cast<u32x4*>(Bs + (p * BN + q / KQ) * LDK + 4 * (q % KQ)) = rb[p][i];
     }
   };
 
   const int li = lane & 31, lh = lane >> 5;
   const int bn_local = li >> 1, bt = li & 1;
+  // B column of the real block form: even lanes (real part of C) take
+  // (re b, -im b), odd lanes (imaginary part) take (im b, re b); as one
+  // branch-free rotate-and-xor per word
+  const uint32_t brot = bt ? 16u : 0u, bxor = bt ? 0u : 0x80000000u;
   int buf = 0;
-  if (kbeg < kend) {
-    load(kbeg);
+  if (klen > 0) {
+    load(0);
     store(0);
   }
   __syncthreads();
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) load(k0 + BK);
+  for (int kl = 0; kl < klen; kl += BK) {
+    const bool more = kl + BK < klen;
+    if (more) load(kl + BK);
     const uint32_t* As = smem + buf * STAGE;
     const uint32_t* Bs = As + A_WORDS;
 #pragma unroll
@@ -671,7 +728,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
         for (int j = 0; j < TN; ++j) {
           u32x4 w = *reinterpret_cast<const u32x4*>(Bs + (p * BN + wn0 + j * 16 + bn_local) * LDK + kk + 4 * lh);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = bt == 0 ? (w[q] ^ 0x80000000u) : ((w[q] >> 16) | (w[q] << 16));
+          for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_alignbit(w[q], w[q], brot) ^ bxor;
           bv[p][j] = w;
         }
       }
@@ -855,6 +912,10 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
     P.tiles_n = tiles_n;
+    P.regions = (tiles_m % 8 == 0 && tiles_n % 8 == 0 && (int64_t(tiles_m) * tiles_n) % 256 == 0) ? 1 : 0;
+    // buffer offsets are 32-bit: a (BM x K) panel of one plane must stay below 2 GiB
+    TN_REQUIRE(int64_t(t.bm > t.bn ? t.bm : t.bn) * g.K * 4 < (int64_t(1) << 31), TN_ERR_UNSUPPORTED,
+               "packed GEMM: K too long for one panel");
     const uint32_t* Ap = reinterpret_cast<const uint32_t*>(A);
     const uint32_t* Bp = reinterpret_cast<const uint32_t*>(B);
     if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16>(Ap, Bp, out, P, g.batch, id, s);
