@@ -35,7 +35,7 @@ HBM_PEAK = 8.0e12
 
 # tile id -> (BM, BN, BK, WGM, WGN) of the kernels in csrc/kernels.hip
 PACKED_TILES = {2: {0: (256, 16, 32, 4, 1), 1: (128, 32, 32, 4, 1), 2: (128, 64, 32, 2, 2),
-                    3: (256, 128, 16, 4, 2), 4: (128, 128, 16, 2, 2)},
+                    3: (256, 128, 16, 4, 2), 4: (128, 128, 16, 2, 2), 5: (256, 128, 16, 4, 2)},
                 3: {0: (256, 16, 16, 4, 1), 1: (128, 32, 16, 4, 1), 2: (128, 64, 16, 2, 2),
                     4: (128, 128, 16, 2, 2)}}
 UNPACKED_TILES = {0: (256, 16), 1: (128, 32), 2: (128, 64), 3: (64, 64)}
@@ -45,7 +45,8 @@ def kernel_name(precision, tile, packed):
     if packed:
         np_ = 3 if precision == "bf16x6" else 2
         bm, bn, bk, wm, wn = PACKED_TILES[np_][tile]
-        return f"gemm_packed_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}>"
+        kern = "gemm_packed_dma_kernel" if tile == 5 else "gemm_packed_kernel"
+        return f"{kern}<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}>"
     bm, bn = UNPACKED_TILES[tile]
     bk = 8 if precision == "fp32" else 16
     wm, wn = (2, 2) if bn >= 64 else (4, 1)

@@ -545,9 +545,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
 
 // Packed-plane complex GEMM for the split precisions.  Operands arrive as NP
 // bf16 planes (from the permute/split pass) with k fastest, so a K tile is
-// copied global -> LDS with 16-byte loads and no conversion; LDS is double
-// buffered (one barrier per K tile).  Each wave owns TM x TN MFMA tiles of
-// 32 rows x 16 complex columns; a K step of 8 complex values is one
+// copied global -> registers -> LDS with 16-byte accesses and no conversion.
+// LDS holds two stages (one barrier per K tile, bank-conflict-free XOR
+// layout).  Each wave owns TM x TN MFMA tiles of 32 rows x
+// 16 complex columns; a K step of 8 complex values is one
 // v_mfma_f32_32x32x16_bf16 per product pair.
 //
 // Global loads are raw buffer loads on a descriptor per operand panel: rows
@@ -595,6 +596,76 @@ __device__ inline __amdgpu_buffer_rsrc_t panel_rsrc(const uint32_t* base, uint32
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(base), 0, int(bytes), 0x00020000);
 }
 
+// LDS tile rows of BK words (16-byte chunks, no padding); chunk c of row r
+// is stored at position c ^ f(r).  With f as below, the 16-byte accesses of
+// any 8 (32 banks) or 16 (64 banks) consecutive lanes hit distinct banks
+// both for the copy-in pattern (KQ lanes per row, consecutive rows) and for
+// the MFMA fragment reads (one chunk of 32 consecutive rows).
+template <int BK>
+__device__ __forceinline__ int lds_word(int r, int c) {
+  static_assert(BK == 16 || BK == 32, "swizzle defined for 4 or 8 chunks per row");
+  const int f = BK == 16 ? (((r >> 1) ^ (r >> 3)) & 3) : ((r ^ (r >> 3)) & 7);
+  return r * BK + 4 * (c ^ f);
+}
+
+// One K tile of the packed GEMM from LDS: per K step of 8 complex values,
+// the A and B fragments of every plane, the B block-form swizzle, and one
+// v_mfma_f32_32x32x16_bf16 per product pair and MFMA tile.
+template <int BM, int BN, int BK, int NP, int TM, int TN>
+__device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32_t* Bs, floatx16 (&acc)[TM][TN],
+                                                int wm0, int wn0, int li, int lh, int bn_local, uint32_t brot,
+                                                uint32_t bxor) {
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 8) {
+    u32x4 av[NP][TM], bv[NP][TN];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        av[p][i] = *reinterpret_cast<const u32x4*>(As + lds_word<BK>(p * BM + wm0 + i * 32 + li, kk / 4 + lh));
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        u32x4 w = *reinterpret_cast<const u32x4*>(Bs + lds_word<BK>(p * BN + wn0 + j * 16 + bn_local, kk / 4 + lh));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_alignbit(w[q], w[q], brot) ^ bxor;
+        bv[p][j] = w;
+      }
+    }
+    // product pairs (pa, pb) with pa + pb < NP, smallest first; the tile
+    // loops are innermost so consecutive MFMAs use independent accumulators
+#pragma unroll
+    for (int s2 = NP - 1; s2 >= 0; --s2)
+#pragma unroll
+      for (int pa = 0; pa <= s2; ++pa) {
+        const int pb = s2 - pa;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
+      }
+  }
+}
+
+// Writes a wave's TM x TN accumulator tiles (32 rows x 16 complex columns
+// each, rows from mw, complex columns from nw) to C (row-major M x N
+// complex); entries outside M x N are skipped.
+template <int TM, int TN>
+__device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[TM][TN], int64_t mw, int64_t nw,
+                                               int lh, int bn_local, int bt, int64_t M, int64_t N) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t m = mw + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int64_t n = nw + j * 16 + bn_local;
+        if (m < M && n < N) Cf[(m * N + n) * 2 + bt] = acc[i][j][r];
+      }
+}
+
 template <int BM, int BN, int BK, int WGM, int WGN, int NP>
 __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
                                                           const uint32_t* __restrict__ Bp,
@@ -602,8 +673,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TM = WM / 32, TN = WN / 16;
   static_assert(TM >= 1 && TN >= 1 && BK % 8 == 0, "bad tile");
-  constexpr int LDK = BK + 4;                       // words per LDS row (16-byte aligned)
-  constexpr int A_WORDS = NP * BM * LDK, B_WORDS = NP * BN * LDK;
+  constexpr int A_WORDS = NP * BM * BK, B_WORDS = NP * BN * BK;
   constexpr int STAGE = A_WORDS + B_WORDS;
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
   constexpr int KQ = BK / 4;                        // uint4 per row per plane
@@ -662,8 +732,10 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  u32x4 ra[NP][A_PP], rb[NP][B_PP];
-  auto load = [&](int kl) {  // kl: word offset of the tile inside the K chunk
+  using ASet = u32x4[NP][A_PP];
+  using BSet = u32x4[NP][B_PP];
+  u32x4 ra0[NP][A_PP], rb0[NP][B_PP];
+  auto load = [&](int kl, ASet& ra, BSet& rb) {  // kl: word offset of the tile in the K chunk
     const uint32_t dk = uint32_t(kl) * 4;
 #pragma unroll
     for (int i = 0; i < A_PP; ++i) {
@@ -678,7 +750,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
       for (int p = 0; p < NP; ++p) rb[p][i] = __builtin_amdgcn_raw_buffer_load_b128(src_b[p], off, 0, 0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, const ASet& ra, const BSet& rb) {
     uint32_t* As = smem + buf * STAGE;
     uint32_t* Bs = As + A_WORDS;
 #pragma unroll
@@ -687,7 +759,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
       if (AQ % NT != 0 && q >= AQ) break;
 #pragma unroll
       for (int p = 0; p < NP; ++p)
-        *reinterpret_cast<u32x4*>(As + (p * BM + q / KQ) * LDK + 4 * (q % KQ)) = ra[p][i];
+        *reinterpret_cast<u32x4*>(As + lds_word<BK>(p * BM + q / KQ, q % KQ)) = ra[p][i];
     }
 #pragma unroll
     for (int i = 0; i < B_PP; ++i) {
@@ -695,7 +767,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
       if (BQ % NT != 0 && q >= BQ) break;
 #pragma unroll
       for (int p = 0; p < NP; ++p)
-        *reinterpret_cast<u32x4*>(Bs + (p * BN + q / KQ) * LDK + 4 * (q % KQ)) = rb[p][i];
+        *reinterpret_cast<u32x4*>(Bs + lds_word<BK>(p * BN + q / KQ, q % KQ)) = rb[p][i];
     }
   };
 
@@ -705,65 +777,163 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   // (re b, -im b), odd lanes (imaginary part) take (im b, re b); as one
   // branch-free rotate-and-xor per word
   const uint32_t brot = bt ? 16u : 0u, bxor = bt ? 0u : 0x80000000u;
+
+  auto multiply = [&](int buf) {
+    const uint32_t* As = smem + buf * STAGE;
+    packed_multiply<BM, BN, BK, NP, TM, TN>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
+  };
+
+  // K tile t (word offset kl = t BK) is multiplied from stage t % 2 while
+  // tile t + 1 is loaded into registers; it goes to the other stage after
   int buf = 0;
   if (klen > 0) {
-    load(0);
-    store(0);
+    load(0, ra0, rb0);
+    store(0, ra0, rb0);
   }
   __syncthreads();
   for (int kl = 0; kl < klen; kl += BK) {
     const bool more = kl + BK < klen;
-    if (more) load(kl + BK);
-    const uint32_t* As = smem + buf * STAGE;
-    const uint32_t* Bs = As + A_WORDS;
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 8) {
-      u32x4 av[NP][TM], bv[NP][TN];
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-          av[p][i] = *reinterpret_cast<const u32x4*>(As + (p * BM + wm0 + i * 32 + li) * LDK + kk + 4 * lh);
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          u32x4 w = *reinterpret_cast<const u32x4*>(Bs + (p * BN + wn0 + j * 16 + bn_local) * LDK + kk + 4 * lh);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_alignbit(w[q], w[q], brot) ^ bxor;
-          bv[p][j] = w;
-        }
-      }
-      // product pairs (pa, pb) with pa + pb < NP, smallest first; the tile
-      // loops are innermost so consecutive MFMAs use independent accumulators
-#pragma unroll
-      for (int s2 = NP - 1; s2 >= 0; --s2)
-#pragma unroll
-        for (int pa = 0; pa <= s2; ++pa) {
-          const int pb = s2 - pa;
-#pragma unroll
-          for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]),
-                  acc[i][j], 0, 0, 0);
-        }
-    }
-    if (more) store(buf ^ 1);
+    if (more) load(kl + BK, ra0, rb0);
+    multiply(buf);
+    if (more) store(buf ^ 1, ra0, rb0);
     __syncthreads();
     buf ^= 1;
   }
 
-  float* Cf = reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N);
+  packed_store_c<TM, TN>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
+                         acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N);
+}
+
+// Direct-to-LDS variant for exactly tiled GEMMs (M % BM == N % BN == 0 and
+// every K chunk a whole number of BK tiles).  Each wave copies 64 x 16-byte
+// chunks per instruction with buffer_load ... lds straight into the swizzled
+// LDS layout (lane l lands at byte 16 l of its 1 KB block, so it fetches the
+// logical chunk that the XOR layout stores there).  No staging registers are
+// needed, so LDS holds three stages and the copy of K tile t + 2 is issued
+// while tile t is multiplied: a load has two tiles of MFMA work to land.
+// Synchronisation per tile: wait until this wave's copies of tile t are done
+// (the ones of tile t + 1 may still be in flight), then one barrier, which
+// also frees the stage tile t - 1 occupied.
+template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+__global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const uint32_t* __restrict__ Ap,
+                                                              const uint32_t* __restrict__ Bp,
+                                                              float2* __restrict__ C, PackedArgs P) {
+#if defined(__HIP_DEVICE_COMPILE__)  // device-only builtins; the host pass needs only the stub
+  constexpr int NW = WGM * WGN;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 32, TN = WN / 16;
+  constexpr int KQ = BK / 4;                         // 16-byte chunks per row
+  constexpr int RPL = 64 / KQ;                       // rows covered by one wave-wide copy
+  constexpr int AB = BM / RPL, BB = BN / RPL;        // row blocks per plane
+  static_assert(AB % NW == 0 && BB % NW == 0, "row blocks must split evenly over the waves");
+  constexpr int A_PW = NP * AB / NW, B_PW = NP * BB / NW;   // copies per wave per K tile
+  constexpr int PER_TILE = A_PW + B_PW;
+  static_assert(PER_TILE <= 15, "vmcnt immediate");
+  constexpr int A_WORDS = NP * BM * BK, B_WORDS = NP * BN * BK;
+  constexpr int STAGE = A_WORDS + B_WORDS;
+  extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+
+  int tm_idx, tn_idx;
+  packed_tile_of(blockIdx.x, gridDim.x, P, tm_idx, tn_idx);
+  const int64_t m0 = int64_t(tm_idx) * BM, n0 = int64_t(tn_idx) * BN;
+  const int zb = blockIdx.z;
+  const int ks = zb % P.ksplit;
+  const int64_t bidx = zb / P.ksplit;
+  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int klen = int(min(P.K, kbeg + P.kchunk) - kbeg);
+  const int ntiles = klen / BK;
+
+  __amdgpu_buffer_rsrc_t src_a[NP], src_b[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    src_a[p] = panel_rsrc(Ap + bidx * P.M * P.K + p * P.plane_a + m0 * P.K + kbeg,
+                          uint32_t(((BM - 1) * P.K + klen) * 4));
+    src_b[p] = panel_rsrc(Bp + bidx * P.N * P.K + p * P.plane_b + n0 * P.K + kbeg,
+                          uint32_t(((BN - 1) * P.K + klen) * 4));
+  }
+  // copy i of this wave: row block (NW i + wave) of the planes laid out one
+  // after another; lane l takes row l / KQ of the block and the logical chunk
+  // stored at physical position l % KQ
+  uint32_t voff_a[A_PW], voff_b[B_PW];
+#pragma unroll
+  for (int i = 0; i < A_PW; ++i) {
+    const int blk = (NW * i) % AB + wave;
+    const int p = (NW * i) / AB;
+    const int r = blk * RPL + lane / KQ;
+    const int c = (lane % KQ) ^ ((lds_word<BK>(p * BM + r, 0) >> 2) & (KQ - 1));
+    voff_a[i] = uint32_t((int64_t(r) * P.K + 4 * c) * 4);
+  }
+#pragma unroll
+  for (int i = 0; i < B_PW; ++i) {
+    const int blk = (NW * i) % BB + wave;
+    const int p = (NW * i) / BB;
+    const int r = blk * RPL + lane / KQ;
+    const int c = (lane % KQ) ^ ((lds_word<BK>(p * BN + r, 0) >> 2) & (KQ - 1));
+    voff_b[i] = uint32_t((int64_t(r) * P.K + 4 * c) * 4);
+  }
+  auto issue = [&](int t, int stage) {
+    uint32_t* base = smem + stage * STAGE;
+    const uint32_t dk = uint32_t(t * BK) * 4;
+#pragma unroll
+    for (int i = 0; i < A_PW; ++i) {
+      const int p = (NW * i) / AB;
+      uint32_t* dst = base + (p * BM + ((NW * i) % AB + wave) * RPL) * BK;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(src_a[p], (__attribute__((address_space(3))) void*)dst, 16,
+                                               voff_a[i] + dk, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < B_PW; ++i) {
+      const int p = (NW * i) / BB;
+      uint32_t* dst = base + A_WORDS + (p * BN + ((NW * i) % BB + wave) * RPL) * BK;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(src_b[p], (__attribute__((address_space(3))) void*)dst, 16,
+                                               voff_b[i] + dk, 0, 0, 0);
+    }
+  };
+
+  floatx16 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t m = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-        const int64_t n = n0 + wn0 + j * 16 + bn_local;
-        if (m < P.M && n < P.N) Cf[(m * P.N + n) * 2 + bt] = acc[i][j][r];
-      }
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int li = lane & 31, lh = lane >> 5;
+  const int bn_local = li >> 1, bt = li & 1;
+  const uint32_t brot = bt ? 16u : 0u, bxor = bt ? 0u : 0x80000000u;
+
+  // the barrier is an s_barrier between compiler memory fences (no wait on
+  // the copies still in flight); the vmcnt waits are explicit
+  auto barrier = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  if (ntiles > 0) issue(0, 0);
+  if (ntiles > 1) issue(1, 1);
+  int stage = 0;    // stage of tile t; tile t + 2 goes to the one before it
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) {
+      __builtin_amdgcn_s_waitcnt(0x0F70 | PER_TILE);   // vmcnt(PER_TILE): tile t landed
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt(0)
+    }
+    barrier();
+    const int prev = stage == 0 ? 2 : stage - 1;
+    if (t + 2 < ntiles) issue(t + 2, prev);
+    const uint32_t* As = smem + stage * STAGE;
+    packed_multiply<BM, BN, BK, NP, TM, TN>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
+    stage = stage == 2 ? 0 : stage + 1;
+  }
+
+  packed_store_c<TM, TN>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
+                         acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N);
+#endif
 }
 
 __global__ __launch_bounds__(256) void reduce_splitk_kernel(const float2* __restrict__ part,
@@ -789,13 +959,18 @@ struct TileShape {
   int bm, bn;
 };
 constexpr TileShape kUnpackedTiles[4] = {{256, 16}, {128, 32}, {128, 64}, {64, 64}};
-constexpr TileShape kPackedTiles[5] = {{256, 16}, {128, 32}, {128, 64}, {256, 128}, {128, 128}};
+constexpr TileShape kPackedTiles[6] = {{256, 16}, {128, 32}, {128, 64}, {256, 128}, {128, 128}, {256, 128}};
+
+// Tile 5 (direct-to-LDS copies) needs whole tiles in M, N and K.
+bool dma_exact(const GemmDesc& g) {
+  return g.packed && g.precision == TN_PREC_BF16X3 && g.M % 256 == 0 && g.N % 128 == 0 && g.K % 16 == 0;
+}
 
 int default_tile(const GemmDesc& g) {
   if (g.N <= 16) return 0;
   if (g.N <= 32) return 1;
   if (g.packed && g.precision == TN_PREC_BF16X3 && g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22))
-    return 3;
+    return dma_exact(g) ? 5 : 3;
   return 2;
 }
 
@@ -805,7 +980,7 @@ int tile_of(const GemmDesc& g) { return g.tile >= 0 ? g.tile : default_tile(g); 
 int tile_bk(const GemmDesc& g, int id) {
   if (!g.packed) return g.precision == TN_PREC_FP32 ? 8 : 16;
   if (g.precision == TN_PREC_BF16X6) return 16;
-  return (id == 3 || id == 4) ? 16 : 32;
+  return (id == 3 || id == 4 || id == 5) ? 16 : 32;
 }
 
 int choose_ksplit(const GemmDesc& g, int id, int64_t* kchunk) {
@@ -826,6 +1001,7 @@ int gemm_tile_of(const GemmDesc& g) { return tile_of(g); }
 std::vector<int> gemm_tile_candidates(const GemmDesc& g) {
   if (!g.packed) return {0, 1, 2, 3};
   if (g.precision == TN_PREC_BF16X6) return {0, 1, 2, 4};
+  if (dma_exact(g)) return {0, 1, 2, 3, 4, 5};
   return {0, 1, 2, 3, 4};
 }
 
@@ -856,8 +1032,7 @@ static void launch_gemm_prec(const float2* A, const float2* B, float2* C, const 
 template <int BM, int BN, int BK, int WGM, int WGN, int NP>
 static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
                               int64_t batch, hipStream_t s) {
-  constexpr int LDK = BK + 4;
-  constexpr size_t lds = size_t(2) * NP * (BM + BN) * LDK * sizeof(uint32_t);
+  constexpr size_t lds = size_t(2) * NP * (BM + BN) * BK * sizeof(uint32_t);
   static_assert(lds <= 160 * 1024, "LDS tile exceeds the 160 KB of a CU");
   static bool attr_set = false;
   if (!attr_set) {
@@ -867,6 +1042,21 @@ static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, c
   }
   dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
   gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+static void launch_packed_dma(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
+                              int64_t batch, hipStream_t s) {
+  constexpr size_t lds = size_t(3) * NP * (BM + BN) * BK * sizeof(uint32_t);
+  static_assert(lds <= 160 * 1024, "LDS stages exceed the 160 KB of a CU");
+  static bool attr_set = false;
+  if (!attr_set) {
+    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    attr_set = true;
+  }
+  dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
+  gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
 }
 
 template <int NP, int BK>
@@ -879,6 +1069,10 @@ static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, co
       if constexpr (NP == 2) { launch_packed_cfg<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s); break; }
       [[fallthrough]];
     case 4: launch_packed_cfg<128, 128, 16, 2, 2, NP>(A, B, C, P, batch, s); break;
+    case 5:
+      if constexpr (NP == 2) { launch_packed_dma<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s); break; }
+      launch_packed_cfg<128, 128, 16, 2, 2, NP>(A, B, C, P, batch, s);
+      break;
     default: launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s); break;
   }
 }

@@ -1,0 +1,64 @@
+"""Full-size parity: the 49-qubit 7x7 grid circuit of 14 cycles, with the
+benchmark's path search (best of greedy and 32 randomised-greedy trials,
+seed 1, T = 0.5), 64 GiB slicing budget and default launch configuration,
+i.e. the exact kernel sequence and shapes the benchmark times (2^13 slices of
+2^49.5 flops each).
+
+The amplitude of that circuit cannot be computed by the oracle, so the
+two-qubit gates are fSim(0, 0) (the identity): the network keeps its
+structure (labels, path and slicing depend on gate positions only) while
+every slice gets a closed-form value, the product of per-wire factors with
+the sliced bonds projected (oracle/separable.py).
+
+Error measure: |a - r| / max(|r|, 2^-(n + n_sliced)/2), the floor being the
+RMS amplitude of one slice of a normalised state (a slice whose bonds
+project onto nearly orthogonal states has an exact value far below what any
+finite-precision contraction resolves).  Bound per precision: the 1e-5
+target, or 4x the library's a-priori estimate when that is larger (it sums
+u^2 (1 + log2 K) over the plan's GEMMs, u = 2^-17 for split-BF16x3, whose
+estimate at this depth is 1.4e-4).
+"""
+
+import numpy as np
+import pytest
+
+from oracle.separable import separable_slice_amplitude
+from workloads import grid_random_circuit, random_bitstrings
+
+pytestmark = pytest.mark.gpu
+
+PATH_OPTS = dict(trials=32, seed=1, temperature=0.5, mem_budget_bytes=64.0 * 2 ** 30)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_rqc_7x7_14_full_size_slices(gpu, workspace, precision):
+    import torch
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim", fsim_params=(0.0, 0.0))
+    net = tn.tn_build_network(n, ops)
+    path = tn.tn_find_path(net, "random_greedy", **PATH_OPTS)
+    ns = path.cost.n_sliced
+    assert ns == 13
+    floor = 2.0 ** (-(n + ns) / 2)
+    bits = random_bitstrings(2, n, 12345)
+    need = tn.tn_amplitudes_workspace(net, path, len(bits), precision)
+    big = torch.empty(need, dtype=torch.uint8, device=gpu)
+    tn.tn_set_workspace(big)
+    try:
+        for s in (1, 4096):
+            print(f"full-size {precision} slice {s}", flush=True)
+            out, rep = tn.tn_amplitudes(net, path, bits, precision=precision, slice_begin=s, slice_count=1)
+            got = out.cpu().numpy().reshape(len(bits))
+            assert rep.nonfinite == 0
+            tol = max(1e-5, 4 * rep.err_bound)
+            vals = {l: (s >> (ns - 1 - i)) & 1 for i, l in enumerate(path.sliced)}
+            for b in range(len(bits)):
+                ref = separable_slice_amplitude(n, ops, bits[b], vals)
+                err = abs(got[b] - ref) / max(abs(ref), floor)
+                print(f"  bits {b}: got {got[b]:.6e} ref {ref:.6e} err {err:.2e} "
+                      f"(bound {rep.err_bound:.1e}, tol {tol:.1e})", flush=True)
+                assert err <= tol, (s, b, err, tol)
+    finally:
+        tn.tn_set_workspace(workspace)
+        del big
+        torch.cuda.empty_cache()
