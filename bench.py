@@ -29,7 +29,7 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-PEAKS = {"bf16x3": 2.5e15, "bf16x6": 2.5e15, "fp32": 157.3e12}
+PEAKS = {"bf16x3": 2.5e15, "bf16x6": 2.5e15, "f16x3": 2.5e15, "fp32": 157.3e12}
 HBM_PEAK = 8.0e12
 
 
@@ -46,7 +46,8 @@ def kernel_name(precision, tile, packed):
         np_ = 3 if precision == "bf16x6" else 2
         bm, bn, bk, wm, wn = PACKED_TILES[np_][tile]
         kern = "gemm_packed_dma_kernel" if tile == 5 else "gemm_packed_kernel"
-        return f"{kern}<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}>"
+        f16 = "true" if precision == "f16x3" else "false"
+        return f"{kern}<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}, {f16}>"
     bm, bn = UNPACKED_TILES[tile]
     bk = 8 if precision == "fp32" else 16
     wm, wn = (2, 2) if bn >= 64 else (4, 1)
@@ -72,7 +73,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "bf16x6", "fp32", "auto"])
+    ap.add_argument("--precision", default="f16x3", choices=["bf16x3", "bf16x6", "f16x3", "fp32", "auto"])
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time FP32 steps")
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -268,6 +269,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16x3-split c64, fp32 accumulate", "bf16x6": "bf16x6-split c64, fp32 accumulate",
+                  "f16x3": "scaled f16x3-split c64, fp32 accumulate",
                   "fp32": "c64 fp32", "auto": "c64 auto"}[a.precision],
         "data": "synthetic",
         "config": {"workload": f"{a.rows}x{a.cols} grid random circuit, {a.cycles} cycles, fSim(pi/2,pi/6), "

@@ -246,11 +246,15 @@ enum { TN_C64 = 0, TN_C128 = 1 };
 
 /* Arithmetic of the complex GEMMs.  FP32: FP32 MFMA.  BF16X3: each operand
  * split as hi + lo bfloat16, products hi*hi + hi*lo + lo*hi, FP32
- * accumulation.  BF16X6: three-way bfloat16 split, six products (about FP32
- * accuracy).  AUTO: the library picks per contraction from an error
- * estimate (BF16X3 for large contractions, FP32 elsewhere). */
+ * accumulation (about 2^-17 relative per GEMM).  BF16X6: three-way bfloat16
+ * split, six products (about FP32 accuracy).  F16X3: each operand scaled by
+ * a power of two chosen from its largest entry (so it spans [2^14, 2^15)),
+ * split as hi + lo fp16, three products, FP32 accumulation, scales undone
+ * exactly (about 2^-21 relative per GEMM at the speed of BF16X3).  AUTO: the
+ * library picks per contraction (F16X3 for large contractions, FP32
+ * elsewhere). */
 enum { TN_PREC_FP32 = 0, TN_PREC_BF16X3 = 1, TN_PREC_BF16X6 = 2,
-       TN_PREC_AUTO = 3 };
+       TN_PREC_AUTO = 3, TN_PREC_F16X3 = 4 };
 
 typedef struct {
   void* data;                 /* device pointer, row-major, caller-owned    */

@@ -288,7 +288,7 @@ tn_status tn_contract_pair(const tn_tensor* A, const int32_t* modesA, const tn_t
                            int32_t precision, void* stream) {
   return guarded([&] {
     TN_REQUIRE(A && B && C, TN_ERR_ARG, "null tensor");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     std::map<int32_t, int> ids;
     std::map<int32_t, int64_t> ext;
     TRef X, Y;
@@ -323,7 +323,7 @@ tn_status tn_amplitudes_workspace(const tn_network* n, const tn_path* p, int64_t
                                   int32_t precision, size_t* bytes) {
   return guarded([&] {
     TN_REQUIRE(n && p && bytes && n_bs >= 1, TN_ERR_ARG, "bad argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     *bytes = ws_layout(*plan, n_bs).total;
   });
@@ -337,7 +337,7 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
     TN_REQUIRE(n && p && bits && out && n_bs >= 1, TN_ERR_ARG, "bad argument");
     tn_exec_opts o{TN_PREC_FP32, 0, 0, -1, 0, 0, nullptr};
     if (opts) o = *opts;
-    TN_REQUIRE(o.precision >= TN_PREC_FP32 && o.precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(o.precision >= TN_PREC_FP32 && o.precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     const int nq = n->net.n_qubits;
     TN_REQUIRE(int(p->open_q.size()) == nq, TN_ERR_ARG, "path belongs to another network");
     for (int64_t b = 0; b < n_bs; ++b)
@@ -496,7 +496,7 @@ tn_status tn_amplitudes_autotune(const tn_network* n_, const tn_path* p_, int32_
     auto* n = const_cast<tn_network*>(n_);
     auto* p = const_cast<tn_path*>(p_);
     TN_REQUIRE(n && p && reps >= 1, TN_ERR_ARG, "bad argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(n, p, precision);
     const WsLayout L = ws_layout(*plan, 1);
     const Workspace ws = get_ws();
@@ -514,7 +514,7 @@ tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p, int32_t
                                   tn_plan_info* info) {
   return guarded([&] {
     TN_REQUIRE(n && p && info, TN_ERR_ARG, "null argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     std::memset(info, 0, sizeof(*info));
     info->n_ops = int32_t(plan->ops.size());
@@ -532,7 +532,7 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
                                  int32_t* kind, double* flops, double* bytes, int64_t* shape) {
   return guarded([&] {
     TN_REQUIRE(n && p, TN_ERR_ARG, "null argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_AUTO, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     for (size_t k = 0; k < plan->ops.size(); ++k) {
       const PlanOp& op = plan->ops[k];

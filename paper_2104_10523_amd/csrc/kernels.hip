@@ -55,18 +55,56 @@ __device__ __forceinline__ void split_c(float2 v, uint32_t* w) {
   }
 }
 
-// NP = 0 writes complex64; NP = 2 / 3 writes NP planes of packed bf16 words
-// (plane p at out + p * plane).
+// Split-FP16 operands: the value times a power of two (chosen per operand
+// from its largest magnitude, so that it lands in [2^14, 2^15)) split into a
+// round-to-nearest fp16 part and the fp16 rounding of the remainder.
+constexpr int kF16 = 4;   // plane mode: two planes of packed fp16 words
+__device__ __forceinline__ uint32_t f16_bits(float x) {
+  return uint32_t(__builtin_bit_cast(unsigned short, static_cast<_Float16>(x)));
+}
+__device__ __forceinline__ float f16_to_float(uint32_t h) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h)));
+}
+__device__ __forceinline__ void split_c_f16(float2 v, float scale, uint32_t* w) {
+  float r = v.x * scale, i = v.y * scale;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const uint32_t hr = f16_bits(r), hi = f16_bits(i);
+    w[p] = hr | (hi << 16);
+    r -= f16_to_float(hr);
+    i -= f16_to_float(hi);
+  }
+}
+// Exponent s of the operand scale 2^s from the bits of its largest |re|, |im|
+// (0 for an all-zero or non-finite operand).
+__device__ __forceinline__ int f16_scale_exp(uint32_t max_bits) {
+  const float m = __uint_as_float(max_bits);
+  if (!(m > 0.f) || !isfinite(m)) return 0;
+  return min(100, max(-100, 14 - ilogbf(m)));
+}
+
+// NP = 0 writes complex64; NP = 2 / 3 writes NP planes of packed bf16 words,
+// NP = kF16 two planes of packed fp16 words of the scaled value (plane p at
+// out + p * plane).
 template <int NP>
-__device__ __forceinline__ void put(void* out, int64_t plane, int64_t idx, float2 v) {
+__device__ __forceinline__ void put(void* out, int64_t plane, int64_t idx, float2 v, float scale) {
   if constexpr (NP == 0) {
     static_cast<float2*>(out)[idx] = v;
+  } else if constexpr (NP == kF16) {
+    uint32_t w[2];
+    split_c_f16(v, scale, w);
+    static_cast<uint32_t*>(out)[idx] = w[0];
+    static_cast<uint32_t*>(out)[plane + idx] = w[1];
   } else {
     uint32_t w[NP];
     split_c<NP>(v, w);
 #pragma unroll
     for (int p = 0; p < NP; ++p) static_cast<uint32_t*>(out)[p * plane + idx] = w[p];
   }
+}
+
+__device__ __forceinline__ float operand_scale(const uint32_t* smax) {
+  return smax ? ldexpf(1.f, f16_scale_exp(*smax)) : 1.f;
 }
 
 // ------------------------------------------------------------------ permute
@@ -84,7 +122,9 @@ struct PermArgs {
 
 template <int NP>
 __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __restrict__ in,
-                                                            void* __restrict__ out, PermArgs P) {
+                                                            void* __restrict__ out, PermArgs P,
+                                                            const uint32_t* __restrict__ smax) {
+  const float scale = NP == kF16 ? operand_scale(smax) : 1.f;
   __shared__ int64_t s_in_lo[32], s_in_hi[32], s_out_lo[32], s_out_hi[32];
   __shared__ int s_l_lo[32], s_l_hi[32];
   __shared__ float2 tile[1024 + 32];
@@ -124,7 +164,7 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
     __syncthreads();
     for (int f = t; f < tsize; f += 256) {
       const int e = s_l_lo[f & 31] | s_l_hi[f >> 5];
-      put<NP>(out, P.plane, ob + s_out_lo[f & 31] + s_out_hi[f >> 5], tile[e + (e >> 5)]);
+      put<NP>(out, P.plane, ob + s_out_lo[f & 31] + s_out_hi[f >> 5], tile[e + (e >> 5)], scale);
     }
     __syncthreads();
   }
@@ -140,7 +180,9 @@ struct PermSimpleArgs {
 template <int NP>
 __global__ __launch_bounds__(256) void permute_simple_kernel(const float2* __restrict__ in,
                                                              void* __restrict__ out,
-                                                             PermSimpleArgs P, int64_t n) {
+                                                             PermSimpleArgs P, int64_t n,
+                                                             const uint32_t* __restrict__ smax) {
+  const float scale = NP == kF16 ? operand_scale(smax) : 1.f;
   for (int64_t o = int64_t(blockIdx.x) * 256 + threadIdx.x; o < n; o += int64_t(gridDim.x) * 256) {
     int64_t off = o;
     if (!P.identity) {
@@ -148,12 +190,13 @@ __global__ __launch_bounds__(256) void permute_simple_kernel(const float2* __res
       for (int j = 0; j < P.nb; ++j)
         if (P.src[j] >= 0 && ((o >> j) & 1)) off |= int64_t(1) << P.src[j];
     }
-    put<NP>(out, P.plane, o, in[off]);
+    put<NP>(out, P.plane, o, in[off], scale);
   }
 }
 
 template <int NP>
-static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d, hipStream_t s) {
+static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d, const uint32_t* smax,
+                              hipStream_t s) {
   const int nb = d.nb;
   const int64_t n = int64_t(1) << nb;
   bool is_perm = d.nb_in == nb;
@@ -179,7 +222,7 @@ static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d,
     P.plane = n;
     for (int j = 0; j < kMaxBits; ++j) P.src[j] = j < nb ? d.src[j] : -1;
     const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap() * 2);
-    permute_simple_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, n);
+    permute_simple_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, n, smax);
     TN_HIP(hipGetLastError());
     return;
   }
@@ -219,16 +262,46 @@ static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d,
   P.rb = rb;
   P.n_tiles = int64_t(1) << rb;
   const int64_t blocks = std::min<int64_t>(P.n_tiles, 256 * 32);
-  permute_tiled_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P);
+  permute_tiled_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, smax);
   TN_HIP(hipGetLastError());
 }
 
-void launch_permute(const float2* in, void* out, const PermuteDesc& d, hipStream_t s) {
+__global__ void scale_clear_kernel(uint32_t* slot) { *slot = 0u; }
+
+// Largest |re|, |im| of n complex values, as float bits (order-preserving for
+// non-negative floats) combined into *slot with an atomic max.
+__global__ __launch_bounds__(256) void maxabs_kernel(const float2* __restrict__ in, int64_t n,
+                                                     uint32_t* __restrict__ slot) {
+  float m = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const float2 v = in[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __shared__ float part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(slot, __float_as_uint(fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]))));
+}
+
+void launch_permute(const float2* in, void* out, const PermuteDesc& d, uint32_t* smax, hipStream_t s) {
   TN_REQUIRE(d.nb >= 0 && d.nb <= 62, TN_ERR_UNSUPPORTED, "tensor too large to permute");
+  if (d.f16) {
+    TN_REQUIRE(d.np == 2 && smax != nullptr, TN_ERR_ARG, "internal: fp16 planes need a scale slot");
+    const int64_t n_in = int64_t(1) << d.nb_in;
+    scale_clear_kernel<<<1, 1, 0, s>>>(smax);
+    const int64_t blocks = std::min<int64_t>(ceil_div(n_in, 256), grid_cap());
+    maxabs_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, n_in, smax);
+    TN_HIP(hipGetLastError());
+    launch_permute_np<kF16>(in, out, d, smax, s);
+    return;
+  }
   switch (d.np) {
-    case 0: launch_permute_np<0>(in, out, d, s); break;
-    case 2: launch_permute_np<2>(in, out, d, s); break;
-    case 3: launch_permute_np<3>(in, out, d, s); break;
+    case 0: launch_permute_np<0>(in, out, d, nullptr, s); break;
+    case 2: launch_permute_np<2>(in, out, d, nullptr, s); break;
+    case 3: launch_permute_np<3>(in, out, d, nullptr, s); break;
     default: throw Error(TN_ERR_ARG, "internal: bad plane count");
   }
 }
@@ -335,6 +408,7 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
@@ -561,6 +635,8 @@ struct PackedArgs {
   int tiles_m, tiles_n;
   int regions;                 // 1: XCD region order (see packed_tile_of)
   int64_t plane_a, plane_b;
+  const uint32_t* smax_a;      // split-FP16: operand max bits (scale 2^s); else null
+  const uint32_t* smax_b;
 };
 
 // Block -> output tile.  Workgroups are dispatched round-robin over the 8
@@ -611,7 +687,7 @@ __device__ __forceinline__ int lds_word(int r, int c) {
 // One K tile of the packed GEMM from LDS: per K step of 8 complex values,
 // the A and B fragments of every plane, the B block-form swizzle, and one
 // v_mfma_f32_32x32x16_bf16 per product pair and MFMA tile.
-template <int BM, int BN, int BK, int NP, int TM, int TN>
+template <int BM, int BN, int BK, int NP, int TM, int TN, bool F16>
 __device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32_t* Bs, floatx16 (&acc)[TM][TN],
                                                 int wm0, int wn0, int li, int lh, int bn_local, uint32_t brot,
                                                 uint32_t bxor) {
@@ -642,18 +718,22 @@ __device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
+            if constexpr (F16)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(f16x8, av[pa][i]), __builtin_bit_cast(f16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
       }
   }
 }
 
 // Writes a wave's TM x TN accumulator tiles (32 rows x 16 complex columns
 // each, rows from mw, complex columns from nw) to C (row-major M x N
-// complex); entries outside M x N are skipped.
-template <int TM, int TN>
+// complex), times 2^shift; entries outside M x N are skipped.
+template <int TM, int TN, bool F16>
 __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[TM][TN], int64_t mw, int64_t nw,
-                                               int lh, int bn_local, int bt, int64_t M, int64_t N) {
+                                               int lh, int bn_local, int bt, int64_t M, int64_t N, int shift) {
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -662,11 +742,16 @@ __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[
       for (int r = 0; r < 16; ++r) {
         const int64_t m = mw + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
         const int64_t n = nw + j * 16 + bn_local;
-        if (m < M && n < N) Cf[(m * N + n) * 2 + bt] = acc[i][j][r];
+        if (m < M && n < N) Cf[(m * N + n) * 2 + bt] = F16 ? ldexpf(acc[i][j][r], shift) : acc[i][j][r];
       }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+// Undoes the two operand scales of a split-FP16 GEMM.
+__device__ __forceinline__ int packed_shift(const PackedArgs& P) {
+  return P.smax_a ? -(f16_scale_exp(*P.smax_a) + f16_scale_exp(*P.smax_b)) : 0;
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int NP, bool F16>
 __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint32_t* __restrict__ Ap,
                                                           const uint32_t* __restrict__ Bp,
                                                           float2* __restrict__ C, PackedArgs P) {
@@ -780,7 +865,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
 
   auto multiply = [&](int buf) {
     const uint32_t* As = smem + buf * STAGE;
-    packed_multiply<BM, BN, BK, NP, TM, TN>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
+    packed_multiply<BM, BN, BK, NP, TM, TN, F16>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
   };
 
   // K tile t (word offset kl = t BK) is multiplied from stage t % 2 while
@@ -800,8 +885,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
     buf ^= 1;
   }
 
-  packed_store_c<TM, TN>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
-                         acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N);
+  packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
+                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P));
 }
 
 // Direct-to-LDS variant for exactly tiled GEMMs (M % BM == N % BN == 0 and
@@ -814,7 +899,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
 // Synchronisation per tile: wait until this wave's copies of tile t are done
 // (the ones of tile t + 1 may still be in flight), then one barrier, which
 // also frees the stage tile t - 1 occupied.
-template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+template <int BM, int BN, int BK, int WGM, int WGN, int NP, bool F16>
 __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const uint32_t* __restrict__ Ap,
                                                               const uint32_t* __restrict__ Bp,
                                                               float2* __restrict__ C, PackedArgs P) {
@@ -927,12 +1012,12 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
     const int prev = stage == 0 ? 2 : stage - 1;
     if (t + 2 < ntiles) issue(t + 2, prev);
     const uint32_t* As = smem + stage * STAGE;
-    packed_multiply<BM, BN, BK, NP, TM, TN>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
+    packed_multiply<BM, BN, BK, NP, TM, TN, F16>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
     stage = stage == 2 ? 0 : stage + 1;
   }
 
-  packed_store_c<TM, TN>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
-                         acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N);
+  packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
+                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P));
 #endif
 }
 
@@ -963,13 +1048,15 @@ constexpr TileShape kPackedTiles[6] = {{256, 16}, {128, 32}, {128, 64}, {256, 12
 
 // Tile 5 (direct-to-LDS copies) needs whole tiles in M, N and K.
 bool dma_exact(const GemmDesc& g) {
-  return g.packed && g.precision == TN_PREC_BF16X3 && g.M % 256 == 0 && g.N % 128 == 0 && g.K % 16 == 0;
+  return g.packed && (g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_F16X3) && g.M % 256 == 0 &&
+         g.N % 128 == 0 && g.K % 16 == 0;
 }
 
 int default_tile(const GemmDesc& g) {
   if (g.N <= 16) return 0;
   if (g.N <= 32) return 1;
-  if (g.packed && g.precision == TN_PREC_BF16X3 && g.N >= 128 && g.M >= 256 && g.M * g.N >= (int64_t(1) << 22))
+  if (g.packed && (g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_F16X3) && g.N >= 128 && g.M >= 256 &&
+      g.M * g.N >= (int64_t(1) << 22))
     return dma_exact(g) ? 5 : 3;
   return 2;
 }
@@ -1029,56 +1116,56 @@ static void launch_gemm_prec(const float2* A, const float2* B, float2* C, const 
   }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+template <int BM, int BN, int BK, int WGM, int WGN, int NP, bool F16>
 static void launch_packed_cfg(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
                               int64_t batch, hipStream_t s) {
   constexpr size_t lds = size_t(2) * NP * (BM + BN) * BK * sizeof(uint32_t);
   static_assert(lds <= 160 * 1024, "LDS tile exceeds the 160 KB of a CU");
   static bool attr_set = false;
   if (!attr_set) {
-    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP>),
+    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP, F16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     attr_set = true;
   }
   dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
-  gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
+  gemm_packed_kernel<BM, BN, BK, WGM, WGN, NP, F16><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int NP>
+template <int BM, int BN, int BK, int WGM, int WGN, int NP, bool F16>
 static void launch_packed_dma(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
                               int64_t batch, hipStream_t s) {
   constexpr size_t lds = size_t(3) * NP * (BM + BN) * BK * sizeof(uint32_t);
   static_assert(lds <= 160 * 1024, "LDS stages exceed the 160 KB of a CU");
   static bool attr_set = false;
   if (!attr_set) {
-    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP>),
+    TN_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP, F16>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     attr_set = true;
   }
   dim3 grid(unsigned(P.tiles_m * P.tiles_n), 1, unsigned(batch * P.ksplit));
-  gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
+  gemm_packed_dma_kernel<BM, BN, BK, WGM, WGN, NP, F16><<<grid, WGM * WGN * 64, lds, s>>>(A, B, C, P);
 }
 
-template <int NP, int BK>
+template <int NP, int BK, bool F16>
 static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, const PackedArgs& P,
                              int64_t batch, int id, hipStream_t s) {
   switch (id) {
-    case 0: launch_packed_cfg<256, 16, BK, 4, 1, NP>(A, B, C, P, batch, s); break;
-    case 1: launch_packed_cfg<128, 32, BK, 4, 1, NP>(A, B, C, P, batch, s); break;
+    case 0: launch_packed_cfg<256, 16, BK, 4, 1, NP, F16>(A, B, C, P, batch, s); break;
+    case 1: launch_packed_cfg<128, 32, BK, 4, 1, NP, F16>(A, B, C, P, batch, s); break;
     case 3:
-      if constexpr (NP == 2) { launch_packed_cfg<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s); break; }
+      if constexpr (NP == 2) { launch_packed_cfg<256, 128, 16, 4, 2, 2, F16>(A, B, C, P, batch, s); break; }
       [[fallthrough]];
-    case 4: launch_packed_cfg<128, 128, 16, 2, 2, NP>(A, B, C, P, batch, s); break;
+    case 4: launch_packed_cfg<128, 128, 16, 2, 2, NP, F16>(A, B, C, P, batch, s); break;
     case 5:
-      if constexpr (NP == 2) { launch_packed_dma<256, 128, 16, 4, 2, 2>(A, B, C, P, batch, s); break; }
-      launch_packed_cfg<128, 128, 16, 2, 2, NP>(A, B, C, P, batch, s);
+      if constexpr (NP == 2) { launch_packed_dma<256, 128, 16, 4, 2, 2, F16>(A, B, C, P, batch, s); break; }
+      launch_packed_cfg<128, 128, 16, 2, 2, NP, F16>(A, B, C, P, batch, s);
       break;
-    default: launch_packed_cfg<128, 64, BK, 2, 2, NP>(A, B, C, P, batch, s); break;
+    default: launch_packed_cfg<128, 64, BK, 2, 2, NP, F16>(A, B, C, P, batch, s); break;
   }
 }
 
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
-                 hipStream_t s) {
+                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s) {
   TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1, TN_ERR_ARG, "bad GEMM shape");
   TN_REQUIRE(!g.packed || g.K % 4 == 0, TN_ERR_ARG, "internal: packed GEMM needs K % 4 == 0");
   const int id = tile_of(g);
@@ -1102,6 +1189,8 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.K = g.K;
     P.plane_a = g.plane_a;
     P.plane_b = g.plane_b;
+    P.smax_a = nullptr;
+    P.smax_b = nullptr;
     P.ksplit = ksplit;
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
@@ -1112,8 +1201,16 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
                "packed GEMM: K too long for one panel");
     const uint32_t* Ap = reinterpret_cast<const uint32_t*>(A);
     const uint32_t* Bp = reinterpret_cast<const uint32_t*>(B);
-    if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16>(Ap, Bp, out, P, g.batch, id, s);
-    else launch_packed_np<2, 32>(Ap, Bp, out, P, g.batch, id, s);
+    if (g.precision == TN_PREC_BF16X6) {
+      launch_packed_np<3, 16, false>(Ap, Bp, out, P, g.batch, id, s);
+    } else if (g.precision == TN_PREC_F16X3) {
+      TN_REQUIRE(smax_a && smax_b, TN_ERR_ARG, "internal: split-FP16 GEMM needs operand scales");
+      P.smax_a = smax_a;
+      P.smax_b = smax_b;
+      launch_packed_np<2, 32, true>(Ap, Bp, out, P, g.batch, id, s);
+    } else {
+      launch_packed_np<2, 32, false>(Ap, Bp, out, P, g.batch, id, s);
+    }
   } else {
     const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision
                                                                                      : TN_PREC_FP32;

@@ -16,13 +16,17 @@ constexpr int kMaxBits = 64;
 // src[j] == -1 broadcasts (stride 0).  `nb` output bits; `nb_in` input bits.
 // np = 2 or 3 additionally splits every entry into np bfloat16 parts and
 // writes np planes of packed (re | im << 16) words, plane p at out + p * 2^nb.
+// f16 = 1 (np = 2): the parts are fp16 parts of the entry times 2^s, with s
+// set from the largest |re|, |im| of the input, whose float bits the call
+// first writes to *smax (a 4-byte device slot; null otherwise).
 struct PermuteDesc {
   int nb = 0;
   int nb_in = 0;
   int np = 0;
+  int f16 = 0;
   int8_t src[kMaxBits];
 };
-void launch_permute(const float2* in, void* out, const PermuteDesc& d, hipStream_t s);
+void launch_permute(const float2* in, void* out, const PermuteDesc& d, uint32_t* smax, hipStream_t s);
 
 // C[m * 2^nn + n] = sum_k A[expand(m) + kscat(k)] * B[bscat(k, n)]
 //   A: `a_bits` bits; K bits of A at positions kpos (ascending), others are M.
@@ -47,12 +51,14 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 // Complex GEMM C[b][m][n] = sum_k A[b](m,k) * B[b](k,n), contiguous operands.
 // transA = 0: A[b][m][k]; 1: A[b][k][m].  transB = 0: B[b][k][n]; 1: B[b][n][k].
 // packed = 1: A and B are bf16 planes from launch_permute (np = 2 for
-// BF16X3, 3 for BF16X6) in the layouts [b][M][K] and [b][N][K] (k fastest);
-// plane_a / plane_b are the plane strides in words; K must be a multiple of 4.
+// BF16X3, 3 for BF16X6; fp16 planes for F16X3, whose operand max slots
+// smax_a / smax_b give the scales to undo) in the layouts [b][M][K] and
+// [b][N][K] (k fastest); plane_a / plane_b are the plane strides in words;
+// K must be a multiple of 4.
 struct GemmDesc {
   int64_t M = 1, N = 1, K = 1, batch = 1;
   int transA = 0, transB = 0;
-  int precision = 0;       // TN_PREC_FP32 / BF16X3 / BF16X6
+  int precision = 0;       // TN_PREC_FP32 / BF16X3 / BF16X6 / F16X3
   int packed = 0;
   int64_t plane_a = 0, plane_b = 0;
   int tile = -1;           // block tile id (-1: shape heuristic)
@@ -64,7 +70,7 @@ size_t gemm_workspace_bytes(const GemmDesc& g);
 std::vector<int> gemm_tile_candidates(const GemmDesc& g);
 int gemm_tile_of(const GemmDesc& g);
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
-                 hipStream_t s);
+                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s);
 
 // Gather every leaf of one job into the leaf arena: fixed labels take their
 // value from the job's bit-string (kind 0) or slice index (kind 1).

@@ -592,7 +592,7 @@ tn_status tn_mps_apply_gate(tn_mps* m, int32_t site, const double* gate, int32_t
     g.K = cm;
     g.precision = TN_PREC_FP32;
     TN_REQUIRE(gemm_workspace_bytes(g) <= m->gemm_work_bytes, TN_ERR_WORKSPACE, "MPS GEMM scratch too small");
-    launch_gemm(m->site[site], m->site[site + 1], m->theta, g, m->gemm_work, s);
+    launch_gemm(m->site[site], m->site[site + 1], m->theta, g, m->gemm_work, nullptr, nullptr, s);
     Mat4 G;
     read_mat(gate, 4, G.g);
     const int rows = 2 * cl, cols = 2 * cr;

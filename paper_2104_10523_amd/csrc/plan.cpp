@@ -81,12 +81,13 @@ double p2(size_t bits) { return std::ldexp(1.0, int(bits)); }
 // GEMMs) instead of complex64.
 TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
                   std::vector<PlanOp>& ops, std::vector<int64_t>* scratch, int out_buf = -1,
-                  int64_t out_off = 0, int np = 0) {
+                  int64_t out_off = 0, int np = 0, bool f16 = false) {
   PlanOp op;
   op.kind = OP_PERMUTE;
   op.pm.nb = int(target.size());
   op.pm.nb_in = int(in.labels.size());
   op.pm.np = np;
+  op.pm.f16 = f16 ? 1 : 0;
   TN_REQUIRE(op.pm.nb <= kMaxBits && op.pm.nb_in <= kMaxBits, TN_ERR_UNSUPPORTED, "rank > 64");
   for (int j = 0; j < op.pm.nb; ++j)
     op.pm.src[j] = int8_t(pos_of(in.labels, target[op.pm.nb - 1 - j]));
@@ -100,6 +101,11 @@ TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
     const int64_t elems = int64_t(1) << op.pm.nb;
     out.off = arena.alloc(np ? (elems * np + 1) / 2 : elems);
     scratch->push_back(out.off);
+  }
+  if (f16) {
+    op.smax = arena.alloc(1);
+    scratch->push_back(op.smax);
+    out.smax = op.smax;
   }
   op.a_buf = in.buf;
   op.a_off = in.off;
@@ -149,7 +155,7 @@ TRef emit_sum_out(const TRef& X, const std::vector<int>& dang, Arena& arena,
 
 int resolve_precision(int precision, int64_t M, int64_t N, int64_t K) {
   if (precision != TN_PREC_AUTO) return precision;
-  return (K >= 64 && M >= 1024 && N >= 64) ? TN_PREC_BF16X3 : TN_PREC_FP32;
+  return (K >= 64 && M >= 1024 && N >= 64) ? TN_PREC_F16X3 : TN_PREC_FP32;
 }
 
 }  // namespace
@@ -298,13 +304,16 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   auto lowest = [](const TRef& T) { return T.labels.empty() ? -1 : T.labels.back(); };
   int transA = 0, transB = 0;
   TRef Ap = A, Bp = B;
-  const int prec = resolve_precision(precision, Mn, Nn, Kn);
-  const bool packed = (prec == TN_PREC_BF16X3 || prec == TN_PREC_BF16X6) && Kn % 4 == 0 &&
-                      !(Mn == 1 && Nn == 1);
+  int prec = resolve_precision(precision, Mn, Nn, Kn);
+  const bool packable = Kn % 4 == 0 && !(Mn == 1 && Nn == 1);
+  // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
+  if (prec == TN_PREC_F16X3 && !packable) prec = TN_PREC_FP32;
+  const bool packed = (prec == TN_PREC_BF16X3 || prec == TN_PREC_BF16X6 || prec == TN_PREC_F16X3) && packable;
   const int np = prec == TN_PREC_BF16X6 ? 3 : 2;
+  const bool f16 = prec == TN_PREC_F16X3;
   if (packed) {
-    Ap = emit_permute(A, cat({b_o, m_o, k_o}), arena, ops, scratch, -1, 0, np);
-    Bp = emit_permute(B, cat({b_o, n_o, k_o}), arena, ops, scratch, -1, 0, np);
+    Ap = emit_permute(A, cat({b_o, m_o, k_o}), arena, ops, scratch, -1, 0, np, f16);
+    Bp = emit_permute(B, cat({b_o, n_o, k_o}), arena, ops, scratch, -1, 0, np, f16);
     transA = 0;
     transB = 1;
   } else if (Mn == 1 && Nn == 1) {
@@ -363,6 +372,8 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.gm.packed = packed ? 1 : 0;
     op.gm.plane_a = Bn * Mn * Kn;
     op.gm.plane_b = Bn * Nn * Kn;
+    op.smax_a = Ap.smax;
+    op.smax_b = Bp.smax;
     op.gm.tile = tuned_tile(op.gm);
     // room for the split-K partials of any candidate tile, so the
     // autotuner may pick any of them later
@@ -385,6 +396,12 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   return out;
 }
 
+namespace {
+uint32_t* slot(float2* const bufs[6], int64_t off) {
+  return off >= 0 ? reinterpret_cast<uint32_t*>(bufs[BUF_WORK] + off) : nullptr;
+}
+}  // namespace
+
 void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s) {
   for (const PlanOp& op : ops) {
     const float2* a = bufs[op.a_buf] + op.a_off;
@@ -393,8 +410,8 @@ void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t 
     void* w = op.work_off >= 0 ? static_cast<void*>(bufs[BUF_WORK] + op.work_off) : nullptr;
     switch (op.kind) {
       case OP_APPLY: launch_apply_small(a, b, c, op.ap, s); break;
-      case OP_PERMUTE: launch_permute(a, c, op.pm, s); break;
-      case OP_GEMM: launch_gemm(a, b, c, op.gm, w, s); break;
+      case OP_PERMUTE: launch_permute(a, c, op.pm, slot(bufs, op.smax), s); break;
+      case OP_GEMM: launch_gemm(a, b, c, op.gm, w, slot(bufs, op.smax_a), slot(bufs, op.smax_b), s); break;
       case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, w, s); break;
     }
   }
@@ -448,9 +465,11 @@ void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hip
         // every address of the proxy stays inside the op's real operands
         g.K = std::min<int64_t>(g.K, 512);
         if (gemm_workspace_bytes(g) > size_t(op.work_elems) * sizeof(float2)) continue;
-        launch_gemm(a, b, c, g, w, s);  // warm
+        const uint32_t* sa = slot(bufs, op.smax_a);
+        const uint32_t* sb = slot(bufs, op.smax_b);
+        launch_gemm(a, b, c, g, w, sa, sb, s);  // warm
         TN_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch_gemm(a, b, c, g, w, s);
+        for (int r = 0; r < reps; ++r) launch_gemm(a, b, c, g, w, sa, sb, s);
         TN_HIP(hipEventRecord(e1, s));
         TN_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -572,7 +591,9 @@ AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, 
       P.bytes_per_job += op.bytes;
       if (op.kind == OP_GEMM) {
         P.gemm_ops++;
-        const double u = op.gm.precision == TN_PREC_BF16X3 ? std::ldexp(1.0, -17) : std::ldexp(1.0, -24);
+        const double u = op.gm.precision == TN_PREC_BF16X3   ? std::ldexp(1.0, -17)
+                         : op.gm.precision == TN_PREC_F16X3 ? std::ldexp(1.0, -21)
+                                                            : std::ldexp(1.0, -24);
         err2 += u * u * (1.0 + std::log2(double(op.gm.K)));
       } else if (op.kind != OP_PERMUTE) {
         err2 += std::ldexp(1.0, -48);

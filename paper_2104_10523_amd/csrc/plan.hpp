@@ -18,6 +18,7 @@ struct TRef {
   int buf = BUF_WORK;
   int64_t off = 0;            // element offset in the buffer
   std::vector<int> labels;    // layout, outermost first; every label is one bit
+  int64_t smax = -1;          // split-FP16 planes: BUF_WORK offset of the max slot
 };
 
 enum OpKind : int { OP_APPLY = 0, OP_PERMUTE = 1, OP_GEMM = 2, OP_DOT = 3 };
@@ -28,6 +29,8 @@ struct PlanOp {
   int64_t a_off = 0, b_off = 0, c_off = 0;
   int64_t work_off = -1;      // split-K / dot scratch (elements of float2)
   int64_t work_elems = 0;     // size of that scratch
+  int64_t smax = -1;          // PERMUTE to fp16 planes: its max slot (BUF_WORK offset)
+  int64_t smax_a = -1, smax_b = -1;   // GEMM on fp16 planes: the operands' slots
   ApplySmallDesc ap;
   PermuteDesc pm;
   GemmDesc gm;

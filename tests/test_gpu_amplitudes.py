@@ -114,7 +114,7 @@ def test_ghz_and_qft(gpu, workspace):
     check_amps(got[0], ref, n)
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6", "auto"])
+@pytest.mark.parametrize("precision", ["bf16x3", "bf16x6", "f16x3", "auto"])
 def test_precisions_c1(gpu, workspace, precision):
     n, ops = grid_random_circuit(3, 4, 8, 1)
     got, rep, _ = amps(n, ops, [-1] * n, precision=precision)

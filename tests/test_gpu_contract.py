@@ -3,8 +3,12 @@
 Label sets are drawn at random: batch, contracted (K), free (M, N) and
 summed-out labels in shuffled orders, so every kernel path is exercised:
 bit-addressed small-operand apply, permute + MFMA GEMM (FP32, BF16x3,
-BF16x6), split-K, dot, outer product, scalar output, pure permutation and
-ragged tiles.
+BF16x6, scaled FP16x3), split-K, dot, outer product, scalar output, pure
+permutation and ragged tiles.
+
+Tolerances (relative L2 over C): FP32 and BF16x6 2e-6; BF16x3 2e-5 (a
+bfloat16 hi + lo split keeps 16 significant bits, products within 2^-17);
+FP16x3 3e-6 (fp16 hi + lo keeps 22 bits, products within 2^-21).
 """
 
 import zlib
@@ -18,7 +22,7 @@ from tests.helpers import l2_rel, floored_rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 2e-6, "bf16x6": 2e-6, "bf16x3": 2e-5}
+TOL = {"fp32": 2e-6, "bf16x6": 2e-6, "bf16x3": 2e-5, "f16x3": 3e-6}
 
 
 def make_case(seed, nb=0, nm=0, nk=0, nn=0, da=0, db=0, wide=None, shuffle=True):
@@ -79,7 +83,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x6", "f16x3"])
 @pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
 def test_contract_pair(gpu, workspace, name, kw, precision):
     seed = zlib.crc32(f"{name}/{precision}".encode()) % 10000
@@ -110,7 +114,7 @@ def test_contract_pair_large_mfma(gpu, workspace):
     idx = [tuple(int(rng.integers(0, e)) for e in shape_c) for _ in range(2048)]
     ref = contract_entries(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc, idx)
     rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
-    for prec in ("fp32", "bf16x3", "bf16x6"):
+    for prec in ("fp32", "bf16x3", "bf16x6", "f16x3"):
         got = run(A, la, B, lb, lc, shape_c, prec)
         g = np.array([got[i] for i in idx])
         e2 = l2_rel(g, ref)
@@ -118,6 +122,33 @@ def test_contract_pair_large_mfma(gpu, workspace):
         print(f"large {prec}: l2 {e2:.2e} floored {ef:.2e}", flush=True)
         assert e2 <= TOL[prec], (prec, e2)
         assert ef <= 20 * TOL[prec], (prec, ef)
+
+
+@pytest.mark.parametrize("sa,sb", [(1e-25, 1e20), (1e30, 1e-30), (3e-7, 5e4)])
+def test_contract_pair_f16_operand_scaling(gpu, workspace, sa, sb):
+    """Split-FP16 scales each operand by a power of two from its largest
+    entry, so magnitudes far outside fp16's range (6e-8 .. 65504) keep their
+    accuracy; the product's scale is undone exactly."""
+    A, la, B, lb, lc, shape_c = make_case(31, nm=9, nk=7, nn=8)
+    A = (A * np.float32(sa)).astype(np.complex64)
+    B = (B * np.float32(sb)).astype(np.complex64)
+    got = run(A, la, B, lb, lc, shape_c, "f16x3")
+    ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+    assert np.all(np.isfinite(got))
+    assert l2_rel(got, ref) <= TOL["f16x3"], l2_rel(got, ref)
+
+
+def test_contract_pair_f16_wide_range_and_zero(gpu, workspace):
+    """Entries spanning eight decades within one operand stay accurate in
+    the L2 sense; an all-zero operand gives exact zeros."""
+    A, la, B, lb, lc, shape_c = make_case(32, nm=8, nk=8, nn=8)
+    rng = np.random.default_rng(3)
+    A = (A * (10.0 ** rng.uniform(-8, 0, A.shape))).astype(np.complex64)
+    got = run(A, la, B, lb, lc, shape_c, "f16x3")
+    ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+    assert l2_rel(got, ref) <= TOL["f16x3"], l2_rel(got, ref)
+    got0 = run(np.zeros_like(A), la, B, lb, lc, shape_c, "f16x3")
+    assert np.all(got0 == 0)
 
 
 def test_contract_pair_errors(gpu, workspace):

@@ -16,7 +16,8 @@ project onto nearly orthogonal states has an exact value far below what any
 finite-precision contraction resolves).  Bound per precision: the 1e-5
 target, or 4x the library's a-priori estimate when that is larger (it sums
 u^2 (1 + log2 K) over the plan's GEMMs, u = 2^-17 for split-BF16x3, whose
-estimate at this depth is 1.4e-4).
+estimate at this depth is 1.4e-4; 2^-21 for scaled split-FP16x3, 8.5e-6;
+2^-24 for FP32).
 """
 
 import numpy as np
@@ -30,7 +31,7 @@ pytestmark = pytest.mark.gpu
 PATH_OPTS = dict(trials=32, seed=1, temperature=0.5, mem_budget_bytes=64.0 * 2 ** 30)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3"])
 def test_rqc_7x7_14_full_size_slices(gpu, workspace, precision):
     import torch
     import paper_2104_10523_amd as tn
