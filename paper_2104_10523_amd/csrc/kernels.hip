@@ -684,9 +684,57 @@ __device__ __forceinline__ int lds_word(int r, int c) {
   return r * BK + 4 * (c ^ f);
 }
 
-// One K tile of the packed GEMM from LDS: per K step of 8 complex values,
-// the A and B fragments of every plane, the B block-form swizzle, and one
-// v_mfma_f32_32x32x16_bf16 per product pair and MFMA tile.
+// Fragments of one K step (8 complex values) of a wave's TM x TN MFMA tiles
+// from an LDS stage: every plane's A rows and B columns, raw words.
+template <int BM, int BN, int BK, int NP, int TM, int TN>
+__device__ __forceinline__ void packed_load_frags(const uint32_t* As, const uint32_t* Bs, int kk, u32x4 (&av)[NP][TM],
+                                                  u32x4 (&bv)[NP][TN], int wm0, int wn0, int li, int lh,
+                                                  int bn_local) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+      av[p][i] = *reinterpret_cast<const u32x4*>(As + lds_word<BK>(p * BM + wm0 + i * 32 + li, kk / 4 + lh));
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+      bv[p][j] = *reinterpret_cast<const u32x4*>(Bs + lds_word<BK>(p * BN + wn0 + j * 16 + bn_local, kk / 4 + lh));
+  }
+}
+
+// The B block-form swizzle and one v_mfma_f32_32x32x16_bf16 (or _f16) per
+// product pair (pa, pb), pa + pb < NP, smallest first, and MFMA tile; the
+// tile loops are innermost so consecutive MFMAs use independent accumulators.
+template <int NP, int TM, int TN, bool F16>
+__device__ __forceinline__ void packed_mma(const u32x4 (&av)[NP][TM], u32x4 (&bv)[NP][TN], floatx16 (&acc)[TM][TN],
+                                           uint32_t brot, uint32_t bxor) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[p][j][q] = __builtin_amdgcn_alignbit(bv[p][j][q], bv[p][j][q], brot) ^ bxor;
+#pragma unroll
+  for (int s2 = NP - 1; s2 >= 0; --s2)
+#pragma unroll
+    for (int pa = 0; pa <= s2; ++pa) {
+      const int pb = s2 - pa;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (F16)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, av[pa][i]),
+                                                               __builtin_bit_cast(f16x8, bv[pb][j]), acc[i][j], 0,
+                                                               0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[pa][i]),
+                                                                __builtin_bit_cast(bf16x8, bv[pb][j]), acc[i][j],
+                                                                0, 0, 0);
+        }
+    }
+}
+
+// One K tile of the packed GEMM from an LDS stage, K step by K step.
 template <int BM, int BN, int BK, int NP, int TM, int TN, bool F16>
 __device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32_t* Bs, floatx16 (&acc)[TM][TN],
                                                 int wm0, int wn0, int li, int lh, int bn_local, uint32_t brot,
@@ -694,37 +742,8 @@ __device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32
 #pragma unroll
   for (int kk = 0; kk < BK; kk += 8) {
     u32x4 av[NP][TM], bv[NP][TN];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        av[p][i] = *reinterpret_cast<const u32x4*>(As + lds_word<BK>(p * BM + wm0 + i * 32 + li, kk / 4 + lh));
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        u32x4 w = *reinterpret_cast<const u32x4*>(Bs + lds_word<BK>(p * BN + wn0 + j * 16 + bn_local, kk / 4 + lh));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_alignbit(w[q], w[q], brot) ^ bxor;
-        bv[p][j] = w;
-      }
-    }
-    // product pairs (pa, pb) with pa + pb < NP, smallest first; the tile
-    // loops are innermost so consecutive MFMAs use independent accumulators
-#pragma unroll
-    for (int s2 = NP - 1; s2 >= 0; --s2)
-#pragma unroll
-      for (int pa = 0; pa <= s2; ++pa) {
-        const int pb = s2 - pa;
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            if constexpr (F16)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                  __builtin_bit_cast(f16x8, av[pa][i]), __builtin_bit_cast(f16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                  __builtin_bit_cast(bf16x8, av[pa][i]), __builtin_bit_cast(bf16x8, bv[pb][j]), acc[i][j], 0, 0, 0);
-      }
+    packed_load_frags<BM, BN, BK, NP, TM, TN>(As, Bs, kk, av, bv, wm0, wn0, li, lh, bn_local);
+    packed_mma<NP, TM, TN, F16>(av, bv, acc, brot, bxor);
   }
 }
 
@@ -913,7 +932,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
   static_assert(AB % NW == 0 && BB % NW == 0, "row blocks must split evenly over the waves");
   constexpr int A_PW = NP * AB / NW, B_PW = NP * BB / NW;   // copies per wave per K tile
   constexpr int PER_TILE = A_PW + B_PW;
-  static_assert(PER_TILE <= 15, "vmcnt immediate");
+  static_assert(2 * PER_TILE <= 15, "vmcnt immediate");
   constexpr int A_WORDS = NP * BM * BK, B_WORDS = NP * BN * BK;
   constexpr int STAGE = A_WORDS + B_WORDS;
   extern __shared__ __attribute__((aligned(16))) uint32_t smem[];
@@ -999,21 +1018,42 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
   };
-  if (ntiles > 0) issue(0, 0);
-  if (ntiles > 1) issue(1, 1);
-  int stage = 0;    // stage of tile t; tile t + 2 goes to the one before it
-  for (int t = 0; t < ntiles; ++t) {
-    if (t + 1 < ntiles) {
-      __builtin_amdgcn_s_waitcnt(0x0F70 | PER_TILE);   // vmcnt(PER_TILE): tile t landed
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt(0)
-    }
+  // Per tile t (stage t % 3, fragments of its two K steps in registers F0 and
+  // F1): read F1, multiply F0; then wait for tile t + 1 and pass the barrier
+  // while those MFMAs run (every wave is done reading stage t % 3, so the copy
+  // of tile t + 3 goes there), read the next tile's F0, multiply F1.
+  static_assert(BK == 16, "two K steps per tile");
+  u32x4 a0[NP][TM], b0[NP][TN], a1[NP][TM], b1[NP][TN];
+  for (int t = 0; t < 3 && t < ntiles; ++t) issue(t, t);
+  if (ntiles > 0) {
+    if (ntiles > 2) __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * PER_TILE));
+    else if (ntiles > 1) __builtin_amdgcn_s_waitcnt(0x0F70 | PER_TILE);
+    else __builtin_amdgcn_s_waitcnt(0x0F70);
     barrier();
-    const int prev = stage == 0 ? 2 : stage - 1;
-    if (t + 2 < ntiles) issue(t + 2, prev);
+    packed_load_frags<BM, BN, BK, NP, TM, TN>(smem, smem + A_WORDS, 0, a0, b0, wm0, wn0, li, lh, bn_local);
+  }
+  int stage = 0;
+  for (int t = 0; t < ntiles; ++t) {
     const uint32_t* As = smem + stage * STAGE;
-    packed_multiply<BM, BN, BK, NP, TM, TN, F16>(As, As + A_WORDS, acc, wm0, wn0, li, lh, bn_local, brot, bxor);
-    stage = stage == 2 ? 0 : stage + 1;
+    packed_load_frags<BM, BN, BK, NP, TM, TN>(As, As + A_WORDS, 8, a1, b1, wm0, wn0, li, lh, bn_local);
+    __builtin_amdgcn_sched_barrier(0);
+    packed_mma<NP, TM, TN, F16>(a0, b0, acc, brot, bxor);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < ntiles) {
+      // this wave's reads of stage t % 3 are complete and tile t + 1 landed
+      // (tile t + 2's copies may still be in flight)
+      if (t + 2 < ntiles) __builtin_amdgcn_s_waitcnt(0x0070 | PER_TILE);   // vmcnt(PER_TILE), lgkmcnt(0)
+      else __builtin_amdgcn_s_waitcnt(0x0070);                             // vmcnt(0), lgkmcnt(0)
+      barrier();
+      if (t + 3 < ntiles) issue(t + 3, stage);
+      const int next = stage == 2 ? 0 : stage + 1;
+      const uint32_t* An = smem + next * STAGE;
+      packed_load_frags<BM, BN, BK, NP, TM, TN>(An, An + A_WORDS, 0, a0, b0, wm0, wn0, li, lh, bn_local);
+      stage = next;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    packed_mma<NP, TM, TN, F16>(a1, b1, acc, brot, bxor);
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),

@@ -9,8 +9,13 @@
 // Tensors: two-qubit gates in circuit order, then lone wires in qubit order.
 // Labels are handed out as legs are created (a's output, then b's).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
+#include <exception>
 #include <limits>
+#include <mutex>
+#include <thread>
 
 #include "network.hpp"
 
@@ -290,21 +295,50 @@ PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int
 
 std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
                                                     int trials, double temperature) {
+  // Trial r draws from its own stream (seed + r * golden ratio), so the
+  // trials run on host threads in any order; the winner is the first, in
+  // trial order, of the lowest (flops, peak), the deterministic greedy path
+  // winning ties, exactly as a sequential scan would pick.
   auto best = greedy_path(pr, nullptr, temperature);
   PathStats bs = path_stats(pr, best, {});
-  double bf = bs.flops, bp = bs.peak;
-  for (int r = 0; r < trials; ++r) {
-    uint64_t g = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
-    uint64_t st = splitmix64_next(&g);
-    auto p = greedy_path(pr, &st, temperature);
-    PathStats s = path_stats(pr, p, {});
-    if (s.flops < bf || (s.flops == bf && s.peak < bp)) {
-      best = std::move(p);
-      bf = s.flops;
-      bp = s.peak;
+  if (trials <= 0) return best;
+  std::vector<std::vector<std::pair<int, int>>> paths(trials);
+  std::vector<double> fl(trials), pk(trials);
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex err_mu;
+  auto worker = [&]() {
+    for (int r; (r = next.fetch_add(1)) < trials;) {
+      try {
+        uint64_t g = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
+        uint64_t st = splitmix64_next(&g);
+        paths[r] = greedy_path(pr, &st, temperature);
+        const PathStats s = path_stats(pr, paths[r], {});
+        fl[r] = s.flops;
+        pk[r] = s.peak;
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+      }
     }
-  }
-  return best;
+  };
+  int nt = int(std::max(1u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) nt = std::min(nt, std::max(1, std::atoi(e)));
+  nt = std::min({nt, 16, trials});
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+  double bf = bs.flops, bp = bs.peak;
+  int win = -1;
+  for (int r = 0; r < trials; ++r)
+    if (fl[r] < bf || (fl[r] == bf && pk[r] < bp)) {
+      win = r;
+      bf = fl[r];
+      bp = pk[r];
+    }
+  return win < 0 ? best : std::move(paths[win]);
 }
 
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

@@ -90,9 +90,11 @@ def test_random_greedy_matches_oracle():
     onet = build_network(n, ops)
     lnet = tn.tn_build_network(n, ops)
     leaves, ext, opened = _oracle_leaves(onet)
-    for seed, T in ((1, 1.0), (77, 0.5)):
-        p = tn.tn_find_path(lnet, "random_greedy", trials=6, seed=seed, temperature=T)
-        po = random_greedy_path(leaves, ext, opened, seed=seed, trials=6, temperature=T)
+    # 40 trials spread over the library's host threads: the winner must still
+    # be the sequential scan's
+    for seed, T, trials in ((1, 1.0, 6), (77, 0.5, 6), (5, 0.5, 40)):
+        p = tn.tn_find_path(lnet, "random_greedy", trials=trials, seed=seed, temperature=T)
+        po = random_greedy_path(leaves, ext, opened, seed=seed, trials=trials, temperature=T)
         assert p.pairs == po
 
 
@@ -203,9 +205,9 @@ def test_scorer_features_match_oracle():
 def test_identity_coupled_7x7_has_benchmark_path():
     """The full-size GPU parity case (fSim(0, 0) couplers) plans exactly like
     the benchmark's 7x7 grid circuit: same pairwise path and sliced labels."""
-    opts = dict(trials=32, seed=1, temperature=0.5, mem_budget_bytes=64.0 * 2 ** 30)
+    opts = dict(trials=1024, seed=1, temperature=0.5, mem_budget_bytes=128.0 * 2 ** 30)
     n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim")
     _, ops0 = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim", fsim_params=(0.0, 0.0))
     p = tn.tn_find_path(tn.tn_build_network(n, ops), "random_greedy", **opts)
     p0 = tn.tn_find_path(tn.tn_build_network(n, ops0), "random_greedy", **opts)
-    assert p.pairs == p0.pairs and p.sliced == p0.sliced and p.cost.n_sliced == 13
+    assert p.pairs == p0.pairs and p.sliced == p0.sliced and p.cost.n_sliced == 8
