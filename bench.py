@@ -245,7 +245,11 @@ def main():
                 "amplitudes_per_s": 1.0 / (ns * float(pj.mean())),
                 "gemm_tflops": float(f32[b32].sum()) / float(os32[b32].sum()) / 1e12,
                 "speedup_of_split": float(pj.mean()) / T,
-                "slice_amplitude_rel_diff": float(abs(amps[0] - a32[0]) / max(abs(a32[0]), 1e-300))}
+                "slice_amplitude_rel_diff": float(abs(amps[0] - a32[0]) / max(abs(a32[0]), 1e-300)),
+                # floor: the RMS amplitude of one slice of a normalised state
+                "slice_amplitude_floored_diff": float(abs(amps[0] - a32[0]) /
+                                                      max(abs(a32[0]), 2.0 ** (-(n + path.cost.n_sliced) / 2))),
+                "slice_amplitude_over_floor": float(abs(a32[0]) / 2.0 ** (-(n + path.cost.n_sliced) / 2))}
         print(f"# fp32 step {pj.mean():.3f}s", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:

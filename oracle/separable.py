@@ -59,3 +59,23 @@ def separable_slice_amplitude(n: int, ops, bits: Sequence[int], fixed: Dict[int,
             nxt += 1
         amp *= state[q][int(bits[q])]
     return complex(amp)
+
+
+def dominant_bits(n: int, ops, fixed: Dict[int, int]):
+    """The bit-string with the largest |slice value| for the given bond
+    values: the product form lets each wire take its larger final component."""
+    state = [np.array([1.0, 0.0], dtype=np.complex128) for _ in range(n)]
+    nxt = 0
+    for op in ops:
+        if len(op.qubits) == 1:
+            q = op.qubits[0]
+            state[q] = gate_matrix(op.name, op.params) @ state[q]
+            continue
+        for q in op.qubits:
+            if nxt in fixed:
+                b = fixed[nxt]
+                keep = np.zeros(2, dtype=np.complex128)
+                keep[b] = state[q][b]
+                state[q] = keep
+            nxt += 1
+    return [int(np.abs(state[q][1]) > np.abs(state[q][0])) for q in range(n)]

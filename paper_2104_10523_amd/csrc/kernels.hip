@@ -417,6 +417,8 @@ struct GemmArgs {
   int ksplit;
   int transA, transB;
   int tiles_m, tiles_n;
+  int64_t kbase;        // first k of this launch (K-chunked launches)
+  int beta;             // 1: add into C (later K chunks); 0: overwrite
 };
 
 // Block tile BM x BN complex outputs, BK complex per K step; 4 waves laid out
@@ -457,7 +459,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
   const int zb = blockIdx.z;
   const int ks = zb % P.ksplit;
   const int64_t bidx = zb / P.ksplit;
-  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int64_t kbeg = P.kbase + int64_t(ks) * P.kchunk;
   const int64_t kend = min(P.K, kbeg + P.kchunk);
   const float2* Ab = A + bidx * P.M * P.K;
   const float2* Bb = B + bidx * P.K * P.N;
@@ -613,7 +615,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const float2* __restrict
       for (int r = 0; r < 16; ++r) {
         const int64_t m = m0 + wm0 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
         const int64_t n = n0 + wn0 + j * 16 + bn_local;
-        if (m < P.M && n < P.N) Cf[(m * P.N + n) * 2 + bt] = acc[i][j][r];
+        if (m < P.M && n < P.N) {
+          float* c = Cf + (m * P.N + n) * 2 + bt;
+          *c = P.beta ? *c + acc[i][j][r] : acc[i][j][r];
+        }
       }
 }
 
@@ -633,21 +638,28 @@ struct PackedArgs {
   int64_t kchunk;
   int ksplit;
   int tiles_m, tiles_n;
-  int regions;                 // 1: XCD region order (see packed_tile_of)
+  int order;                   // block order (see packed_tile_of)
   int64_t plane_a, plane_b;
   const uint32_t* smax_a;      // split-FP16: operand max bits (scale 2^s); else null
   const uint32_t* smax_b;
+  int64_t kbase;               // first k of this launch (K-chunked launches)
+  int beta;                    // 1: add into C (later K chunks); 0: overwrite
 };
 
 // Block -> output tile.  Workgroups are dispatched round-robin over the 8
-// XCDs (block b runs on XCD b % 8).  With `regions`, the blocks of one XCD
-// walk 4 x 8-tile regions (the 32 tiles its CUs hold at once share 4 A and
-// 8 B panels in that XCD's L2), and the 8 XCDs take 8 neighbouring regions
-// (2 region rows x 4 region columns) so that the last-level cache sees the
-// panels they share.  Otherwise: each XCD takes a contiguous range of a
-// grouped (8 tile rows) order.
+// XCDs (block b runs on XCD b % 8).  Order 1 (XCD regions): the blocks of
+// one XCD walk 4 x 8-tile regions (the 32 tiles its CUs hold at once share 4
+// A and 8 B panels in that XCD's L2), and the 8 XCDs take 8 neighbouring
+// regions (2 region rows x 4 region columns) so that the last-level cache
+// sees the panels they share.  Order 0: each XCD takes a contiguous range of
+// a grouped (8 tile rows) order.  Order 2: row-major in block order.
 __device__ inline void packed_tile_of(int b, int nblk, const PackedArgs& P, int& tm, int& tn) {
-  if (P.regions) {
+  if (P.order == 2) {
+    tm = b / P.tiles_n;
+    tn = b % P.tiles_n;
+    return;
+  }
+  if (P.order == 1) {
     const int x = b & 7, j = b >> 3;
     const int g = (j >> 5) * 8 + x, w = j & 31;
     const int RN = P.tiles_n >> 3;
@@ -749,10 +761,12 @@ __device__ __forceinline__ void packed_multiply(const uint32_t* As, const uint32
 
 // Writes a wave's TM x TN accumulator tiles (32 rows x 16 complex columns
 // each, rows from mw, complex columns from nw) to C (row-major M x N
-// complex), times 2^shift; entries outside M x N are skipped.
+// complex), times 2^shift, added to what C holds when `beta`; entries
+// outside M x N are skipped.
 template <int TM, int TN, bool F16>
 __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[TM][TN], int64_t mw, int64_t nw,
-                                               int lh, int bn_local, int bt, int64_t M, int64_t N, int shift) {
+                                               int lh, int bn_local, int bt, int64_t M, int64_t N, int shift,
+                                               int beta) {
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -761,7 +775,11 @@ __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[
       for (int r = 0; r < 16; ++r) {
         const int64_t m = mw + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
         const int64_t n = nw + j * 16 + bn_local;
-        if (m < M && n < N) Cf[(m * N + n) * 2 + bt] = F16 ? ldexpf(acc[i][j][r], shift) : acc[i][j][r];
+        if (m < M && n < N) {
+          const float v = F16 ? ldexpf(acc[i][j][r], shift) : acc[i][j][r];
+          float* c = Cf + (m * N + n) * 2 + bt;
+          *c = beta ? *c + v : v;
+        }
       }
 }
 
@@ -797,7 +815,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   const int zb = blockIdx.z;
   const int ks = zb % P.ksplit;
   const int64_t bidx = zb / P.ksplit;
-  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int64_t kbeg = P.kbase + int64_t(ks) * P.kchunk;
   const int64_t kend = min(P.K, kbeg + P.kchunk);
   const int klen = int(kend - kbeg);
   const int64_t rows_a = min<int64_t>(BM, P.M - m0), rows_b = min<int64_t>(BN, P.N - n0);
@@ -905,7 +923,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_kernel(const uint3
   }
 
   packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
-                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P));
+                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P), P.beta);
 }
 
 // Direct-to-LDS variant for exactly tiled GEMMs (M % BM == N % BN == 0 and
@@ -948,7 +966,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
   const int zb = blockIdx.z;
   const int ks = zb % P.ksplit;
   const int64_t bidx = zb / P.ksplit;
-  const int64_t kbeg = int64_t(ks) * P.kchunk;
+  const int64_t kbeg = P.kbase + int64_t(ks) * P.kchunk;
   const int klen = int(min(P.K, kbeg + P.kchunk) - kbeg);
   const int ntiles = klen / BK;
 
@@ -1057,7 +1075,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
   }
 
   packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
-                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P));
+                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P), P.beta);
 #endif
 }
 
@@ -1085,6 +1103,8 @@ struct TileShape {
 };
 constexpr TileShape kUnpackedTiles[4] = {{256, 16}, {128, 32}, {128, 64}, {64, 64}};
 constexpr TileShape kPackedTiles[6] = {{256, 16}, {128, 32}, {128, 64}, {256, 128}, {128, 128}, {256, 128}};
+
+constexpr int64_t kAccChunk = 4096;   // complex k per FP32 accumulator chain (all MFMA GEMMs)
 
 // Tile 5 (direct-to-LDS copies) needs whole tiles in M, N and K.
 bool dma_exact(const GemmDesc& g) {
@@ -1231,25 +1251,37 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.plane_b = g.plane_b;
     P.smax_a = nullptr;
     P.smax_b = nullptr;
+    P.kbase = 0;
+    P.beta = 0;
     P.ksplit = ksplit;
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
     P.tiles_n = tiles_n;
-    P.regions = (tiles_m % 8 == 0 && tiles_n % 8 == 0 && (int64_t(tiles_m) * tiles_n) % 256 == 0) ? 1 : 0;
+    const bool regions_fit = tiles_m % 8 == 0 && tiles_n % 8 == 0 && (int64_t(tiles_m) * tiles_n) % 256 == 0;
+    P.order = g.order == 2 ? 2 : (g.order == 0 || !regions_fit) ? 0 : 1;
     // buffer offsets are 32-bit: a (BM x K) panel of one plane must stay below 2 GiB
     TN_REQUIRE(int64_t(t.bm > t.bn ? t.bm : t.bn) * g.K * 4 < (int64_t(1) << 31), TN_ERR_UNSUPPORTED,
                "packed GEMM: K too long for one panel");
     const uint32_t* Ap = reinterpret_cast<const uint32_t*>(A);
     const uint32_t* Bp = reinterpret_cast<const uint32_t*>(B);
-    if (g.precision == TN_PREC_BF16X6) {
-      launch_packed_np<3, 16, false>(Ap, Bp, out, P, g.batch, id, s);
-    } else if (g.precision == TN_PREC_F16X3) {
+    if (g.precision == TN_PREC_F16X3) {
       TN_REQUIRE(smax_a && smax_b, TN_ERR_ARG, "internal: split-FP16 GEMM needs operand scales");
       P.smax_a = smax_a;
       P.smax_b = smax_b;
-      launch_packed_np<2, 32, true>(Ap, Bp, out, P, g.batch, id, s);
-    } else {
-      launch_packed_np<2, 32, false>(Ap, Bp, out, P, g.batch, id, s);
+    }
+    // Long contractions run as several launches over K chunks of
+    // kAccChunk, each adding its FP32 sums into C: an accumulator chain never
+    // spans more than kAccChunk complex k, and the chunks add in a fixed order.
+    const int64_t nchunks = ksplit == 1 ? ceil_div(g.K, kAccChunk) : 1;
+    for (int64_t c = 0; c < nchunks; ++c) {
+      if (nchunks > 1) {
+        P.kbase = c * kAccChunk;
+        P.kchunk = kAccChunk;
+        P.beta = c > 0 ? 1 : 0;
+      }
+      if (g.precision == TN_PREC_BF16X6) launch_packed_np<3, 16, false>(Ap, Bp, out, P, g.batch, id, s);
+      else if (g.precision == TN_PREC_F16X3) launch_packed_np<2, 32, true>(Ap, Bp, out, P, g.batch, id, s);
+      else launch_packed_np<2, 32, false>(Ap, Bp, out, P, g.batch, id, s);
     }
   } else {
     const int prec = g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_BF16X6 ? g.precision
@@ -1264,10 +1296,20 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
     P.tiles_n = tiles_n;
-    switch (prec) {
-      case TN_PREC_FP32: launch_gemm_prec<TN_PREC_FP32, 8>(A, B, out, P, g.batch, id, s); break;
-      case TN_PREC_BF16X3: launch_gemm_prec<TN_PREC_BF16X3, 16>(A, B, out, P, g.batch, id, s); break;
-      default: launch_gemm_prec<TN_PREC_BF16X6, 16>(A, B, out, P, g.batch, id, s); break;
+    P.kbase = 0;
+    P.beta = 0;
+    const int64_t nchunks = ksplit == 1 ? ceil_div(g.K, kAccChunk) : 1;   // as for the packed GEMMs
+    for (int64_t c = 0; c < nchunks; ++c) {
+      if (nchunks > 1) {
+        P.kbase = c * kAccChunk;
+        P.kchunk = kAccChunk;
+        P.beta = c > 0 ? 1 : 0;
+      }
+      switch (prec) {
+        case TN_PREC_FP32: launch_gemm_prec<TN_PREC_FP32, 8>(A, B, out, P, g.batch, id, s); break;
+        case TN_PREC_BF16X3: launch_gemm_prec<TN_PREC_BF16X3, 16>(A, B, out, P, g.batch, id, s); break;
+        default: launch_gemm_prec<TN_PREC_BF16X6, 16>(A, B, out, P, g.batch, id, s); break;
+      }
     }
   }
   TN_HIP(hipGetLastError());

@@ -62,6 +62,7 @@ struct GemmDesc {
   int packed = 0;
   int64_t plane_a = 0, plane_b = 0;
   int tile = -1;           // block tile id (-1: shape heuristic)
+  int order = -1;          // packed block order: 0 grouped, 1 XCD regions, 2 row-major (-1: heuristic)
 };
 // Workspace needed for split-K partials (bytes); 0 when no split is used.
 size_t gemm_workspace_bytes(const GemmDesc& g);

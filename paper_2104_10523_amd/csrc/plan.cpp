@@ -594,7 +594,14 @@ AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, 
         const double u = op.gm.precision == TN_PREC_BF16X3   ? std::ldexp(1.0, -17)
                          : op.gm.precision == TN_PREC_F16X3 ? std::ldexp(1.0, -21)
                                                             : std::ldexp(1.0, -24);
-        err2 += u * u * (1.0 + std::log2(double(op.gm.K)));
+        // FP32 roundings along one accumulator chain, cut every 4096
+        // complex k (then one add per chunk): split kernels round once per
+        // product per 8 complex k, the FP32 MFMA once per complex k
+        const double K = double(op.gm.K);
+        const double nprod = op.gm.precision == TN_PREC_BF16X6 ? 6.0 : 3.0;
+        const double per_chunk = op.gm.packed ? std::min(K, 4096.0) / 8.0 * nprod : std::min(K, 4096.0);
+        const double chain = per_chunk + std::ceil(K / 4096.0);
+        err2 += u * u * (1.0 + std::log2(K)) + std::ldexp(1.0, -48) * chain;
       } else if (op.kind != OP_PERMUTE) {
         err2 += std::ldexp(1.0, -48);
       }

@@ -23,7 +23,7 @@ estimate at this depth is 1.4e-4; 2^-21 for scaled split-FP16x3, 8.5e-6;
 import numpy as np
 import pytest
 
-from oracle.separable import separable_slice_amplitude
+from oracle.separable import dominant_bits, separable_slice_amplitude
 from workloads import grid_random_circuit, random_bitstrings
 
 pytestmark = pytest.mark.gpu
@@ -47,26 +47,30 @@ def test_rqc_7x7_14_full_size_slices(gpu, workspace, identity_coupled, precision
     ns = path.cost.n_sliced
     assert ns == 8
     floor = 2.0 ** (-(n + ns) / 2)
-    bits = random_bitstrings(2, n, 12345)
-    need = tn.tn_amplitudes_workspace(net, path, len(bits), precision)
+    rnd = random_bitstrings(1, n, 12345)[0]
+    need = tn.tn_amplitudes_workspace(net, path, 2, precision)
     big = torch.empty(need, dtype=torch.uint8, device=gpu)
     tn.tn_set_workspace(big)
     try:
         # two slices for the benchmark's precision, one for the others (an
-        # FP32 slice takes ~17 s per bit-string at this size)
+        # FP32 slice takes ~11 s per bit-string at this size)
         for s in ((1, 201) if precision == "f16x3" else (1,)):
+            vals = {l: (s >> (ns - 1 - i)) & 1 for i, l in enumerate(path.sliced)}
+            # the slice's largest amplitude (typical magnitude, so the relative
+            # error means something) and one uniform bit-string
+            bits = np.array([dominant_bits(n, ops, vals), rnd], dtype=np.int8)
             print(f"full-size {precision} slice {s}", flush=True)
             out, rep = tn.tn_amplitudes(net, path, bits, precision=precision, slice_begin=s, slice_count=1)
             got = out.cpu().numpy().reshape(len(bits))
             assert rep.nonfinite == 0
             tol = max(1e-5, 4 * rep.err_bound)
-            vals = {l: (s >> (ns - 1 - i)) & 1 for i, l in enumerate(path.sliced)}
             for b in range(len(bits)):
                 ref = separable_slice_amplitude(n, ops, bits[b], vals)
                 err = abs(got[b] - ref) / max(abs(ref), floor)
-                print(f"  bits {b}: got {got[b]:.6e} ref {ref:.6e} err {err:.2e} "
-                      f"(bound {rep.err_bound:.1e}, tol {tol:.1e})", flush=True)
+                print(f"  bits {b}: got {got[b]:.6e} ref {ref:.6e} |ref|/floor {abs(ref) / floor:.2f} "
+                      f"err {err:.2e} (bound {rep.err_bound:.1e}, tol {tol:.1e})", flush=True)
                 assert err <= tol, (s, b, err, tol)
+            assert abs(separable_slice_amplitude(n, ops, bits[0], vals)) >= floor
     finally:
         tn.tn_set_workspace(workspace)
         del big

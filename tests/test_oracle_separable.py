@@ -12,7 +12,7 @@ from oracle import statevector as sv
 from oracle.contract import contract_path
 from oracle.network import build_network, fix_labels, fix_outputs
 from oracle.paths import greedy_path
-from oracle.separable import separable_slice_amplitude
+from oracle.separable import dominant_bits, separable_slice_amplitude
 from workloads import Op, grid_random_circuit
 
 IDENT = (0.0, 0.0)   # fSim(0, 0) is the identity
@@ -61,3 +61,18 @@ def test_lone_wire_and_rejects_entangling_gates():
         assert abs(separable_slice_amplitude(3, ops, bits, {}) - psi[bits]) <= 1e-15
     with pytest.raises(ValueError):
         separable_slice_amplitude(2, [Op("cz", (0, 1))], [0, 0], {})
+
+
+def test_dominant_bits_maximise_the_slice_value():
+    """Brute force over all bit-strings of a 3x3 identity-coupled circuit."""
+    n, ops = grid_random_circuit(3, 3, 6, 4, two_qubit="fsim", fsim_params=IDENT)
+    net = build_network(n, ops)
+    inner = _inner_labels(net)
+    rng = np.random.default_rng(9)
+    for trial in range(3):
+        pick = sorted(int(l) for l in rng.choice(inner, size=4, replace=False))
+        fixed = {l: int(rng.integers(0, 2)) for l in pick}
+        best = max(abs(separable_slice_amplitude(n, ops, bits, fixed))
+                   for bits in itertools.product(range(2), repeat=n))
+        got = abs(separable_slice_amplitude(n, ops, dominant_bits(n, ops, fixed), fixed))
+        assert got == pytest.approx(best, rel=1e-14)
