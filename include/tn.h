@@ -340,9 +340,11 @@ typedef struct {
 tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p,
                                   int32_t precision, tn_plan_info* info);
 /* Per-op detail (arrays of n_ops, any may be NULL): kind (TN_OP_*),
- * algorithmic flops and bytes, and `shape`, 6 int64 per op: m, n, k, batch,
- * block-tile id, packed flag for GEMMs (1 for other kinds, tile -1; for
- * APPLY: rows, 2^#N, 2^#K). */
+ * algorithmic flops and bytes, and `shape`, 8 int64 per op: m, n, k, batch,
+ * block-tile id, packed flag, GEMM kernel launches (K-chunked accumulation:
+ * ceil(k / 4096) unless split-K is used), 0 — for GEMMs; other kinds give
+ * 1, 1, 1, 1, -1, 0, 1, 0 except APPLY: rows, 2^#N, 2^#K in the first three,
+ * DOT: k and batch in the third and fourth. */
 tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p,
                                  int32_t precision, int32_t* kind,
                                  double* flops, double* bytes, int64_t* shape);

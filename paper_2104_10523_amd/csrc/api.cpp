@@ -540,14 +540,17 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
       if (flops) flops[k] = op.flops;
       if (bytes) bytes[k] = op.bytes;
       if (shape) {
-        int64_t* r = shape + 6 * k;
+        int64_t* r = shape + 8 * k;
         r[0] = r[1] = r[2] = r[3] = 1;
         r[4] = -1;
         r[5] = 0;
+        r[6] = op.kind == OP_GEMM ? 0 : 1;
+        r[7] = 0;
         if (op.kind == OP_GEMM) {
           r[0] = op.gm.M; r[1] = op.gm.N; r[2] = op.gm.K; r[3] = op.gm.batch;
           r[4] = gemm_tile_of(op.gm);
           r[5] = op.gm.packed;
+          r[6] = gemm_dispatches(op.gm);
         } else if (op.kind == OP_APPLY) {
           r[0] = int64_t(1) << (op.ap.a_bits - op.ap.nk);
           r[1] = int64_t(1) << op.ap.nn;

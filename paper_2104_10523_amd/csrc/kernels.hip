@@ -1145,6 +1145,12 @@ int choose_ksplit(const GemmDesc& g, int id, int64_t* kchunk) {
 
 int gemm_tile_of(const GemmDesc& g) { return tile_of(g); }
 
+int64_t gemm_dispatches(const GemmDesc& g) {
+  int64_t kchunk = 0;
+  const int ksplit = choose_ksplit(g, tile_of(g), &kchunk);
+  return ksplit == 1 ? ceil_div(g.K, kAccChunk) : 1;
+}
+
 std::vector<int> gemm_tile_candidates(const GemmDesc& g) {
   if (!g.packed) return {0, 1, 2, 3};
   if (g.precision == TN_PREC_BF16X6) return {0, 1, 2, 4};

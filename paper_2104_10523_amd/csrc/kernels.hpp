@@ -70,6 +70,9 @@ size_t gemm_workspace_bytes(const GemmDesc& g);
 // launch uses (the heuristic when g.tile < 0).
 std::vector<int> gemm_tile_candidates(const GemmDesc& g);
 int gemm_tile_of(const GemmDesc& g);
+// Launches of the GEMM kernel itself one launch_gemm makes (K chunks of the
+// accumulator chains; a split-K reduction is not counted).
+int64_t gemm_dispatches(const GemmDesc& g);
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
                  const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s);
 
