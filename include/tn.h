@@ -163,9 +163,12 @@ typedef struct {
  * n+t), then slice.  Cost model and heuristics: a greedy step picks the
  * connected pair minimising (|C|-|A|-|B|, flops, i, j); the randomised
  * version samples exp(-(sigma - sigma_min)/T), sigma = sign(d)log2(1+|d|),
- * from SplitMix64 and keeps the best of greedy + `trials` by (flops, peak).
- * Slicing adds, while 8*peak > budget, the label of the peak step that
- * minimises (peak, total flops, label).  Host only.
+ * from SplitMix64 (trial r seeded with seed + r * 0x9E3779B97F4A7C15, trials
+ * on up to 16 host threads) and keeps the best of greedy + `trials` by
+ * (flops, peak); with a budget, the 16 best by (flops, peak) are sliced and
+ * the lowest (total flops, peak) is kept.  Slicing adds, while 8*peak >
+ * budget, the label of the peak step that minimises (peak, total flops,
+ * label).  Host only.
  * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */
 tn_status tn_find_path(const tn_network* n, const tn_path_opts* o,
                        tn_path** out, tn_path_cost* cost);

@@ -191,20 +191,39 @@ def path_stats(leaves, ext, path, open_set=(), sliced=()) -> dict:
             "n_slices": n_slices, "total_flops": flops * n_slices}
 
 
+RERANK = 16   # candidates re-ranked by their sliced cost when a budget is given
+
+
 def random_greedy_path(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
-                       temperature: float = 1.0):
-    best = greedy_path(leaves, ext, open_set)
-    bs = path_stats(leaves, ext, best, open_set)
-    best_key = (bs["flops"], bs["peak"])
+                       temperature: float = 1.0, budget_bytes: float = 0.0):
+    """Best of the plain greedy path and `trials` randomised ones (trial r
+    draws from SplitMix64 seeded with seed + r * golden ratio), by unsliced
+    (flops, peak), earlier candidates winning ties.  With a memory budget,
+    the RERANK best are sliced to it (slice_path) and the lowest (total
+    flops, peak) wins instead."""
+    cands = [greedy_path(leaves, ext, open_set)]
     for r in range(trials):
         g = SplitMix64((seed + r * GOLDEN) & MASK64)
         rng = SplitMix64(g.next_u64())
-        p = greedy_path(leaves, ext, open_set, rng=rng, temperature=temperature)
+        cands.append(greedy_path(leaves, ext, open_set, rng=rng, temperature=temperature))
+    keys = []
+    for i, p in enumerate(cands):
         s = path_stats(leaves, ext, p, open_set)
-        key = (s["flops"], s["peak"])
-        if key < best_key:
-            best, best_key = p, key
-    return best
+        keys.append((s["flops"], s["peak"], i))
+    order = [k[2] for k in sorted(keys)]
+    if budget_bytes <= 0:
+        return cands[order[0]]
+    best = None
+    for rank, i in enumerate(order[:RERANK]):
+        try:
+            sl = slice_path(leaves, ext, cands[i], open_set, budget_bytes)
+        except ValueError:
+            continue
+        s = path_stats(leaves, ext, cands[i], open_set, sl)
+        key = (s["total_flops"], s["peak"], rank)
+        if best is None or key < best[0]:
+            best = (key, i)
+    return cands[order[0] if best is None else best[1]]
 
 
 def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:

@@ -235,7 +235,7 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
       pairs = greedy_path(pr, nullptr, 1.0);
     } else if (algo == TN_PATH_RANDOM_GREEDY) {
       TN_REQUIRE(o->trials >= 0 && o->temperature > 0, TN_ERR_ARG, "bad random-greedy options");
-      pairs = random_greedy_path(pr, o->seed, o->trials, o->temperature);
+      pairs = random_greedy_path(pr, o->seed, o->trials, o->temperature, o->mem_budget_bytes);
     } else {
       TN_REQUIRE(o->model != nullptr, TN_ERR_STATE, "learned path needs a model");
       int used = TN_PATH_GREEDY;

@@ -293,52 +293,87 @@ PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int
   return ps;
 }
 
-std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
-                                                    int trials, double temperature) {
-  // Trial r draws from its own stream (seed + r * golden ratio), so the
-  // trials run on host threads in any order; the winner is the first, in
-  // trial order, of the lowest (flops, peak), the deterministic greedy path
-  // winning ties, exactly as a sequential scan would pick.
-  auto best = greedy_path(pr, nullptr, temperature);
-  PathStats bs = path_stats(pr, best, {});
-  if (trials <= 0) return best;
-  std::vector<std::vector<std::pair<int, int>>> paths(trials);
-  std::vector<double> fl(trials), pk(trials);
+namespace {
+int path_threads(int work) {
+  int nt = int(std::max(1u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) nt = std::min(nt, std::max(1, std::atoi(e)));
+  return std::max(1, std::min({nt, 16, work}));
+}
+
+// Runs body(i) for i in [0, n) on host threads; the first exception wins.
+template <class F>
+void parallel_for(int n, F&& body) {
   std::atomic<int> next{0};
   std::exception_ptr err;
   std::mutex err_mu;
   auto worker = [&]() {
-    for (int r; (r = next.fetch_add(1)) < trials;) {
+    for (int i; (i = next.fetch_add(1)) < n;) {
       try {
-        uint64_t g = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
-        uint64_t st = splitmix64_next(&g);
-        paths[r] = greedy_path(pr, &st, temperature);
-        const PathStats s = path_stats(pr, paths[r], {});
-        fl[r] = s.flops;
-        pk[r] = s.peak;
+        body(i);
       } catch (...) {
         std::lock_guard<std::mutex> lk(err_mu);
         if (!err) err = std::current_exception();
       }
     }
   };
-  int nt = int(std::max(1u, std::thread::hardware_concurrency()));
-  if (const char* e = std::getenv("OMP_NUM_THREADS")) nt = std::min(nt, std::max(1, std::atoi(e)));
-  nt = std::min({nt, 16, trials});
+  const int nt = path_threads(n);
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
   worker();
   for (auto& th : pool) th.join();
   if (err) std::rethrow_exception(err);
-  double bf = bs.flops, bp = bs.peak;
-  int win = -1;
-  for (int r = 0; r < trials; ++r)
-    if (fl[r] < bf || (fl[r] == bf && pk[r] < bp)) {
-      win = r;
-      bf = fl[r];
-      bp = pk[r];
+}
+}  // namespace
+
+std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
+                                                    int trials, double temperature, double budget_bytes) {
+  // Trial r draws from its own stream (seed + r * golden ratio), so the
+  // trials run on host threads in any order.  Candidates are the plain
+  // greedy path (rank -1) and the trials, ordered by unsliced (flops, peak,
+  // rank); without a budget the first wins, exactly as a sequential scan
+  // would pick.
+  trials = std::max(trials, 0);
+  std::vector<std::vector<std::pair<int, int>>> paths(trials + 1);
+  std::vector<double> fl(trials + 1), pk(trials + 1);
+  paths[0] = greedy_path(pr, nullptr, temperature);
+  {
+    const PathStats s = path_stats(pr, paths[0], {});
+    fl[0] = s.flops;
+    pk[0] = s.peak;
+  }
+  parallel_for(trials, [&](int r) {
+    uint64_t g = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
+    uint64_t st = splitmix64_next(&g);
+    paths[r + 1] = greedy_path(pr, &st, temperature);
+    const PathStats s = path_stats(pr, paths[r + 1], {});
+    fl[r + 1] = s.flops;
+    pk[r + 1] = s.peak;
+  });
+  std::vector<int> order(trials + 1);
+  for (int i = 0; i <= trials; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return fl[a] < fl[b] || (fl[a] == fl[b] && pk[a] < pk[b]);
+  });
+  if (budget_bytes <= 0) return std::move(paths[order[0]]);
+  // re-rank the best few by what slicing to the budget leaves
+  const int nr = std::min(kRerank, trials + 1);
+  std::vector<double> tf(nr, 0.0), tp(nr, 0.0);
+  std::vector<char> ok(nr, 0);
+  parallel_for(nr, [&](int i) {
+    try {
+      const auto& path = paths[order[i]];
+      const PathStats s = path_stats(pr, path, slice_path(pr, path, budget_bytes));
+      tf[i] = s.total_flops;
+      tp[i] = s.peak;
+      ok[i] = 1;
+    } catch (const Error& e) {
+      if (e.code != TN_ERR_BUDGET) throw;
     }
-  return win < 0 ? best : std::move(paths[win]);
+  });
+  int win = -1;
+  for (int i = 0; i < nr; ++i)
+    if (ok[i] && (win < 0 || tf[i] < tf[win] || (tf[i] == tf[win] && tp[i] < tp[win]))) win = i;
+  return std::move(paths[order[win < 0 ? 0 : win]]);
 }
 
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

@@ -69,8 +69,12 @@ PathProblem make_problem(const Network& net, const std::vector<char>& open_q);
 
 std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng_state,
                                              double temperature);
+// With budget_bytes > 0 the kRerank best candidates by unsliced (flops,
+// peak) are sliced to the budget and the lowest (total flops, peak) wins.
+constexpr int kRerank = 16;
 std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
-                                                    int trials, double temperature);
+                                                    int trials, double temperature,
+                                                    double budget_bytes = 0.0);
 PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
                      const std::vector<int>& sliced);
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

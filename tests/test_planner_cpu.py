@@ -98,6 +98,22 @@ def test_random_greedy_matches_oracle():
         assert p.pairs == po
 
 
+def test_random_greedy_with_budget_reranks_like_oracle():
+    """With a memory budget the best candidates are re-ranked by their
+    sliced total flops; library and oracle pick the same path and slices."""
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    peak = path_stats(leaves, ext, greedy_path(leaves, ext, opened), opened)["peak"]
+    for div, trials in ((16, 24), (256, 40)):
+        budget = 8 * peak / div
+        p = tn.tn_find_path(lnet, "random_greedy", trials=trials, seed=9, temperature=0.5, mem_budget_bytes=budget)
+        po = random_greedy_path(leaves, ext, opened, seed=9, trials=trials, temperature=0.5, budget_bytes=budget)
+        assert p.pairs == po
+        assert p.sliced == slice_path(leaves, ext, po, opened, budget)
+
+
 def test_slicing_matches_oracle_and_meets_budget():
     n, ops = grid_random_circuit(4, 5, 10, 3)
     onet = build_network(n, ops)
