@@ -644,6 +644,8 @@ struct PackedArgs {
   const uint32_t* smax_b;
   int64_t kbase;               // first k of this launch (K-chunked launches)
   int beta;                    // 1: add into C (later K chunks); 0: overwrite
+  int flush_tiles;             // direct-to-LDS kernel: add the accumulators into C
+                               // every flush_tiles K tiles (0: only at the end)
 };
 
 // Block -> output tile.  Workgroups are dispatched round-robin over the 8
@@ -780,6 +782,26 @@ __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[
           float* c = Cf + (m * N + n) * 2 + bt;
           *c = beta ? *c + v : v;
         }
+      }
+}
+
+// Adds (beta) or writes a wave's accumulator tiles into an exactly tiled C
+// through a buffer descriptor on the wave's 64 x 64 complex block: one
+// per-lane byte offset, and per element a uniform (scalar) row offset, so the
+// flush needs almost no address registers.  `row_bytes` = 8 N.
+template <int TM, int TN, bool F16>
+__device__ __forceinline__ void packed_flush_exact(__amdgpu_buffer_rsrc_t cb, const floatx16 (&acc)[TM][TN],
+                                                   uint32_t lane_off, uint32_t row_bytes, int shift, int beta) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t soff = uint32_t(i * 32 + 8 * (r >> 2) + (r & 3)) * row_bytes + uint32_t(j * 16 * 8);
+        float v = F16 ? ldexpf(acc[i][j][r], shift) : acc[i][j][r];
+        if (beta) v += __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(cb, lane_off, soff, 0));
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), cb, lane_off, soff, 0);
       }
 }
 
@@ -1041,6 +1063,14 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
   // while those MFMAs run (every wave is done reading stage t % 3, so the copy
   // of tile t + 3 goes there), read the next tile's F0, multiply F1.
   static_assert(BK == 16, "two K steps per tile");
+  // C block of this wave (exact tiles: every element in range)
+  float2* Cw = C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N + (m0 + wm0) * P.N + (n0 + wn0);
+  const uint32_t row_bytes = uint32_t(P.N * 8);
+  const __amdgpu_buffer_rsrc_t cb = __builtin_amdgcn_make_buffer_rsrc(
+      Cw, 0, int(uint32_t(WM - 1) * row_bytes + uint32_t(WN * 8)), 0x00020000);
+  const uint32_t lane_off = uint32_t(4 * (lane >> 5)) * row_bytes + uint32_t(((lane & 31) >> 1) * 8 + (lane & 1) * 4);
+  const int shift = packed_shift(P);
+  int beta = P.beta;
   u32x4 a0[NP][TM], b0[NP][TN], a1[NP][TM], b1[NP][TN];
   for (int t = 0; t < 3 && t < ntiles; ++t) issue(t, t);
   if (ntiles > 0) {
@@ -1072,10 +1102,20 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
     __builtin_amdgcn_sched_barrier(0);
     packed_mma<NP, TM, TN, F16>(a1, b1, acc, brot, bxor);
     __builtin_amdgcn_sched_barrier(0);
+    if (P.flush_tiles > 0 && (t + 1) % P.flush_tiles == 0 && t + 1 < ntiles) {
+      // cut the FP32 accumulator chain: add this K chunk's sums into C
+      packed_flush_exact<TM, TN, F16>(cb, acc, lane_off, row_bytes, shift, beta);
+      beta = 1;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    }
   }
 
-  packed_store_c<TM, TN, F16>(reinterpret_cast<float*>(C + (int64_t(ks) * (gridDim.z / P.ksplit) + bidx) * P.M * P.N),
-                              acc, m0 + wm0, n0 + wn0, lh, bn_local, bt, P.M, P.N, packed_shift(P), P.beta);
+  packed_flush_exact<TM, TN, F16>(cb, acc, lane_off, row_bytes, shift, beta);
 #endif
 }
 
@@ -1108,8 +1148,9 @@ constexpr int64_t kAccChunk = 4096;   // complex k per FP32 accumulator chain (a
 
 // Tile 5 (direct-to-LDS copies) needs whole tiles in M, N and K.
 bool dma_exact(const GemmDesc& g) {
+  // the C flush addresses a wave's 64-row block with 32-bit byte offsets
   return g.packed && (g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_F16X3) && g.M % 256 == 0 &&
-         g.N % 128 == 0 && g.K % 16 == 0;
+         g.N % 128 == 0 && g.K % 16 == 0 && 64 * 8 * g.N < (int64_t(1) << 31);
 }
 
 int default_tile(const GemmDesc& g) {
@@ -1147,8 +1188,9 @@ int gemm_tile_of(const GemmDesc& g) { return tile_of(g); }
 
 int64_t gemm_dispatches(const GemmDesc& g) {
   int64_t kchunk = 0;
-  const int ksplit = choose_ksplit(g, tile_of(g), &kchunk);
-  return ksplit == 1 ? ceil_div(g.K, kAccChunk) : 1;
+  const int id = tile_of(g);
+  const int ksplit = choose_ksplit(g, id, &kchunk);
+  return ksplit == 1 && !(g.packed && id == 5) ? ceil_div(g.K, kAccChunk) : 1;
 }
 
 std::vector<int> gemm_tile_candidates(const GemmDesc& g) {
@@ -1259,6 +1301,7 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.smax_b = nullptr;
     P.kbase = 0;
     P.beta = 0;
+    P.flush_tiles = 0;
     P.ksplit = ksplit;
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
@@ -1275,10 +1318,11 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
       P.smax_a = smax_a;
       P.smax_b = smax_b;
     }
-    // Long contractions run as several launches over K chunks of
-    // kAccChunk, each adding its FP32 sums into C: an accumulator chain never
-    // spans more than kAccChunk complex k, and the chunks add in a fixed order.
-    const int64_t nchunks = ksplit == 1 ? ceil_div(g.K, kAccChunk) : 1;
+    // Long contractions cut their FP32 accumulator chains every kAccChunk
+    // complex k, adding each chunk's sums into C in K order: inside the
+    // direct-to-LDS kernel (tile 5), else as one launch per K chunk.
+    const int64_t nchunks = ksplit == 1 && id != 5 ? ceil_div(g.K, kAccChunk) : 1;
+    if (id == 5) P.flush_tiles = int(kAccChunk / 16);
     for (int64_t c = 0; c < nchunks; ++c) {
       if (nchunks > 1) {
         P.kbase = c * kAccChunk;
