@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="f16x3", choices=["bf16x3", "bf16x6", "f16x3", "fp32", "auto"])
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time FP32 steps")
-    ap.add_argument("--budget-gib", type=float, default=128.0)
+    ap.add_argument("--budget-gib", type=float, default=160.0)
     ap.add_argument("--trials", type=int, default=1024, help="randomised-greedy path search trials")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")

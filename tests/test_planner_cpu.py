@@ -221,9 +221,9 @@ def test_scorer_features_match_oracle():
 def test_identity_coupled_7x7_has_benchmark_path():
     """The full-size GPU parity case (fSim(0, 0) couplers) plans exactly like
     the benchmark's 7x7 grid circuit: same pairwise path and sliced labels."""
-    opts = dict(trials=1024, seed=1, temperature=0.5, mem_budget_bytes=128.0 * 2 ** 30)
+    opts = dict(trials=1024, seed=1, temperature=0.5, mem_budget_bytes=160.0 * 2 ** 30)
     n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim")
     _, ops0 = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim", fsim_params=(0.0, 0.0))
     p = tn.tn_find_path(tn.tn_build_network(n, ops), "random_greedy", **opts)
     p0 = tn.tn_find_path(tn.tn_build_network(n, ops0), "random_greedy", **opts)
-    assert p.pairs == p0.pairs and p.sliced == p0.sliced and p.cost.n_sliced == 8
+    assert p.pairs == p0.pairs and p.sliced == p0.sliced and p.cost.n_sliced == 7
