@@ -201,129 +201,102 @@ __global__ void write_sites_kernel(const double2* __restrict__ W, const double2*
 
 // ---------------------------------------------------------------- QR
 
-// X (m x n, row-major, FP64) from a site: !adj: X[(l,s), r] = A[l,s,r]
+// X (m x n, column-major, FP64) from a site: !adj: X[(l,s), r] = A[l,s,r]
 // (m = 2 chil, n = chir); adj: X = (A as chil x 2chir)^dagger (m = 2 chir,
-// n = chil).
+// n = chil).  Columns are contiguous so a wave streams one column.
 __global__ void site_to_x_kernel(const float2* __restrict__ A, double2* __restrict__ X, int chil, int chir,
                                  int adj) {
   const int64_t n = int64_t(chil) * 2 * chir;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     const float2 a = A[i];
     if (!adj) {
-      X[i] = make_double2(a.x, a.y);
+      const int64_t row = i / chir, col = i % chir;          // row = (l, s)
+      X[col * (2 * chil) + row] = make_double2(a.x, a.y);
     } else {
-      const int64_t l = i / (2 * chir), c = i % (2 * chir);
-      X[c * chil + l] = make_double2(a.x, -a.y);
+      const int64_t l = i / (2 * chir), c = i % (2 * chir);  // X[c, l] = conj A[l, c]
+      X[l * (2 * chir) + c] = make_double2(a.x, -a.y);
     }
   }
 }
 
-// Householder QR of X (m x n row-major, in place) in one workgroup; writes
-// R (k x n, k = min(m, n)) and the reflectors' scalars to tau (k entries).
-__global__ __launch_bounds__(1024) void householder_kernel(double2* __restrict__ X, int m, int n,
-                                                           double2* __restrict__ R, double2* __restrict__ tau) {
-  __shared__ double red[16];
-  __shared__ double2 s_alpha;
-  __shared__ double s_beta, s_vnorm2;
-  const int k = min(m, n);
-  for (int j = 0; j < k; ++j) {
-    double ss = 0;
-    for (int i = j + threadIdx.x; i < m; i += blockDim.x) {
-      const double2 x = X[int64_t(i) * n + j];
-      ss += x.x * x.x + x.y * x.y;
-    }
-    ss = block_sum(ss, red);
-    if (threadIdx.x == 0) {
-      const double2 alpha = X[int64_t(j) * n + j];
-      const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
-      const double nrm = sqrt(ss);
-      // beta = -e^{i arg alpha} ||x||; v = x - beta e_1
-      const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
-      const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
-      s_alpha = make_double2(alpha.x - beta.x, alpha.y - beta.y);  // v[0]
-      // |v|^2 = |x|^2 - |alpha|^2 + |alpha - beta|^2
-      s_vnorm2 = ss - an * an + s_alpha.x * s_alpha.x + s_alpha.y * s_alpha.y;
-      s_beta = nrm;
-      X[int64_t(j) * n + j] = s_alpha;
-      R[int64_t(j) * n + j] = beta;
-      tau[j] = make_double2(s_vnorm2 > 0 ? 2.0 / s_vnorm2 : 0.0, 0.0);
-    }
-    __syncthreads();
-    const double t2 = s_vnorm2 > 0 ? 2.0 / s_vnorm2 : 0.0;
-    // apply H = I - t2 v v^dagger to columns c > j: one wave per column
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int c = j + 1 + wave; c < n; c += nw) {
-      double dr = 0, di = 0;  // v^dagger x_c
-      for (int i = j + lane; i < m; i += 64) {
-        const double2 v = X[int64_t(i) * n + j], x = X[int64_t(i) * n + c];
-        dr += v.x * x.x + v.y * x.y;
-        di += v.x * x.y - v.y * x.x;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        dr += __shfl_xor(dr, o);
-        di += __shfl_xor(di, o);
-      }
-      const double2 f = make_double2(t2 * dr, t2 * di);
-      for (int i = j + lane; i < m; i += 64) {
-        const double2 v = X[int64_t(i) * n + j];
-        double2 x = X[int64_t(i) * n + c];
-        const double2 fv = cmul(v, f);
-        x.x -= fv.x;
-        x.y -= fv.y;
-        X[int64_t(i) * n + c] = x;
-      }
-      if (lane == 0) {
-        // row j of R after the reflection (read once all lanes updated it)
-      }
-    }
-    __syncthreads();
-    for (int c = j + 1 + threadIdx.x; c < n; c += blockDim.x) R[int64_t(j) * n + c] = X[int64_t(j) * n + c];
-    for (int c = threadIdx.x; c < j; c += blockDim.x) R[int64_t(j) * n + c] = make_double2(0, 0);
-    __syncthreads();
+__global__ void zero_kernel(double2* __restrict__ p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = make_double2(0, 0);
+}
+
+// Householder step j of the QR of X (m x n, column-major, in place): the
+// reflector of column j, v = x - beta e_j with beta = -e^{i arg x_j} ||x||,
+// stored over the column; R[j, j] = beta (R: k x n row-major); tau[j] =
+// 2 / ||v||^2.
+__global__ __launch_bounds__(256) void hh_reflect_kernel(double2* __restrict__ X, int m, int n, int j,
+                                                         double2* __restrict__ R, double2* __restrict__ tau) {
+  __shared__ double red[8];
+  double2* x = X + int64_t(j) * m;
+  double ss = 0;
+  for (int i = j + threadIdx.x; i < m; i += blockDim.x) ss += x[i].x * x[i].x + x[i].y * x[i].y;
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) {
+    const double2 alpha = x[j];
+    const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+    const double nrm = sqrt(ss);
+    const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
+    const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+    const double2 v0 = make_double2(alpha.x - beta.x, alpha.y - beta.y);
+    // |v|^2 = |x|^2 - |alpha|^2 + |alpha - beta|^2
+    const double vn2 = ss - an * an + v0.x * v0.x + v0.y * v0.y;
+    x[j] = v0;
+    R[int64_t(j) * n + j] = beta;
+    tau[j] = make_double2(vn2 > 0 ? 2.0 / vn2 : 0.0, 0.0);
   }
 }
 
-// Q (m x k, row-major) = H_0 ... H_{k-1} [I; 0], one workgroup.
-__global__ __launch_bounds__(1024) void form_q_kernel(const double2* __restrict__ X, int m, int n,
-                                                      const double2* __restrict__ tau, double2* __restrict__ Q) {
-  const int k = min(m, n);
-  for (int64_t i = threadIdx.x; i < int64_t(m) * k; i += blockDim.x)
-    Q[i] = make_double2((i / k) == (i % k) ? 1.0 : 0.0, 0.0);
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int j = k - 1; j >= 0; --j) {
-    const double t2 = tau[j].x;
-    for (int c = j + wave; c < k; c += nw) {
-      double dr = 0, di = 0;
-      for (int i = j + lane; i < m; i += 64) {
-        const double2 v = X[int64_t(i) * n + j], q = Q[int64_t(i) * k + c];
-        dr += v.x * q.x + v.y * q.y;
-        di += v.x * q.y - v.y * q.x;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        dr += __shfl_xor(dr, o);
-        di += __shfl_xor(di, o);
-      }
-      const double2 f = make_double2(t2 * dr, t2 * di);
-      for (int i = j + lane; i < m; i += 64) {
-        const double2 fv = cmul(X[int64_t(i) * n + j], f);
-        double2 q = Q[int64_t(i) * k + c];
-        q.x -= fv.x;
-        q.y -= fv.y;
-        Q[int64_t(i) * k + c] = q;
-      }
-    }
-    __syncthreads();
+// Applies I - tau_j v_j v_j^dagger (v_j: rows j.. of column j of V, m rows,
+// column-major) to columns c0 .. c1-1 of Y (m rows, column-major), one wave
+// per column; with R, also records row j of the result (R[j, c]).
+__global__ __launch_bounds__(256) void hh_apply_kernel(const double2* __restrict__ V, int m, int j,
+                                                       const double2* __restrict__ tau, double2* __restrict__ Y,
+                                                       int c0, int c1, double2* __restrict__ R, int n) {
+  const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= c1) return;
+  const double t2 = tau[j].x;
+  const double2* v = V + int64_t(j) * m;
+  double2* y = Y + int64_t(c) * m;
+  double dr = 0, di = 0;  // v^dagger y
+  for (int i = j + lane; i < m; i += 64) {
+    const double2 a = v[i], b = y[i];
+    dr += a.x * b.x + a.y * b.y;
+    di += a.x * b.y - a.y * b.x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dr += __shfl_xor(dr, o);
+    di += __shfl_xor(di, o);
+  }
+  const double2 f = make_double2(t2 * dr, t2 * di);
+  for (int i = j + lane; i < m; i += 64) {
+    const double2 fv = cmul(v[i], f);
+    double2 b = y[i];
+    b.x -= fv.x;
+    b.y -= fv.y;
+    y[i] = b;
+    if (R && i == j) R[int64_t(j) * n + c] = b;
   }
 }
 
-// Write Q back as the site: !adj: A[(l,s), k] = Q; adj: A = Q^dagger
-// (k x 2chir) -> A[k, (s,r)].
+// Q (m x k, column-major) = [I; 0], before the reflectors are applied.
+__global__ void q_init_kernel(double2* __restrict__ Q, int m, int k) {
+  const int64_t n = int64_t(m) * k;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    Q[i] = make_double2((i % m) == (i / m) ? 1.0 : 0.0, 0.0);
+}
+
+// Write Q (m x k, column-major) back as the site: !adj: A[(l,s), k] = Q;
+// adj: A = Q^dagger (k x 2chir) -> A[k, (s,r)].
 __global__ void q_to_site_kernel(const double2* __restrict__ Q, float2* __restrict__ A, int m, int k, int adj) {
   const int64_t n = int64_t(m) * k;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t r = i / k, c = i % k;
-    const double2 q = Q[i];
+    const double2 q = Q[c * m + r];
     if (!adj) A[i] = make_float2(float(q.x), float(q.y));
     else A[c * m + r] = make_float2(float(q.x), float(-q.y));
   }
@@ -425,6 +398,7 @@ struct tn_mps {
   void* gemm_work = nullptr;
   size_t gemm_work_bytes = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> sweeps;   // (mm, nn) -> one Jacobi sweep
+  std::map<std::pair<int, int>, hipGraphExec_t> qrs;      // (rows, cols) -> Householder QR
   hipStream_t gstream = nullptr;
 
   int chil(int i) const { return i == 0 ? 1 : chi[i - 1]; }
@@ -432,6 +406,7 @@ struct tn_mps {
 
   ~tn_mps() {
     for (auto& kv : sweeps) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : qrs) (void)hipGraphExecDestroy(kv.second);
     for (float2* p : site) (void)hipFree(p);
     for (void* p : {(void*)theta, (void*)tmp, (void*)W, (void*)V, (void*)X, (void*)Q, (void*)R, (void*)tau,
                     (void*)S, (void*)zbuf, (void*)flag, (void*)order, gemm_work})
@@ -442,12 +417,44 @@ struct tn_mps {
 
 namespace {
 
+// Householder QR of X (rows x cols, column-major) into R (k x cols, row-major)
+// and Q (rows x k, column-major), k = min(rows, cols): per step j one
+// reflector kernel and one trailing update (a wave per column), then Q from
+// the reflectors in reverse order.  Captured once per shape as a hipGraph
+// (the buffers are the MPS's own) and replayed on `s`.
+void run_qr(tn_mps* m, int rows, int cols, hipStream_t s) {
+  const auto key = std::make_pair(rows, cols);
+  auto it = m->qrs.find(key);
+  if (it == m->qrs.end()) {
+    const int k = std::min(rows, cols);
+    if (!m->gstream) TN_HIP(hipStreamCreateWithFlags(&m->gstream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    TN_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
+    zero_kernel<<<grid_for(int64_t(k) * cols), 256, 0, m->gstream>>>(m->R, int64_t(k) * cols);
+    for (int j = 0; j < k; ++j) {
+      hh_reflect_kernel<<<1, 256, 0, m->gstream>>>(m->X, rows, cols, j, m->R, m->tau);
+      if (j + 1 < cols)
+        hh_apply_kernel<<<(cols - j - 1 + 3) / 4, 256, 0, m->gstream>>>(m->X, rows, j, m->tau, m->X, j + 1, cols,
+                                                                        m->R, cols);
+    }
+    q_init_kernel<<<grid_for(int64_t(rows) * k), 256, 0, m->gstream>>>(m->Q, rows, k);
+    for (int j = k - 1; j >= 0; --j)
+      hh_apply_kernel<<<(k - j + 3) / 4, 256, 0, m->gstream>>>(m->X, rows, j, m->tau, m->Q, j, k, nullptr, 0);
+    const hipError_t e = hipStreamEndCapture(m->gstream, &g);
+    TN_REQUIRE(e == hipSuccess, TN_ERR_DEVICE, "graph capture of the QR failed");
+    TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    it = m->qrs.emplace(key, ge).first;
+  }
+  TN_HIP(hipGraphLaunch(it->second, s));   // stream-ordered with the caller's work
+}
+
 void move_right(tn_mps* m, int c, hipStream_t s) {
   const int cl = m->chil(c), cr = m->chir(c);
   const int rows = 2 * cl, cols = cr, k = std::min(rows, cols);
   site_to_x_kernel<<<grid_for(int64_t(cl) * 2 * cr), 256, 0, s>>>(m->site[c], m->X, cl, cr, 0);
-  householder_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->R, m->tau);
-  form_q_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->tau, m->Q);
+  run_qr(m, rows, cols, s);
   q_to_site_kernel<<<grid_for(int64_t(rows) * k), 256, 0, s>>>(m->Q, m->site[c], rows, k, 0);
   // next site: (cr, 2, cr2) -> (k, 2, cr2)
   const int cr2 = m->chir(c + 1);
@@ -463,8 +470,7 @@ void move_left(tn_mps* m, int c, hipStream_t s) {
   const int cl = m->chil(c), cr = m->chir(c);
   const int rows = 2 * cr, cols = cl, k = std::min(rows, cols);   // X = A^dagger
   site_to_x_kernel<<<grid_for(int64_t(cl) * 2 * cr), 256, 0, s>>>(m->site[c], m->X, cl, cr, 1);
-  householder_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->R, m->tau);
-  form_q_kernel<<<1, 1024, 0, s>>>(m->X, rows, cols, m->tau, m->Q);
+  run_qr(m, rows, cols, s);
   // A_c = Q^dagger : (k, 2 cr)
   q_to_site_kernel<<<grid_for(int64_t(rows) * k), 256, 0, s>>>(m->Q, m->site[c], rows, k, 1);
   // previous site (cl2, 2, cl) -> (cl2, 2, k): B R^dagger
