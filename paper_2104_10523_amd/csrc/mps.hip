@@ -97,53 +97,103 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // One round of the parallel (circle-method) ordering: block k rotates the
-// column pair (p, q) of W (mm x nn, column-major) and of V (nn x nn).
+// column pair (p, q) of W (mm x nn, column-major) and of V (nn x nn).  Each
+// thread keeps up to kJRowsPerThread rows of both pairs in registers, so the
+// V columns are fetched together with W, and the four sums share one
+// two-barrier reduction; larger matrices stream the rest from memory.
+constexpr int kJRowsPerThread = 2;
+
+__device__ __forceinline__ void rotate(double2& a, double2& b, double c, double2 sp, double2 sm) {
+  const double2 sb = cmul(sm, b), sa = cmul(sp, a);
+  a = make_double2(c * a.x - sb.x, c * a.y - sb.y);
+  b = make_double2(sa.x + c * b.x, sa.y + c * b.y);
+}
+
 __global__ __launch_bounds__(256) void jacobi_round_kernel(double2* __restrict__ W, double2* __restrict__ V,
                                                            int mm, int nn, int npad, int round, double tol,
                                                            int* flag) {
-  __shared__ double red[3][8];
-  const int k = blockIdx.x;
+  __shared__ double red[4][4];
+  const int k = blockIdx.x, tid = threadIdx.x;
   auto idx = [&](int i) { return i == 0 ? 0 : ((i - 1 + round) % (npad - 1)) + 1; };
   int p = idx(k), q = idx(npad - 1 - k);
   if (p > q) { const int t = p; p = q; q = t; }
   if (q >= nn) return;  // pair with the padding column
   double2* wp = W + int64_t(p) * mm;
   double2* wq = W + int64_t(q) * mm;
+  double2* vp = V + int64_t(p) * nn;
+  double2* vq = V + int64_t(q) * nn;
+  double2 ra[kJRowsPerThread], rb[kJRowsPerThread], va[kJRowsPerThread], vb[kJRowsPerThread];
+#pragma unroll
+  for (int u = 0; u < kJRowsPerThread; ++u) {
+    const int i = tid + 256 * u;
+    ra[u] = i < mm ? wp[i] : make_double2(0, 0);
+    rb[u] = i < mm ? wq[i] : make_double2(0, 0);
+    va[u] = i < nn ? vp[i] : make_double2(0, 0);
+    vb[u] = i < nn ? vq[i] : make_double2(0, 0);
+  }
   double al = 0, be = 0, gr = 0, gi = 0;
-  for (int i = threadIdx.x; i < mm; i += blockDim.x) {
-    const double2 a = wp[i], b = wq[i];
+  auto accum = [&](double2 a, double2 b) {
     al += a.x * a.x + a.y * a.y;
     be += b.x * b.x + b.y * b.y;
     gr += a.x * b.x + a.y * b.y;
     gi += a.x * b.y - a.y * b.x;
+  };
+#pragma unroll
+  for (int u = 0; u < kJRowsPerThread; ++u) accum(ra[u], rb[u]);
+  for (int i = tid + 256 * kJRowsPerThread; i < mm; i += 256) accum(wp[i], wq[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    al += __shfl_xor(al, o);
+    be += __shfl_xor(be, o);
+    gr += __shfl_xor(gr, o);
+    gi += __shfl_xor(gi, o);
   }
-  al = block_sum(al, red[0]);
-  be = block_sum(be, red[1]);
-  gr = block_sum(gr, red[2]);
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[0][w] = al;
+    red[1][w] = be;
+    red[2][w] = gr;
+    red[3][w] = gi;
+  }
   __syncthreads();
-  gi = block_sum(gi, red[0]);
+  al = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  be = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  gr = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  gi = red[3][0] + red[3][1] + red[3][2] + red[3][3];
   const double g = sqrt(gr * gr + gi * gi);
   if (!(g > tol * sqrt(al * be)) || g == 0.0) return;
-  if (threadIdx.x == 0) *flag = 1;
+  if (tid == 0) *flag = 1;
   const double zeta = (be - al) / (2.0 * g);
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
   const double2 e = make_double2(gr / g, gi / g);               // e^{i phi}
   const double2 sp = make_double2(s * e.x, s * e.y);             // s e^{i phi}
   const double2 sm = make_double2(s * e.x, -s * e.y);            // s e^{-i phi}
-  for (int i = threadIdx.x; i < mm; i += blockDim.x) {
-    const double2 a = wp[i], b = wq[i];
-    const double2 sb = cmul(sm, b), sa = cmul(sp, a);
-    wp[i] = make_double2(c * a.x - sb.x, c * a.y - sb.y);
-    wq[i] = make_double2(sa.x + c * b.x, sa.y + c * b.y);
+#pragma unroll
+  for (int u = 0; u < kJRowsPerThread; ++u) {
+    const int i = tid + 256 * u;
+    if (i < mm) {
+      rotate(ra[u], rb[u], c, sp, sm);
+      wp[i] = ra[u];
+      wq[i] = rb[u];
+    }
+    if (i < nn) {
+      rotate(va[u], vb[u], c, sp, sm);
+      vp[i] = va[u];
+      vq[i] = vb[u];
+    }
   }
-  double2* vp = V + int64_t(p) * nn;
-  double2* vq = V + int64_t(q) * nn;
-  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-    const double2 a = vp[i], b = vq[i];
-    const double2 sb = cmul(sm, b), sa = cmul(sp, a);
-    vp[i] = make_double2(c * a.x - sb.x, c * a.y - sb.y);
-    vq[i] = make_double2(sa.x + c * b.x, sa.y + c * b.y);
+  for (int i = tid + 256 * kJRowsPerThread; i < mm; i += 256) {
+    double2 a = wp[i], b = wq[i];
+    rotate(a, b, c, sp, sm);
+    wp[i] = a;
+    wq[i] = b;
+  }
+  for (int i = tid + 256 * kJRowsPerThread; i < nn; i += 256) {
+    double2 a = vp[i], b = vq[i];
+    rotate(a, b, c, sp, sm);
+    vp[i] = a;
+    vq[i] = b;
   }
 }
 
