@@ -8,10 +8,10 @@
 // probabilities: the pass that applies a gate also accumulates (FP64) the
 // joint marginal of the gate's qubits; the next pass first reduces those
 // partials, draws the damping branches from the uniforms, and applies the
-// chosen Kraus operators (renormalised) together with its own gate as one
-// 16 x 16 operator on four local qubit bits.  Trajectories are sorted by
-// length so the active ones form a prefix (uneven depths).  The final pass
-// applies the last damping; a last kernel accumulates <Z_q>.
+// chosen Kraus operators (renormalised), then its own gate, to amplitudes
+// held in registers in groups of 16 (four local index bits).  Trajectories
+// are sorted by length so the active ones form a prefix (uneven depths).
+// The final pass applies the last damping; a last kernel accumulates <Z_q>.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +26,7 @@
 namespace tn {
 namespace {
 
-constexpr int kBlocksPerTraj = 128;
+constexpr int kBlocksPerTraj = 64;
 constexpr int kMaxQubits = 30;
 
 struct GroupDesc {
@@ -43,43 +43,126 @@ __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Local bit of a qubit inside the 4-bit group, or -1.
-__device__ __forceinline__ int local_of(const int* upos, int bitpos) {
-  for (int i = 0; i < 4; ++i)
-    if (upos[i] == bitpos) return i;
-  return -1;
-}
-
 __global__ void init_state_kernel(float2* __restrict__ psi, int64_t dim) {
   const int64_t t = blockIdx.y;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < dim; i += int64_t(gridDim.x) * blockDim.x)
     psi[t * dim + i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
 }
 
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
+  return make_float2(acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x);
+}
+
+// The 2 x 2 operator A (row-major) on local bit B of the 16 register values.
+template <int B>
+__device__ __forceinline__ void apply_bit(float2 (&v)[16], const float2 (&A)[4]) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i & (1 << B)) continue;
+    const int j = i | (1 << B);
+    const float2 x = v[i], y = v[j];
+    v[i] = cfma(A[1], y, cmulf(A[0], x));
+    v[j] = cfma(A[3], y, cmulf(A[2], x));
+  }
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+struct PassOps {
+  float2 g4[16];        // gate x damping on local bits 0-1, scaled by the renormalisation
+  float2 A2[4], A3[4];  // damping Kraus operators on local bits 2 and 3 (identity if none)
+  int nq;               // gate arity (marginal index: i & 3, i & 1 or 0)
+};
+
+// The pass over this block's groups: 16 amplitudes per thread (addresses
+// base | bits of e); the state is read and written once per pass, so the
+// accesses are non-temporal.
+__device__ __forceinline__ void run_groups(float2* st, int64_t groups, int nblk, const int (&sorted)[4],
+                                           const int64_t (&bit)[4], const PassOps* os, double (&m4)[4]) {
+  float2 g4[16], A2[4], A3[4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) g4[i] = os->g4[i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    A2[i] = os->A2[i];
+    A3[i] = os->A3[i];
+  }
+  const int nq = os->nq;
+  for (int64_t gidx = int64_t(blockIdx.x) * 256 + threadIdx.x; gidx < groups; gidx += int64_t(nblk) * 256) {
+    int64_t base = gidx;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int p = sorted[a];
+      base = ((base >> p) << (p + 1)) | (base & ((int64_t(1) << p) - 1));
+    }
+    int64_t addr[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      addr[e] = base | ((e & 1) ? bit[0] : 0) | ((e & 2) ? bit[1] : 0) | ((e & 4) ? bit[2] : 0) |
+                ((e & 8) ? bit[3] : 0);
+    float2 v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const f2v x = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(st + addr[e]));
+      v[e] = make_float2(x.x, x.y);
+    }
+    apply_bit<2>(v, A2);   // identity unless a damped qubit sits there
+    apply_bit<3>(v, A3);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const float2 x0 = v[4 * h], x1 = v[4 * h + 1], x2 = v[4 * h + 2], x3 = v[4 * h + 3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        v[4 * h + r] = cfma(g4[4 * r + 3], x3, cfma(g4[4 * r + 2], x2, cfma(g4[4 * r + 1], x1, cmulf(g4[4 * r], x0))));
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const f2v x = {v[i].x, v[i].y};
+      __builtin_nontemporal_store(x, reinterpret_cast<f2v*>(st + addr[i]));
+      const double pr = double(v[i].x) * v[i].x + double(v[i].y) * v[i].y;
+      if (nq == 2) m4[i & 3] += pr;
+      else if (nq == 1) m4[i & 1] += pr;
+      else m4[0] += pr;
+    }
+  }
+}
+
 // One pass.  blockIdx.y = trajectory slot (sorted, active prefix);
-// blockIdx.x = block within the trajectory.
+// blockIdx.x = block within the trajectory (nblk of them; the previous pass
+// used nblk_prev).  Each thread holds 16 amplitudes that differ in four
+// index bits: the current gate's qubits sit on local bits 0 (second qubit)
+// and 1 (first qubit), the previous gate's qubits follow, then the highest
+// unused index bits, so consecutive lanes touch consecutive amplitudes.  The
+// chosen damping Kraus operators of the previous group act first: those on
+// local bits 2-3 as 2 x 2 operators, those on bits 0-1 folded into the gate's
+// 4 x 4 operator (scaled by the renormalisation), which acts last.
 __global__ __launch_bounds__(256) void traj_pass_kernel(float2* __restrict__ psi, int n,
                                                         const GroupDesc* __restrict__ desc, int max_len,
-                                                        const int* __restrict__ len, int pass,
-                                                        const double* __restrict__ part_prev,
+                                                        const int* __restrict__ len, int pass, int nblk,
+                                                        int nblk_prev, const double* __restrict__ part_prev,
                                                         double* __restrict__ part_cur) {
-  __shared__ float2 M[16][16];
-  __shared__ float2 Gs[16][16], Ds[16][16];
+  __shared__ PassOps ops_s;
   __shared__ int upos[4];
-  __shared__ int cur_local[2], prev_local[2];
-  __shared__ float2 Dq[2][4];          // per damped local qubit: chosen Kraus (2x2)
-  __shared__ int dq_local[2], n_dq;
-  __shared__ double dscale;
-  __shared__ double red[256];
+  __shared__ double redp[4][4];
   const int t = blockIdx.y;
   const int L = len[t];
   const int64_t dim = int64_t(1) << n;
   const GroupDesc* cur = pass < L ? desc + int64_t(t) * max_len + pass : nullptr;
   const GroupDesc* prev = pass > 0 ? desc + int64_t(t) * max_len + pass - 1 : nullptr;
   const int tid = threadIdx.x;
+  const bool damp = prev && prev->n_damp > 0;
+  if (damp) {
+    // joint marginal of the previous gate's qubits: the previous pass's
+    // per-block partials, reduced in a fixed order
+    const double* pp = part_prev + int64_t(t) * nblk_prev * 4;
+    double acc = 0;
+    for (int x = tid; x < nblk_prev * 4; x += 256) acc += pp[x];
+#pragma unroll
+    for (int o = 32; o >= 4; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((tid & 63) < 4) redp[tid >> 6][tid & 3] = acc;
+  }
+  __syncthreads();
   if (tid == 0) {
-    // local bit positions: current gate qubits first, then the previous
-    // gate's qubits, then the lowest unused index bits
     int k = 0;
     auto add = [&](int bp) {
       for (int i = 0; i < k; ++i)
@@ -88,155 +171,120 @@ __global__ __launch_bounds__(256) void traj_pass_kernel(float2* __restrict__ psi
     };
     if (cur && cur->nq == 2) { add(n - 1 - cur->q[1]); add(n - 1 - cur->q[0]); }
     if (cur && cur->nq == 1) add(n - 1 - cur->q[0]);
-    if (prev && prev->n_damp > 0) {
+    if (damp)
       for (int i = 0; i < prev->nq; ++i) add(n - 1 - prev->q[i]);
+    for (int bp = n - 1; k < 4 && bp >= 0; --bp) add(bp);
+    PassOps& o = ops_s;
+    o.nq = cur ? cur->nq : 0;
+    float2 Dl[2][4];     // damping on local bits 0 and 1 (identity if none)
+    for (int i = 0; i < 4; ++i) {
+      const float2 id = make_float2(i == 0 || i == 3 ? 1.f : 0.f, 0.f);
+      o.A2[i] = o.A3[i] = Dl[0][i] = Dl[1][i] = id;
     }
-    for (int bp = 0; k < 4 && bp < n; ++bp) add(bp);
-    // damping decisions of the previous group from its marginals
-    n_dq = 0;
-    dscale = 1.0;
-    if (prev && prev->n_damp > 0) {
-      double P[4] = {0, 0, 0, 0};
-      const double* pp = part_prev + int64_t(t) * kBlocksPerTraj * 4;
-      for (int b = 0; b < kBlocksPerTraj; ++b)
-        for (int j = 0; j < 4; ++j) P[j] += pp[b * 4 + j];
+    double dscale = 1.0;
+    if (damp) {
+      // damping decisions of the previous group from its marginals; P is
+      // indexed by (first qubit's bit) x 2 + second's
+      double P[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) P[j] = redp[0][j] + redp[1][j] + redp[2][j] + redp[3][j];
       const int pn = prev->nq;
       for (int e = 0; e < prev->n_damp; ++e) {
         const int lq = prev->damp_lq[e];
-        const int bit = pn == 2 ? (lq == 0 ? 1 : 0) : 0;   // q[0] is the high bit of P's index
+        const int bit = pn == 2 ? (lq == 0 ? 1 : 0) : 0;
         const double g = prev->gamma[e];
         double T = 0, P1 = 0;
-        for (int x = 0; x < (1 << pn); ++x) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
           T += P[x];
           if ((x >> bit) & 1) P1 += P[x];
         }
         const double p0 = T > 0 ? (T - g * P1) / T : 1.0;
         const int kb = prev->u[e] < p0 ? 0 : 1;
-        float2* A = Dq[n_dq];
-        if (kb == 0) {
-          A[0] = make_float2(1.f, 0.f); A[1] = make_float2(0.f, 0.f);
-          A[2] = make_float2(0.f, 0.f); A[3] = make_float2(float(sqrt(1.0 - g)), 0.f);
-          for (int x = 0; x < (1 << pn); ++x)
+        float2 A[4];
+        if (kb == 0) {   // A0 = diag(1, sqrt(1 - g))
+          A[0] = make_float2(1.f, 0.f);
+          A[1] = A[2] = make_float2(0.f, 0.f);
+          A[3] = make_float2(float(sqrt(1.0 - g)), 0.f);
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
             if ((x >> bit) & 1) P[x] *= (1.0 - g);
-        } else {
-          A[0] = make_float2(0.f, 0.f); A[1] = make_float2(float(sqrt(g)), 0.f);
-          A[2] = make_float2(0.f, 0.f); A[3] = make_float2(0.f, 0.f);
-          for (int x = 0; x < (1 << pn); ++x)
-            if ((x >> bit) & 1) {
-              P[x & ~(1 << bit)] = g * P[x];
-              P[x] = 0;
-            }
+        } else {         // A1 = sqrt(g) |0><1|
+          A[0] = A[2] = A[3] = make_float2(0.f, 0.f);
+          A[1] = make_float2(float(sqrt(g)), 0.f);
+          double Q[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            double up = 0;   // P[x with the damped bit set]
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+              if (y == (x | (1 << bit))) up = P[y];
+            Q[x] = ((x >> bit) & 1) ? 0.0 : g * up;
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x) P[x] = Q[x];
         }
-        dq_local[n_dq] = local_of(upos, n - 1 - prev->q[lq]);
-        n_dq++;
+        const int bp = n - 1 - prev->q[lq];
+        int loc = 0;
+        for (int i = 0; i < 4; ++i)
+          if (upos[i] == bp) loc = i;
+        float2* dst = loc == 0 ? Dl[0] : loc == 1 ? Dl[1] : loc == 2 ? o.A2 : o.A3;
+        for (int i = 0; i < 4; ++i) dst[i] = A[i];
       }
       double N2 = 0;
+#pragma unroll
       for (int x = 0; x < 4; ++x) N2 += P[x];
       dscale = N2 > 0 ? 1.0 / sqrt(N2) : 1.0;
     }
-    cur_local[0] = cur && cur->nq >= 1 ? local_of(upos, n - 1 - cur->q[0]) : -1;
-    cur_local[1] = cur && cur->nq == 2 ? local_of(upos, n - 1 - cur->q[1]) : -1;
-  }
-  __syncthreads();
-  // G16 and D16 on the four local bits, then M = G16 * D16
-  {
-    const int i = tid >> 4, j = tid & 15;
-    float2 g = make_float2(0.f, 0.f);
-    if (!cur || cur->nq == 0) {
-      g = make_float2(i == j ? 1.f : 0.f, 0.f);
-    } else if (cur->nq == 1) {
-      const int b = cur_local[0];
-      if (((i ^ j) & ~(1 << b)) == 0) g = cur->G[((i >> b) & 1) * 2 + ((j >> b) & 1)];
-    } else {
-      const int b0 = cur_local[0], b1 = cur_local[1];
-      if (((i ^ j) & ~((1 << b0) | (1 << b1))) == 0) {
-        const int ri = ((i >> b0) & 1) * 2 + ((i >> b1) & 1), ci = ((j >> b0) & 1) * 2 + ((j >> b1) & 1);
-        g = cur->G[ri * 4 + ci];
-      }
-    }
-    Gs[i][j] = g;
-    float2 d = make_float2(i == j ? 1.f : 0.f, 0.f);
-    if (n_dq > 0) {
-      int mask = 0;
-      for (int e = 0; e < n_dq; ++e) mask |= 1 << dq_local[e];
-      if (((i ^ j) & ~mask) == 0) {
-        d = make_float2(float(dscale), 0.f);
-        for (int e = 0; e < n_dq; ++e) {
-          const int b = dq_local[e];
-          d = cmulf(d, Dq[e][((i >> b) & 1) * 2 + ((j >> b) & 1)]);
+    // the gate on local bits 0-1 (rows: first qubit's bit x 2 + second's),
+    // times the damping on those bits (applied first), times the scale
+    float2 Gm[16], Dm[16];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        float2 g = make_float2(0.f, 0.f);
+        if (!cur || cur->nq == 0) {
+          if (r == c) g = make_float2(1.f, 0.f);
+        } else if (cur->nq == 1) {
+          if ((r >> 1) == (c >> 1)) g = cur->G[(r & 1) * 2 + (c & 1)];
+        } else {
+          g = cur->G[r * 4 + c];
         }
-      } else {
-        d = make_float2(0.f, 0.f);
+        Gm[r * 4 + c] = g;
+        // local bit 1 is the high bit of the 4 x 4 index
+        Dm[r * 4 + c] = cmulf(Dl[1][(r >> 1) * 2 + (c >> 1)], Dl[0][(r & 1) * 2 + (c & 1)]);
       }
-    }
-    Ds[i][j] = d;
-  }
-  __syncthreads();
-  {
-    const int i = tid >> 4, j = tid & 15;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int k = 0; k < 16; ++k) {
-      const float2 p = cmulf(Gs[i][k], Ds[k][j]);
-      acc.x += p.x;
-      acc.y += p.y;
-    }
-    M[i][j] = acc;
+    const float ds = float(dscale);
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int k = 0; k < 4; ++k) acc = cfma(Gm[r * 4 + k], Dm[k * 4 + c], acc);
+        o.g4[r * 4 + c] = make_float2(acc.x * ds, acc.y * ds);
+      }
   }
   __syncthreads();
   int sorted[4] = {upos[0], upos[1], upos[2], upos[3]};
+#pragma unroll
   for (int a = 0; a < 4; ++a)
+#pragma unroll
     for (int b = a + 1; b < 4; ++b)
       if (sorted[b] < sorted[a]) { const int x = sorted[a]; sorted[a] = sorted[b]; sorted[b] = x; }
+  const int64_t bit[4] = {int64_t(1) << upos[0], int64_t(1) << upos[1], int64_t(1) << upos[2],
+                          int64_t(1) << upos[3]};
   float2* st = psi + int64_t(t) * dim;
   double m4[4] = {0, 0, 0, 0};
-  const int64_t groups = dim >> 4;
-  const int c0 = cur_local[0], c1 = cur_local[1];
-  const int64_t bit0 = int64_t(1) << upos[0], bit1 = int64_t(1) << upos[1], bit2 = int64_t(1) << upos[2],
-                bit3 = int64_t(1) << upos[3];
-  for (int64_t gidx = int64_t(blockIdx.x) * 256 + tid; gidx < groups; gidx += int64_t(kBlocksPerTraj) * 256) {
-    int64_t base = gidx;
-    for (int a = 0; a < 4; ++a) {
-      const int p = sorted[a];
-      base = ((base >> p) << (p + 1)) | (base & ((int64_t(1) << p) - 1));
-    }
-    auto addr_of = [&](int e) {
-      return base | ((e & 1) ? bit0 : 0) | ((e & 2) ? bit1 : 0) | ((e & 4) ? bit2 : 0) | ((e & 8) ? bit3 : 0);
-    };
-    float2 v[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) v[e] = st[addr_of(e)];
-    // one output row at a time: the operator stays in LDS (broadcast reads)
-#pragma unroll 1
-    for (int i = 0; i < 16; ++i) {
-      float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const float2 p = cmulf(M[i][j], v[j]);
-        acc.x += p.x;
-        acc.y += p.y;
-      }
-      st[addr_of(i)] = acc;
-      const double pr = double(acc.x) * acc.x + double(acc.y) * acc.y;
-      int x = 0;
-      if (c1 >= 0) x = ((i >> c0) & 1) * 2 + ((i >> c1) & 1);
-      else if (c0 >= 0) x = (i >> c0) & 1;
-      m4[0] += x == 0 ? pr : 0.0;
-      m4[1] += x == 1 ? pr : 0.0;
-      m4[2] += x == 2 ? pr : 0.0;
-      m4[3] += x == 3 ? pr : 0.0;
-    }
-  }
+  run_groups(st, dim >> 4, nblk, sorted, bit, &ops_s, m4);
   // block reductions in a fixed order (deterministic)
+  __shared__ double redm[4][4];
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
-    red[tid] = m4[k];
-    __syncthreads();
-    for (int w2 = 128; w2 > 0; w2 >>= 1) {
-      if (tid < w2) red[tid] += red[tid + w2];
-      __syncthreads();
-    }
-    if (tid == 0) part_cur[(int64_t(t) * kBlocksPerTraj + blockIdx.x) * 4 + k] = red[0];
-    __syncthreads();
+    double x = m4[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if ((tid & 63) == 0) redm[tid >> 6][k] = x;
   }
+  __syncthreads();
+  if (tid < 4)
+    part_cur[(int64_t(t) * nblk + blockIdx.x) * 4 + tid] = redm[0][tid] + redm[1][tid] + redm[2][tid] + redm[3][tid];
 }
 
 // Per-block sums of |psi_x|^2 and of |psi_x|^2 x_q for every qubit q.
@@ -423,7 +471,13 @@ extern "C" tn_status tn_run_trajectories(const tn_circuit* const* circs, int32_t
                  "cannot allocate the trajectory states");
       TN_HIP(hipMalloc(&ddesc, descs.size() * sizeof(GroupDesc)));
       TN_HIP(hipMalloc(&dlen, n_traj * sizeof(int)));
-      TN_HIP(hipMalloc(&part, size_t(2) * n_traj * kBlocksPerTraj * 4 * sizeof(double)));
+      // blocks per trajectory: at least 4096 blocks per pass while each
+      // thread keeps at least one group (fewer trajectories -> more blocks)
+      const int64_t max_blk = std::max<int64_t>(1, std::min<int64_t>(1024, (dim / 16 + 255) / 256));
+      auto blocks_for = [&](int64_t active) {
+        return int(std::min<int64_t>(max_blk, std::max<int64_t>(64, (4096 + active - 1) / active)));
+      };
+      TN_HIP(hipMalloc(&part, size_t(2) * n_traj * max_blk * 4 * sizeof(double)));
       TN_HIP(hipMalloc(&zpart, size_t(n_traj) * kBlocksPerTraj * (n + 1) * sizeof(double)));
       TN_HIP(hipMalloc(&dz, size_t(n_traj) * n * sizeof(double)));
       TN_HIP(hipMemcpyAsync(ddesc, descs.data(), descs.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
@@ -436,16 +490,19 @@ extern "C" tn_status tn_run_trajectories(const tn_circuit* const* circs, int32_t
       init_state_kernel<<<dim3(unsigned(std::min<int64_t>((dim + 255) / 256, 1024)), unsigned(n_traj)), 256, 0, s>>>(psi, dim);
       TN_HIP(hipGetLastError());
       double bytes = 0;
+      int nblk_prev = 1;
       for (int p = 0; p <= max_len; ++p) {
         int64_t active = 0;
         while (active < n_traj && lens[active] >= p) ++active;
         if (active == 0) break;
-        const double* pp = part + size_t((p + 1) & 1) * n_traj * kBlocksPerTraj * 4;
-        double* pc = part + size_t(p & 1) * n_traj * kBlocksPerTraj * 4;
-        traj_pass_kernel<<<dim3(kBlocksPerTraj, unsigned(active)), 256, 0, s>>>(psi, n, ddesc, max_len, dlen, p,
-                                                                                  pp, pc);
+        const int nblk = blocks_for(active);
+        const double* pp = part + size_t((p + 1) & 1) * n_traj * max_blk * 4;
+        double* pc = part + size_t(p & 1) * n_traj * max_blk * 4;
+        traj_pass_kernel<<<dim3(unsigned(nblk), unsigned(active)), 256, 0, s>>>(psi, n, ddesc, max_len, dlen, p,
+                                                                                 nblk, nblk_prev, pp, pc);
         TN_HIP(hipGetLastError());
         bytes += double(active) * dim * 16.0;
+        nblk_prev = nblk;
       }
       z_partial_kernel<<<dim3(kBlocksPerTraj, unsigned(n_traj)), 256, 0, s>>>(psi, n, zpart);
       TN_HIP(hipGetLastError());
@@ -466,7 +523,7 @@ extern "C" tn_status tn_run_trajectories(const tn_circuit* const* circs, int32_t
         std::memset(rep, 0, sizeof(*rep));
         rep->seconds = ms * 1e-3;
         rep->bytes = bytes;
-        rep->flops = bytes / 16.0 * 16 * 8;   // 16x16 operator per 16 amplitudes
+        rep->flops = bytes / 16.0 * 4 * 8;    // 4x4 gate operator per 4 amplitudes
         rep->slices_run = double(n_traj);
         rep->kernels = double(max_len + 2);
       }

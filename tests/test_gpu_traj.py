@@ -71,3 +71,19 @@ def test_uneven_depth_batch(gpu):
     z, _ = run_gpu(circuits, tpc, U)
     zo = noise.trajectories_expect_z(circuits, tpc, U)
     assert np.abs(z - zo).max() <= 2e-5
+
+
+@pytest.mark.parametrize("rows,cols,depth", [(3, 4, 6), (4, 4, 5)])
+def test_trajectories_wide_registers(gpu, rows, cols, depth):
+    """12 and 16 qubits: many 16-amplitude groups per block and several
+    blocks per trajectory, damping on every gate."""
+    circuits = []
+    for c in range(2):
+        n, ops = grid_random_circuit(rows, cols, depth + c, 70 + c)
+        circuits.append((n, noisy_ops(ops, 0.02, 0.05, 0.1)))
+    tpc = 3
+    ev = max(count_channel_events(o) for _, o in circuits)
+    U = trajectory_uniforms(len(circuits) * tpc, ev, 11)
+    z, _ = run_gpu(circuits, tpc, U)
+    zo = noise.trajectories_expect_z(circuits, tpc, U)
+    assert np.abs(z - zo).max() <= 5e-5
