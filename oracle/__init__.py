@@ -19,6 +19,9 @@ Modules
     noise       O3 density matrix and O4 Kraus trajectories
     mps         O5: matrix-product-state simulator with SVD truncation
     gnn         O7: the contraction-order scorer, forward and backward, FP64
+    observables Pauli-string expectation values: definition, conjugate
+                (double-depth) network with light-cone collapse, and
+                wave-function slicing
 
 Parity pins are listed in each module header; functions without one say
 "parity unpinned".
