@@ -369,6 +369,42 @@ tn_status tn_amplitudes_workspace(const tn_network* n, const tn_path* p,
                                   size_t* bytes);
 
 /* ---------------------------------------------------------------------- */
+/* Expectation values of Pauli strings (Sec. 3.1, operator expectation    */
+/* values: Eq. 2, Table 1)                                                */
+/* ---------------------------------------------------------------------- */
+
+/* A Pauli string is an int8 array of n_qubits entries TN_PAULI_*. */
+enum { TN_PAULI_I = 0, TN_PAULI_X = 1, TN_PAULI_Y = 2, TN_PAULI_Z = 3 };
+
+/* Conjugate (double-depth) network of <Psi|P|Psi> = <0|C^dagger P C|0>,
+ * Psi = C|0..0>.  A gate that contracts with its own conjugate (every gate
+ * outside the backward light cone of P's support) is dropped with it before
+ * the network is built; `kept_ops` (may be NULL) receives the number of
+ * gates of C that remain.  The network is the one of the circuit C_L, P,
+ * C_L^dagger (adjoints as CUSTOM gates), with the same folding and labels as
+ * tn_build_network: find a path with no open qubits, and tn_amplitudes with
+ * the all-zero bit-string returns <P> (real up to rounding).  Host only.
+ * Errors: TN_ERR_ARG (null, sizes, Pauli entries outside 0..3), TN_ERR_GATE
+ * (channel op, unknown id, bad qubit). */
+tn_status tn_build_expectation_network(const tn_circuit* c, const int8_t* pauli,
+                                       tn_network** out, int64_t* kept_ops);
+
+/* <P> by wave-function slicing: `psi` is the device output of tn_amplitudes
+ * for the n_slices bit-strings `bits` (host, n_slices x n_qubits, 0 / 1 for
+ * projected qubits, -1 for the open qubits, the same open set in every row),
+ * i.e. n_slices x 2^#open complex128.  Returns in out[0], out[1] (host) the
+ * real and imaginary parts of sum_s <psi_s|P|psi_s>, accumulated in FP64 on
+ * the device in a fixed order.  X and Y factors of P must act on open
+ * qubits; a Z factor on a projected qubit contributes the slice's sign.  At
+ * most 30 open qubits.  Allocates a small device scratch and synchronises
+ * the stream.  Errors: TN_ERR_ARG (null, sizes, Pauli entries, X/Y on a
+ * projected qubit), TN_ERR_BITS (values, open sets differ), TN_ERR_UNSUPPORTED,
+ * TN_ERR_DEVICE. */
+tn_status tn_pauli_expectation(const void* psi, const int8_t* bits, int64_t n_slices,
+                               int32_t n_qubits, const int8_t* pauli, double* out,
+                               void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Matrix product states (Sec. 3.2)                                       */
 /* ---------------------------------------------------------------------- */
 

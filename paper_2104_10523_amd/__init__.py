@@ -13,13 +13,13 @@ from typing import Iterable, List, Optional, Sequence
 
 import numpy as np
 
-from ._native import (GATE_IDS, PATH_ALGO, PREC, TnCircuit, TnExecOpts, TnNetworkInfo, TnOp,
+from ._native import (GATE_IDS, PATH_ALGO, PAULI, PREC, TnCircuit, TnExecOpts, TnNetworkInfo, TnOp,
                       TnPathCost, TnPathOpts, TnReport, TnTensor, TnError, check, lib)
 
 __all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
            "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
-           "tn_amplitudes_workspace", "tn_mps_create", "tn_mps_apply_gate",
-           "tn_run_trajectories", "PREC", "lib"]
+           "tn_amplitudes_workspace", "tn_build_expectation_network", "tn_pauli_expectation",
+           "tn_mps_create", "tn_mps_apply_gate", "tn_run_trajectories", "PREC", "lib"]
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -221,6 +221,52 @@ def tn_amplitudes(net: Network, path: Path, bits, out=None, precision: str = "fp
                               C.byref(o), C.c_void_p(out.data_ptr()), C.byref(rep),
                               C.c_void_p(_stream_ptr(stream))))
     return out, rep
+
+
+def _pauli_array(n_qubits: int, pauli) -> np.ndarray:
+    """Pauli string as int8 TN_PAULI_* codes: a string like "IZZI", a dict
+    {qubit: "X"|"Y"|"Z"}, or a sequence of codes 0..3."""
+    if isinstance(pauli, str):
+        assert len(pauli) == n_qubits
+        arr = [PAULI[c] for c in pauli.upper()]
+    elif isinstance(pauli, dict):
+        arr = [0] * n_qubits
+        for q, c in pauli.items():
+            arr[int(q)] = PAULI[c.upper()] if isinstance(c, str) else int(c)
+    else:
+        arr = list(pauli)
+    a = np.ascontiguousarray(np.asarray(arr, dtype=np.int8))
+    assert a.size == n_qubits
+    return a
+
+
+def tn_build_expectation_network(n_qubits: int, ops, pauli):
+    """Double-depth network of <Psi|P|Psi> after the light-cone collapse.
+
+    Returns (network, number of gates of the circuit that were kept)."""
+    ca = _CircuitArgs(n_qubits, ops)
+    p = _pauli_array(n_qubits, pauli)
+    h = C.c_void_p()
+    kept = C.c_int64()
+    check(lib().tn_build_expectation_network(C.byref(ca.circ), p.ctypes.data_as(C.POINTER(C.c_int8)),
+                                             C.byref(h), C.byref(kept)))
+    return Network(h.value, n_qubits), int(kept.value)
+
+
+def tn_pauli_expectation(psi, bits, pauli, stream=None) -> complex:
+    """sum_s <psi_s|P|psi_s> over wave-function slices: psi is the complex128
+    CUDA tensor tn_amplitudes returned for the bit-strings `bits`."""
+    b = np.ascontiguousarray(np.asarray(bits, dtype=np.int8))
+    if b.ndim == 1:
+        b = b[None, :]
+    n_slices, n_qubits = b.shape
+    p = _pauli_array(n_qubits, pauli)
+    assert psi.is_contiguous() and psi.shape[0] == n_slices
+    out = (C.c_double * 2)()
+    check(lib().tn_pauli_expectation(C.c_void_p(psi.data_ptr()), b.ctypes.data_as(C.POINTER(C.c_int8)),
+                                     n_slices, n_qubits, p.ctypes.data_as(C.POINTER(C.c_int8)), out,
+                                     C.c_void_p(_stream_ptr(stream))))
+    return complex(out[0], out[1])
 
 
 class Mps:

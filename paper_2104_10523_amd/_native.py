@@ -23,6 +23,7 @@ GATE_IDS = {
 
 PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3, "f16x3": 4}
 PATH_ALGO = {"greedy": 0, "random_greedy": 1, "learned": 2}
+PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 
 
 class TnOp(C.Structure):
@@ -98,7 +99,9 @@ SIGNATURES = {
     "tn_amplitudes_workspace": (I32, [P, P, I64, I32, C.POINTER(C.c_size_t)]),
     "tn_amplitudes_plan_info": (I32, [P, P, I32, C.POINTER(TnPlanInfo)]),
     "tn_amplitudes_autotune": (I32, [P, P, I32, I32, P]),
-    "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),  # shape: 6 per op
+    "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),  # shape: 8 per op
+    "tn_build_expectation_network": (I32, [C.POINTER(TnCircuit), PI8, PP, C.POINTER(C.c_int64)]),
+    "tn_pauli_expectation": (I32, [P, PI8, I64, I32, PI8, PD, P]),
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),

@@ -1,0 +1,243 @@
+// Expectation values of Pauli strings (Sec. 3.1, operator expectation values:
+// Eq. 2 and the two methods of Table 1).
+//
+// Conjugate (double-depth) network: <Psi|P|Psi> = <0|C^dagger P C|0>.  A gate
+// of C whose output never reaches the support of P meets its own conjugate
+// in C^dagger with nothing in between, and the pair contracts to the
+// identity; walking C backwards from P's support keeps exactly the gates in
+// P's backward light cone.  The kept gates, the Pauli factors as one-qubit
+// gates and the adjoints of the kept gates in reverse order form an ordinary
+// circuit, so its network, path search, slicing and amplitude kernels are
+// the ones of a single amplitude (all-zero bit-string).
+//
+// Wave-function slicing: the amplitudes of every projection of the closed
+// qubits (tn_amplitudes with the open set left open) are reduced on the
+// device as sum_s sum_x conj(psi_s[x]) (P psi_s)[x] in FP64.  X and Y
+// factors must sit on open qubits (they would couple different slices); a
+// Z factor on a projected qubit is a sign per slice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "gates.hpp"
+#include "handles.hpp"
+#include "network.hpp"
+
+namespace tn {
+namespace {
+
+constexpr int kRedBlocks = 512;
+
+// One block-partial of sum_x w_s (-1)^{popc(x & zmask)} conj(psi[s][x]) psi[s][x ^ flip]
+// over a grid-stride range of the flattened (s, x) index; FP64 throughout.
+__global__ __launch_bounds__(256) void pauli_partial_kernel(const double2* __restrict__ psi, int64_t n_slices,
+                                                            int n_open, uint32_t flip, uint32_t zmask,
+                                                            const double* __restrict__ w,
+                                                            double2* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int64_t dim = int64_t(1) << n_open;
+  const int64_t total = n_slices * dim;
+  double re = 0, im = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i >> n_open;
+    const uint32_t x = uint32_t(i & (dim - 1));
+    const double2 a = psi[i];
+    const double2 b = psi[(s << n_open) + (x ^ flip)];
+    const double sg = (__popc(x & zmask) & 1) ? -w[s] : w[s];
+    re += sg * (a.x * b.x + a.y * b.y);   // conj(a) b
+    im += sg * (a.x * b.y - a.y * b.x);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = re;
+    red[1][threadIdx.x >> 6] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    part[blockIdx.x] = make_double2(red[0][0] + red[0][1] + red[0][2] + red[0][3],
+                                    red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+}
+
+// Sum of the block partials in a fixed order (one wave).
+__global__ void pauli_final_kernel(const double2* __restrict__ part, int n, double2* __restrict__ out) {
+  double re = 0, im = 0;
+  for (int i = threadIdx.x; i < n; i += 64) {
+    re += part[i].x;
+    im += part[i].y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  if (threadIdx.x == 0) *out = make_double2(re, im);
+}
+
+}  // namespace
+
+// Ops of C in P's backward light cone, in circuit order.
+std::vector<tn_op> light_cone_ops(const tn_circuit& c, const int8_t* pauli) {
+  std::vector<char> live(c.n_qubits, 0);
+  for (int q = 0; q < c.n_qubits; ++q) {
+    TN_REQUIRE(pauli[q] >= TN_PAULI_I && pauli[q] <= TN_PAULI_Z, TN_ERR_ARG, "Pauli entries must be 0..3");
+    live[q] = pauli[q] != TN_PAULI_I;
+  }
+  std::vector<char> keep(c.n_ops, 0);
+  for (int64_t k = c.n_ops - 1; k >= 0; --k) {
+    const tn_op& op = c.ops[k];
+    TN_REQUIRE(!gate_is_channel(op.gate), TN_ERR_GATE, "expectation networks take unitary gates only");
+    const int ar = gate_arity(op.gate);
+    TN_REQUIRE(op.q0 >= 0 && op.q0 < c.n_qubits && (ar == 1 || (op.q1 >= 0 && op.q1 < c.n_qubits && op.q1 != op.q0)),
+               TN_ERR_GATE, "bad qubit index");
+    const bool hit = live[op.q0] || (ar == 2 && live[op.q1]);
+    if (!hit) continue;
+    keep[k] = 1;
+    live[op.q0] = 1;
+    if (ar == 2) live[op.q1] = 1;
+  }
+  std::vector<tn_op> out;
+  for (int64_t k = 0; k < c.n_ops; ++k)
+    if (keep[k]) out.push_back(c.ops[k]);
+  return out;
+}
+
+}  // namespace tn
+
+using namespace tn;
+
+extern "C" {
+
+tn_status tn_build_expectation_network(const tn_circuit* c, const int8_t* pauli, tn_network** out,
+                                       int64_t* kept_ops) {
+  return guarded([&] {
+    TN_REQUIRE(c && pauli && out, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(c->n_qubits >= 1 && c->n_qubits <= 4096, TN_ERR_ARG, "n_qubits must be 1..4096");
+    TN_REQUIRE(c->n_ops >= 0 && (c->n_ops == 0 || c->ops), TN_ERR_ARG, "bad op array");
+    const std::vector<tn_op> cone = light_cone_ops(*c, pauli);
+    // C_L, then P, then C_L^dagger (each kept gate's adjoint, reverse order)
+    std::vector<tn_op> ops(cone);
+    for (int q = 0; q < c->n_qubits; ++q) {
+      if (pauli[q] == TN_PAULI_I) continue;
+      tn_op p;
+      std::memset(&p, 0, sizeof(p));
+      p.gate = pauli[q] == TN_PAULI_X ? TN_GATE_X : pauli[q] == TN_PAULI_Y ? TN_GATE_Y : TN_GATE_Z;
+      p.q0 = q;
+      p.q1 = -1;
+      ops.push_back(p);
+    }
+    std::vector<std::vector<double>> mats;   // adjoint matrices, alive until the build
+    mats.reserve(cone.size());
+    for (auto it = cone.rbegin(); it != cone.rend(); ++it) {
+      const Mat U = gate_unitary(*it);
+      std::vector<double> m(size_t(2) * U.dim * U.dim);
+      for (int r = 0; r < U.dim; ++r)
+        for (int k = 0; k < U.dim; ++k) {
+          const cd a = std::conj(U(k, r));
+          m[2 * (size_t(r) * U.dim + k)] = a.real();
+          m[2 * (size_t(r) * U.dim + k) + 1] = a.imag();
+        }
+      mats.push_back(std::move(m));
+      tn_op a;
+      std::memset(&a, 0, sizeof(a));
+      a.gate = U.dim == 2 ? TN_GATE_CUSTOM1 : TN_GATE_CUSTOM2;
+      a.q0 = it->q0;
+      a.q1 = U.dim == 2 ? -1 : it->q1;
+      a.matrix = mats.back().data();
+      ops.push_back(a);
+    }
+    tn_circuit dd;
+    dd.n_qubits = c->n_qubits;
+    dd.n_ops = int64_t(ops.size());
+    dd.ops = ops.data();
+    auto n = std::make_unique<tn_network>();
+    n->net = build_network(dd);
+    if (kept_ops) *kept_ops = int64_t(cone.size());
+    *out = n.release();
+  });
+}
+
+tn_status tn_pauli_expectation(const void* psi, const int8_t* bits, int64_t n_slices, int32_t n_qubits,
+                               const int8_t* pauli, double* out, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(psi && bits && pauli && out, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(n_slices >= 1 && n_qubits >= 1 && n_qubits <= 4096, TN_ERR_ARG, "bad sizes");
+    // open set from the first bit-string; every slice must share it
+    std::vector<int> open;
+    for (int q = 0; q < n_qubits; ++q) {
+      TN_REQUIRE(bits[q] >= -1 && bits[q] <= 1, TN_ERR_BITS, "bit values must be 0, 1 or -1");
+      if (bits[q] < 0) open.push_back(q);
+    }
+    const int n_open = int(open.size());
+    TN_REQUIRE(n_open <= 30, TN_ERR_UNSUPPORTED, "at most 30 open qubits");
+    uint32_t flip = 0, zmask = 0;
+    int n_y = 0;
+    for (int j = 0; j < n_open; ++j) {
+      const int q = open[j];
+      const uint32_t b = uint32_t(1) << (n_open - 1 - j);   // first open qubit = most significant bit
+      TN_REQUIRE(pauli[q] >= TN_PAULI_I && pauli[q] <= TN_PAULI_Z, TN_ERR_ARG, "Pauli entries must be 0..3");
+      if (pauli[q] == TN_PAULI_X || pauli[q] == TN_PAULI_Y) flip |= b;
+      if (pauli[q] == TN_PAULI_Y || pauli[q] == TN_PAULI_Z) zmask |= b;
+      if (pauli[q] == TN_PAULI_Y) ++n_y;
+    }
+    // per-slice weight: Z factors on projected qubits
+    std::vector<double> w(n_slices, 1.0);
+    for (int64_t s = 0; s < n_slices; ++s)
+      for (int q = 0; q < n_qubits; ++q) {
+        const int8_t b = bits[s * n_qubits + q];
+        TN_REQUIRE(b >= -1 && b <= 1, TN_ERR_BITS, "bit values must be 0, 1 or -1");
+        TN_REQUIRE((b < 0) == (bits[q] < 0), TN_ERR_BITS, "every slice needs the same open set");
+        if (b < 0) continue;
+        TN_REQUIRE(pauli[q] >= TN_PAULI_I && pauli[q] <= TN_PAULI_Z, TN_ERR_ARG, "Pauli entries must be 0..3");
+        TN_REQUIRE(pauli[q] != TN_PAULI_X && pauli[q] != TN_PAULI_Y, TN_ERR_ARG,
+                   "X and Y factors must act on open qubits");
+        if (pauli[q] == TN_PAULI_Z && b == 1) w[s] = -w[s];
+      }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* dw = nullptr;
+    double2* part = nullptr;
+    double2* res = nullptr;
+    auto cleanup = [&]() {
+      for (void* p : {(void*)dw, (void*)part, (void*)res})
+        if (p) (void)hipFree(p);
+    };
+    try {
+      TN_HIP(hipMalloc(&dw, size_t(n_slices) * sizeof(double)));
+      TN_HIP(hipMalloc(&part, kRedBlocks * sizeof(double2)));
+      TN_HIP(hipMalloc(&res, sizeof(double2)));
+      TN_HIP(hipMemcpyAsync(dw, w.data(), size_t(n_slices) * sizeof(double), hipMemcpyHostToDevice, st));
+      const int64_t total = n_slices << n_open;
+      const int blocks = int(std::min<int64_t>(kRedBlocks, (total + 255) / 256));
+      pauli_partial_kernel<<<blocks, 256, 0, st>>>(static_cast<const double2*>(psi), n_slices, n_open, flip, zmask,
+                                                   dw, part);
+      TN_HIP(hipGetLastError());
+      pauli_final_kernel<<<1, 64, 0, st>>>(part, blocks, res);
+      TN_HIP(hipGetLastError());
+      double2 r;
+      TN_HIP(hipMemcpyAsync(&r, res, sizeof(double2), hipMemcpyDeviceToHost, st));
+      TN_HIP(hipStreamSynchronize(st));
+      // (-i)^{n_y}: each Y contributes -i on top of its flip and sign
+      double re = r.x, im = r.y;
+      for (int k = 0; k < (n_y & 3); ++k) {
+        const double t = re;
+        re = im;
+        im = -t;
+      }
+      out[0] = re;
+      out[1] = im;
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
+  });
+}
+
+}  // extern "C"
