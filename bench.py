@@ -84,7 +84,7 @@ def parse():
     ap.add_argument("--cycles", type=int, default=14)
     ap.add_argument("--autotune", action="store_true",
                     help="run the GEMM tile autotuner first (its proxy launches then appear in kernel traces)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "learned"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "learned", "expval"],
                     help="c2 (default) is the benchmark line; the others measure the remaining rows")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
@@ -414,7 +414,114 @@ def bench_learned(a):
             "roofline": None, "cpu_baseline": None}
 
 
-ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "learned": bench_learned}
+def bench_expval(a):
+    """Pauli expectation values (Eq. 2, Table 1).  Conjugate network: <Z Z>
+    on two central qubits of a 7x7 grid, 10 fSim cycles, after the light-cone
+    collapse, every slice of the double-depth network timed with per-op
+    events; FP32 beside it for the error.  Wave-function slicing: the same
+    observable on a 5x5 grid, 10 cycles, 20 open qubits (32 slices),
+    checked against the conjugate method on that circuit."""
+    import itertools
+    import torch
+    import paper_2104_10523_amd as tn
+    from workloads import grid_random_circuit
+    stream = torch.cuda.current_stream()
+    n, ops = grid_random_circuit(7, 7, 10, 2, two_qubit="fsim")
+    codes = [0] * n
+    codes[24] = codes[25] = 3
+    net, kept = tn.tn_build_expectation_network(n, ops, codes)
+    t0 = time.time()
+    path = tn.tn_find_path(net, "random_greedy", trials=1024, seed=1, mem_budget_bytes=160 * 2 ** 30)
+    t_path = time.time() - t0
+    ns = int(path.cost.n_slices)
+    need = max(tn.tn_amplitudes_workspace(net, path, 1, p) for p in ("fp32", a.precision))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    tn.tn_set_workspace(ws)
+    zeros = np.zeros((1, n), np.int8)
+    print(f"# expval: kept {kept} of {len(ops)} gates, 2^{path.cost.n_sliced} slices, total flops "
+          f"2^{math.log2(path.cost.total_flops):.2f}, path {t_path:.1f}s", file=sys.stderr, flush=True)
+    time_steps(net, path, zeros, a.precision, [(0, 0)], stream)          # warm-up: one slice
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_job, op_sec, (info, kind, fl, by, shape), parts = time_steps(net, path, zeros, a.precision,
+                                                                      [(0, s) for s in range(ns)], stream)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    value = complex(parts.sum())
+    _, _, _, parts32 = time_steps(net, path, zeros, "fp32", [(0, s) for s in range(ns)], stream)
+    v32 = complex(parts32.sum())
+    names = {}
+    for k in np.nonzero(kind == 2)[0]:
+        names.setdefault(kernel_name(a.precision, int(shape[k, 4]), int(shape[k, 5])), []).append(k)
+    dom = max(names, key=lambda nm: op_sec[names[nm]].sum())
+    sel = np.array(names[dom])
+    g_flops = float(fl[sel].sum()) * ns
+    g_time = float(op_sec[sel].sum())
+    n_launch = int(shape[sel, 6].sum()) * ns
+    peak = PEAKS[a.precision] if a.precision in PEAKS else PEAKS["bf16x3"]
+    flops_total = float(fl.sum()) * ns
+    # wave-function slicing on a 5x5 grid
+    n5, ops5 = grid_random_circuit(5, 5, 10, 3, two_qubit="fsim")
+    c5 = [0] * n5
+    c5[12] = c5[13] = 3
+    proj = list(range(5))
+    bits = np.full((32, n5), -1, np.int8)
+    for sidx, vals in enumerate(itertools.product((0, 1), repeat=5)):
+        bits[sidx, proj] = vals
+    net5 = tn.tn_build_network(n5, ops5)
+    path5 = tn.tn_find_path(net5, "random_greedy", trials=64, seed=1, open_mask=(bits[0] < 0).astype(np.int8))
+    tn.tn_set_workspace(None)
+    del ws
+    torch.cuda.empty_cache()
+    ws5 = torch.empty(tn.tn_amplitudes_workspace(net5, path5, 32, a.precision), dtype=torch.uint8, device="cuda")
+    tn.tn_set_workspace(ws5)
+
+    def sliced():
+        psi, _ = tn.tn_amplitudes(net5, path5, bits, precision=a.precision)
+        return tn.tn_pauli_expectation(psi, bits, c5)
+    v5 = sliced()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v5 = sliced()
+    t5 = time.perf_counter() - t0
+    netc5, kept5 = tn.tn_build_expectation_network(n5, ops5, c5)
+    pc5 = tn.tn_find_path(netc5, "random_greedy", trials=64, seed=1)
+    tn.tn_set_workspace(torch.empty(tn.tn_amplitudes_workspace(netc5, pc5, 1, "fp32"), dtype=torch.uint8,
+                                    device="cuda"))
+    vc5 = complex(tn.tn_amplitudes(netc5, pc5, np.zeros((1, n5), np.int8), precision="fp32")[0].cpu().numpy()[0, 0])
+    cpu = None
+    if not a.no_cpu:
+        leaves = []
+        outs = set(net.output_labels())
+        for i in range(net.info().n_tensors):
+            _, ls = net.tensor(i)
+            leaves.append([l for l in ls if l not in outs])
+        rate, secs, f = cpu_baseline(path.pairs, (leaves, [2] * net.info().n_labels, set(), path.sliced),
+                                     a.cpu_seconds)
+        cpu = {"value": rate / flops_total, "unit": "expectation values/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle complex128 einsum on the double-depth network's largest pairwise contractions "
+                         f"with <= 2^25-entry tensors ({f:.3g} flops in {secs:.1f}s, {rate / 1e9:.2f} GFLOP/s), "
+                         f"extrapolated to {flops_total:.3g} flops"}
+    return {"metric": "Pauli expectation values/s, <Z24 Z25> on a 49-qubit depth-10 grid (conjugate network)",
+            "value": 1.0 / T, "unit": "expectation values/s", "dtype": f"{a.precision} c64, fp64 slice sum",
+            "config": {"workload": "7x7 grid, 10 cycles, fSim(pi/2,pi/6), seed 2; double-depth network after "
+                                   "light-cone collapse; randomised-greedy path (1024 trials), 160 GiB budget",
+                       "kept_gates": kept, "gates": len(ops), "slices": ns, "seconds": T,
+                       "flops": flops_total, "complex_tflops": flops_total / T / 1e12,
+                       "value": [value.real, value.imag], "fp32_value": [v32.real, v32.imag],
+                       "abs_diff_vs_fp32": abs(value - v32),
+                       "sliced_method": {"workload": "5x5 grid, 10 cycles, fSim, seed 3, <Z12 Z13>, 20 open qubits, "
+                                                     "32 slices", "seconds": t5, "value": [v5.real, v5.imag],
+                                         "conjugate_fp32_value": [vc5.real, vc5.imag],
+                                         "abs_diff": abs(v5 - vc5)}},
+            "roofline": {"bound": "mfma", "achieved": g_flops / g_time / 1e12, "peak": peak / 1e12,
+                         "unit": "TFLOP/s", "frac": g_flops / g_time / peak, "traffic": None, "kernel": dom,
+                         "launches": n_launch, "avg_launch_ms": 1e3 * g_time / max(1, n_launch)},
+            "cpu_baseline": cpu}
+
+
+ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "learned": bench_learned,
+        "expval": bench_expval}
 
 
 def main():
