@@ -13,6 +13,9 @@ from its own statement:
   C backwards from P's support, a gate whose qubits are all outside the
   support grown so far commutes past everything later and meets its
   conjugate, so only the gates in P's backward light cone are applied.
+* density matrix (Sec. 3.3, Eq. 3): for a circuit with noise channels,
+  Tr(rho P) with rho from the O3 density-matrix simulator; for a noiseless
+  circuit it equals <Psi|P|Psi>.
 * wave-function slicing: fix the projected qubits to every assignment s,
   take the open slice psi_s of the state, and sum <psi_s|P_open|psi_s>; a Z
   factor on a projected qubit gives slice s the sign (-1)^{s_q}; X and Y
@@ -26,7 +29,8 @@ Pins (tests): GHZ closed forms (<Z_i Z_j> = 1, <Z_i> = 0, <X...X> = 1,
 gives <X> = 1, S H gives <Y> = 1); the conjugate-network value with and
 without the light-cone collapse and the sliced value all equal the direct
 definition on random circuits; <I...I> = 1; values of Hermitian strings are
-real and lie in [-1, 1].
+real and lie in [-1, 1]; Tr(rho P) of a noiseless circuit equals the
+pure-state value, and a depolarising H-H chain follows its closed form.
 """
 
 from __future__ import annotations
@@ -37,6 +41,7 @@ from typing import List, Sequence
 import numpy as np
 
 from .gates import PAULIS, gate_matrix
+from .noise import dm_simulate
 from .statevector import apply_gate, simulate
 
 CODES = {"I": 0, "X": 1, "Y": 2, "Z": 3}
@@ -119,3 +124,12 @@ def sliced_expectation(n: int, ops, pauli, open_qubits: Sequence[int]) -> comple
             continue
         total += sign * np.vdot(s.reshape(-1), apply_pauli(s, open_codes).reshape(-1))
     return complex(total)
+
+
+def dm_expectation(n: int, ops, pauli) -> complex:
+    """Tr(rho P) of the O3 density matrix (ket axes 0..n-1, bra n..2n-1)."""
+    codes = pauli_codes(n, pauli)
+    rho = dm_simulate(n, ops)
+    d = 1 << n
+    prho = apply_pauli(rho, codes + [0] * n)      # P acting on the ket index: (P rho)
+    return complex(np.trace(prho.reshape(d, d)))
