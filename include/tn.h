@@ -389,6 +389,22 @@ enum { TN_PAULI_I = 0, TN_PAULI_X = 1, TN_PAULI_Y = 2, TN_PAULI_Z = 3 };
 tn_status tn_build_expectation_network(const tn_circuit* c, const int8_t* pauli,
                                        tn_network** out, int64_t* kept_ops);
 
+/* Density-matrix network of Tr(rho P) (Sec. 3.3, Eq. 3): rho is the state
+ * of the circuit c, which may hold channels (TN_CHAN_*), started in
+ * |0..0><0..0|.  Every qubit carries a ket and a bra label; every op in P's
+ * backward light cone becomes its superoperator sum_j A_j (x) conj(A_j) (a
+ * unitary U: U (x) conj(U)) on the (ket, bra) legs, one-qubit ops folded
+ * into the next two-qubit tensor of their qubit; ops outside the cone are
+ * trace-preserving and drop out.  Each live qubit starts as a rank-2
+ * |0><0| tensor and is closed by the rank-2 tensor P_q^T on its (ket, bra)
+ * legs.  The network has no open legs (n_qubits 0): find a path and call
+ * tn_amplitudes with one empty bit-string (n_bs = 1, zero entries); the one
+ * output entry is Tr(rho P).  `kept_ops` (may be NULL) receives the number
+ * of ops of c that remain.  Host only.  Errors: TN_ERR_ARG (null, sizes,
+ * Pauli entries), TN_ERR_GATE (unknown id, bad qubit, bad channel rate). */
+tn_status tn_build_density_network(const tn_circuit* c, const int8_t* pauli,
+                                   tn_network** out, int64_t* kept_ops);
+
 /* <P> by wave-function slicing: `psi` is the device output of tn_amplitudes
  * for the n_slices bit-strings `bits` (host, n_slices x n_qubits, 0 / 1 for
  * projected qubits, -1 for the open qubits, the same open set in every row),

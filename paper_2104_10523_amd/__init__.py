@@ -18,7 +18,8 @@ from ._native import (GATE_IDS, PATH_ALGO, PAULI, PREC, TnCircuit, TnExecOpts, T
 
 __all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
            "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
-           "tn_amplitudes_workspace", "tn_build_expectation_network", "tn_pauli_expectation",
+           "tn_amplitudes_workspace", "tn_build_expectation_network", "tn_build_density_network",
+           "tn_pauli_expectation",
            "tn_mps_create", "tn_mps_apply_gate", "tn_run_trajectories", "PREC", "lib"]
 
 
@@ -251,6 +252,20 @@ def tn_build_expectation_network(n_qubits: int, ops, pauli):
     check(lib().tn_build_expectation_network(C.byref(ca.circ), p.ctypes.data_as(C.POINTER(C.c_int8)),
                                              C.byref(h), C.byref(kept)))
     return Network(h.value, n_qubits), int(kept.value)
+
+
+def tn_build_density_network(n_qubits: int, ops, pauli):
+    """Density-matrix network of Tr(rho P) for a circuit that may hold
+    channels; a closed network (no output legs).
+
+    Returns (network, number of ops of the circuit that were kept)."""
+    ca = _CircuitArgs(n_qubits, ops)
+    p = _pauli_array(n_qubits, pauli)
+    h = C.c_void_p()
+    kept = C.c_int64()
+    check(lib().tn_build_density_network(C.byref(ca.circ), p.ctypes.data_as(C.POINTER(C.c_int8)),
+                                         C.byref(h), C.byref(kept)))
+    return Network(h.value, 0), int(kept.value)
 
 
 def tn_pauli_expectation(psi, bits, pauli, stream=None) -> complex:

@@ -101,6 +101,7 @@ SIGNATURES = {
     "tn_amplitudes_autotune": (I32, [P, P, I32, I32, P]),
     "tn_amplitudes_plan_ops": (I32, [P, P, I32, PI32, PD, PD, C.POINTER(C.c_int64)]),  # shape: 8 per op
     "tn_build_expectation_network": (I32, [C.POINTER(TnCircuit), PI8, PP, C.POINTER(C.c_int64)]),
+    "tn_build_density_network": (I32, [C.POINTER(TnCircuit), PI8, PP, C.POINTER(C.c_int64)]),
     "tn_pauli_expectation": (I32, [P, PI8, I64, I32, PI8, PD, P]),
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),

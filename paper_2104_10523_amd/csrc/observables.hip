@@ -10,6 +10,10 @@
 // circuit, so its network, path search, slicing and amplitude kernels are
 // the ones of a single amplitude (all-zero bit-string).
 //
+// Density-matrix network (Sec. 3.3, Eq. 3): Tr(rho P) for a noisy circuit,
+// every op as its superoperator on (ket, bra) legs, closed by P; a closed
+// network with no output legs, contracted on the same engine.
+//
 // Wave-function slicing: the amplitudes of every projection of the closed
 // qubits (tn_amplitudes with the open set left open) are reduced on the
 // device as sum_s sum_x conj(psi_s[x]) (P psi_s)[x] in FP64.  X and Y
@@ -83,8 +87,10 @@ __global__ void pauli_final_kernel(const double2* __restrict__ part, int n, doub
 
 }  // namespace
 
-// Ops of C in P's backward light cone, in circuit order.
-std::vector<tn_op> light_cone_ops(const tn_circuit& c, const int8_t* pauli) {
+// Ops of C in P's backward light cone, in circuit order.  Channels are
+// accepted when `channels` is set (trace-preserving maps outside the cone
+// drop out of a trace as unitaries do).
+std::vector<tn_op> light_cone_ops(const tn_circuit& c, const int8_t* pauli, bool channels = false) {
   std::vector<char> live(c.n_qubits, 0);
   for (int q = 0; q < c.n_qubits; ++q) {
     TN_REQUIRE(pauli[q] >= TN_PAULI_I && pauli[q] <= TN_PAULI_Z, TN_ERR_ARG, "Pauli entries must be 0..3");
@@ -93,7 +99,8 @@ std::vector<tn_op> light_cone_ops(const tn_circuit& c, const int8_t* pauli) {
   std::vector<char> keep(c.n_ops, 0);
   for (int64_t k = c.n_ops - 1; k >= 0; --k) {
     const tn_op& op = c.ops[k];
-    TN_REQUIRE(!gate_is_channel(op.gate), TN_ERR_GATE, "expectation networks take unitary gates only");
+    TN_REQUIRE(channels || !gate_is_channel(op.gate), TN_ERR_GATE,
+               "conjugate-network expectation values take unitary gates only");
     const int ar = gate_arity(op.gate);
     TN_REQUIRE(op.q0 >= 0 && op.q0 < c.n_qubits && (ar == 1 || (op.q1 >= 0 && op.q1 < c.n_qubits && op.q1 != op.q0)),
                TN_ERR_GATE, "bad qubit index");
@@ -107,6 +114,121 @@ std::vector<tn_op> light_cone_ops(const tn_circuit& c, const int8_t* pauli) {
   for (int64_t k = 0; k < c.n_ops; ++k)
     if (keep[k]) out.push_back(c.ops[k]);
   return out;
+}
+
+// Superoperator of a one- or two-qubit op on interleaved (ket, bra) indices:
+// one qubit: S[(k, b)][(k', b')] = sum_j A_j[k][k'] conj(A_j[b][b']);
+// two qubits (a, c): row and column index (k_a, b_a, k_c, b_c).
+Mat superop(const tn_op& op) {
+  std::vector<Mat> ks;
+  if (gate_is_channel(op.gate)) ks = channel_kraus(op);
+  else ks.push_back(gate_unitary(op));
+  const int d = ks[0].dim;            // 2 or 4
+  Mat S(d * d);
+  for (const Mat& A : ks)
+    for (int ko = 0; ko < d; ++ko)
+      for (int bo = 0; bo < d; ++bo)
+        for (int ki = 0; ki < d; ++ki)
+          for (int bi = 0; bi < d; ++bi) {
+            const cd v = A(ko, ki) * std::conj(A(bo, bi));
+            int r, c;
+            if (d == 2) {
+              r = ko * 2 + bo;
+              c = ki * 2 + bi;
+            } else {   // (k_a k_c), (b_a b_c) -> (k_a b_a k_c b_c)
+              r = ((ko >> 1) << 3) | ((bo >> 1) << 2) | ((ko & 1) << 1) | (bo & 1);
+              c = ((ki >> 1) << 3) | ((bi >> 1) << 2) | ((ki & 1) << 1) | (bi & 1);
+            }
+            S(r, c) += v;
+          }
+  return S;
+}
+
+// Density-matrix network of Tr(rho P), rho = Phi_m ... Phi_1(|0><0|)
+// (Sec. 3.3, Eq. 3): each qubit carries a ket and a bra label; every op of
+// P's backward light cone becomes its superoperator, one-qubit ops folded
+// into the next two-qubit tensor of their qubit (rank 8 over (k, b) of both
+// qubits, outputs first); each live qubit starts as a rank-2 |0><0| tensor
+// and is closed by a rank-2 tensor C[k][b] = P_q[b][k] (with any pending
+// one-qubit ops folded in).  No open legs: n_qubits of the network is 0.
+Network build_density_network(const tn_circuit& c, const int8_t* pauli, int64_t* kept_ops) {
+  const std::vector<tn_op> cone = light_cone_ops(c, pauli, true);
+  const int n = c.n_qubits;
+  std::vector<char> live(n, 0);
+  for (int q = 0; q < n; ++q) live[q] = pauli[q] != TN_PAULI_I;
+  for (const tn_op& op : cone) {
+    live[op.q0] = 1;
+    if (gate_arity(op.gate) == 2) live[op.q1] = 1;
+  }
+  Network net;
+  net.n_qubits = 0;
+  std::vector<Mat> pend(n, Mat::identity(4));
+  std::vector<int> wk(n, -1), wb(n, -1);
+  int nxt = 0;
+  bool any = false;
+  for (int q = 0; q < n; ++q) {
+    if (!live[q]) continue;
+    any = true;
+    NetTensor t;                       // |0><0| on (k, b)
+    t.labels = {nxt, nxt + 1};
+    t.data = {cd(1, 0), cd(0, 0), cd(0, 0), cd(0, 0)};
+    wk[q] = nxt;
+    wb[q] = nxt + 1;
+    nxt += 2;
+    net.tensors.push_back(std::move(t));
+  }
+  for (const tn_op& op : cone) {
+    const Mat S = superop(op);
+    if (gate_arity(op.gate) == 1) {
+      pend[op.q0] = matmul(S, pend[op.q0]);
+      continue;
+    }
+    const int a = op.q0, b = op.q1;
+    const Mat T = matmul(S, kron(pend[a], pend[b]));
+    pend[a] = Mat::identity(4);
+    pend[b] = Mat::identity(4);
+    NetTensor t;
+    t.labels = {nxt, nxt + 1, nxt + 2, nxt + 3, wk[a], wb[a], wk[b], wb[b]};
+    t.data.assign(256, cd(0, 0));
+    for (int r = 0; r < 16; ++r)
+      for (int col = 0; col < 16; ++col) t.data[size_t(r) * 16 + col] = T(r, col);
+    wk[a] = nxt;
+    wb[a] = nxt + 1;
+    wk[b] = nxt + 2;
+    wb[b] = nxt + 3;
+    nxt += 4;
+    net.tensors.push_back(std::move(t));
+  }
+  static const cd PM[4][4] = {{1, 0, 0, 1}, {0, 1, 1, 0}, {0, cd(0, -1), cd(0, 1), 0}, {1, 0, 0, -1}};
+  for (int q = 0; q < n; ++q) {
+    if (!live[q]) continue;
+    // closing row vector over (k, b): P[b][k], then the pending ops
+    const cd* P = PM[int(pauli[q])];
+    NetTensor t;
+    t.labels = {wk[q], wb[q]};
+    t.data.assign(4, cd(0, 0));
+    for (int i = 0; i < 4; ++i) {
+      cd acc(0, 0);
+      for (int o = 0; o < 4; ++o) {
+        const int ko = o >> 1, bo = o & 1;
+        acc += P[bo * 2 + ko] * pend[q](o, i);
+      }
+      t.data[i] = acc;
+    }
+    net.tensors.push_back(std::move(t));
+  }
+  if (!any) {                          // Tr(rho) of nothing: one traced |0><0|
+    NetTensor t0, t1;
+    t0.labels = t1.labels = {0, 1};
+    t0.data = {cd(1, 0), cd(0, 0), cd(0, 0), cd(0, 0)};
+    t1.data = {cd(1, 0), cd(0, 0), cd(0, 0), cd(1, 0)};
+    net.tensors.push_back(std::move(t0));
+    net.tensors.push_back(std::move(t1));
+    nxt = 2;
+  }
+  net.n_labels = nxt;
+  if (kept_ops) *kept_ops = int64_t(cone.size());
+  return net;
 }
 
 }  // namespace tn
@@ -160,6 +282,18 @@ tn_status tn_build_expectation_network(const tn_circuit* c, const int8_t* pauli,
     auto n = std::make_unique<tn_network>();
     n->net = build_network(dd);
     if (kept_ops) *kept_ops = int64_t(cone.size());
+    *out = n.release();
+  });
+}
+
+tn_status tn_build_density_network(const tn_circuit* c, const int8_t* pauli, tn_network** out,
+                                   int64_t* kept_ops) {
+  return guarded([&] {
+    TN_REQUIRE(c && pauli && out, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(c->n_qubits >= 1 && c->n_qubits <= 4096, TN_ERR_ARG, "n_qubits must be 1..4096");
+    TN_REQUIRE(c->n_ops >= 0 && (c->n_ops == 0 || c->ops), TN_ERR_ARG, "bad op array");
+    auto n = std::make_unique<tn_network>();
+    n->net = build_density_network(*c, pauli, kept_ops);
     *out = n.release();
   });
 }

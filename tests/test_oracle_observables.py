@@ -126,3 +126,49 @@ def test_library_double_depth_identity_and_errors():
         tn.tn_build_expectation_network(n, ops, [0, 4, 0, 0])
     with pytest.raises(tn.TnError, match="TN_ERR_GATE"):
         tn.tn_build_expectation_network(n, ops + [Op("depol1", (0,), (0.1,))], "ZIII")
+
+
+# ---- density matrix (Sec. 3.3, Eq. 3) -------------------------------------
+
+from workloads import hh_circuit, noisy_ops
+
+
+def test_dm_expectation_noiseless_equals_pure():
+    r = np.random.default_rng(5)
+    n, ops = grid_random_circuit(2, 3, 4, 61)
+    for w in (1, 2, 3):
+        codes = random_pauli(n, w, r)
+        assert abs(ob.dm_expectation(n, ops, codes) - ob.expectation(n, ops, codes)) < 1e-12
+
+
+def test_dm_expectation_depolarised_hh_closed_form():
+    p, cyc = 0.03, 6
+    _, ops = hh_circuit(cyc)
+    ops = noisy_ops(ops, p, 0.0, 0.0)
+    got = ob.dm_expectation(4, ops, "ZIII")
+    assert abs(got - (1 - 4 * p / 3) ** (2 * cyc)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_library_density_network(seed):
+    """The library's density-matrix network (host side), contracted by the
+    oracle, equals Tr(rho P) of the density-matrix oracle."""
+    import paper_2104_10523_amd as tn
+    r = np.random.default_rng(90 + seed)
+    n, ops = grid_random_circuit(2, 3, 3 + seed, 900 + seed)
+    ops = noisy_ops(ops, 0.02, 0.05, 0.07)
+    codes = random_pauli(n, 1 + seed, r)
+    net, kept = tn.tn_build_density_network(n, ops, codes)
+    assert net.info().n_qubits == 0 and kept <= len(ops)
+    assert abs(contract_closed(net, 0) - ob.dm_expectation(n, ops, codes)) < 1e-12
+
+
+def test_library_density_network_trace_and_light_cone():
+    import paper_2104_10523_amd as tn
+    n, ops = chain_random_circuit(6, 2, 8)
+    ops = noisy_ops(ops, 0.01, 0.02, 0.03)
+    net, kept = tn.tn_build_density_network(n, ops, [0] * n)
+    assert kept == 0 and abs(contract_closed(net, 0) - 1) < 1e-12
+    net, kept = tn.tn_build_density_network(n, ops, [3, 0, 0, 0, 0, 0])
+    assert 0 < kept < len(ops)
+    assert abs(contract_closed(net, 0) - ob.dm_expectation(n, ops, "ZIIIII")) < 1e-12
