@@ -33,6 +33,25 @@ Slicing
     and C at the first step attaining the peak, slice the one giving the
     smallest (peak, total flops over all slices, label).
 
+Recursive bisection (Sec. 3.1 names graph partitioning "plus heuristics";
+this is one reading of that, not the paper's partitioner)
+    leaf graph: one edge per label held by exactly two leaves (open labels
+    excluded); adjacency lists filled in ascending label order.  A trial
+    draws eps = 0.05 + 0.85 u, then cutoff = (2, 4, 8, 16, 32)[x mod 5] from
+    its stream.  A node set of one leaf is that leaf; a set of at most
+    `cutoff` leaves is ordered by greedy with the labels it shares with the
+    rest of the network kept open; a larger set is bisected and its halves'
+    trees are contracted last.  Bisection: part 0 starts at the leaf
+    nodes[x mod n] and grows, one leaf at a time up to floor(n/2), by the
+    outside leaf with most adjacency entries into part 0 (ties: smallest id;
+    none adjacent: smallest outside id).  Then Fiduccia-Mattheyses passes
+    (at most 6): repeatedly move the unlocked leaf of largest cut gain (ties:
+    smallest id) whose move keeps both parts within [lo, n - lo], lo =
+    max(1, floor((1 - eps) n / 2)); keep the shortest prefix of moves with
+    the lowest cut; stop when a pass does not lower the cut.  The plain greedy
+    path and every trial are sliced to the budget, and the lowest (total
+    flops, peak, index) wins.
+
 Parity pins (tests): hand-computed costs of small paths; greedy never worse
 than... (none; greedy is a heuristic) -- instead an exhaustive search over
 all pairwise orders on <= 7 tensors bounds it from below; sliced peak <=
@@ -244,3 +263,153 @@ def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:
         sliced.append(best[1])
         cur = best[2]
     return sliced
+
+
+# ---------------------------------------------------------------- bisection
+
+CUTOFFS = (2, 4, 8, 16, 32)
+
+
+def _leaf_graph(leaves, n_labels, open_set):
+    holders = [[] for _ in range(n_labels)]
+    for i, ls in enumerate(leaves):
+        for l in sorted(ls):
+            holders[l].append(i)
+    adj = [[] for _ in leaves]
+    for l in range(n_labels):
+        h = holders[l]
+        if len(h) == 2 and l not in open_set:
+            adj[h[0]].append(h[1])
+            adj[h[1]].append(h[0])
+    return adj, holders
+
+
+def _bisect(adj, nodes, eps, rng, side):
+    n = len(nodes)
+    aux = {}
+    for v in nodes:
+        side[v] = 1
+        aux[v] = 0
+
+    def add0(v):
+        side[v] = 0
+        for u in adj[v]:
+            if side[u] >= 0:
+                aux[u] += 1
+
+    add0(nodes[rng.next_u64() % n])
+    for _ in range(1, n // 2):
+        pick = None
+        for v in nodes:
+            if side[v] == 1 and aux[v] > 0 and (pick is None or aux[v] > aux[pick]):
+                pick = v
+        if pick is None:
+            pick = next(v for v in nodes if side[v] == 1)
+        add0(pick)
+    lo = max(1, int(math.floor((1.0 - eps) * n / 2.0)))
+    hi = n - lo
+    cut = sum(1 for v in nodes for u in adj[v] if side[u] >= 0 and side[u] != side[v]) // 2
+    for _ in range(6):
+        sizes = [0, 0]
+        locked = {}
+        for v in nodes:
+            sizes[side[v]] += 1
+            locked[v] = False
+            aux[v] = sum((1 if side[u] != side[v] else -1) for u in adj[v] if side[u] >= 0)
+        cur = best_c = cut
+        best_k = 0
+        moved = []
+        for k in range(n):
+            pick = None
+            for v in nodes:
+                if locked[v] or sizes[side[v]] - 1 < lo or sizes[1 - side[v]] + 1 > hi:
+                    continue
+                if pick is None or aux[v] > aux[pick]:
+                    pick = v
+            if pick is None:
+                break
+            s0 = side[pick]
+            side[pick] = 1 - s0
+            sizes[s0] -= 1
+            sizes[1 - s0] += 1
+            cur -= aux[pick]
+            aux[pick] = -aux[pick]
+            locked[pick] = True
+            moved.append(pick)
+            for u in adj[pick]:
+                if side[u] >= 0:
+                    aux[u] += 2 if side[u] == s0 else -2
+            if cur < best_c:
+                best_c, best_k = cur, k + 1
+        for v in reversed(moved[best_k:]):
+            side[v] = 1 - side[v]
+        if best_c >= cut:
+            break
+        cut = best_c
+    p0 = [v for v in nodes if side[v] == 0]
+    p1 = [v for v in nodes if side[v] == 1]
+    for v in nodes:
+        side[v] = -1
+    return p0, p1
+
+
+def partition_path(leaves, ext, open_set, rng: SplitMix64) -> List[Tuple[int, int]]:
+    """One recursive-bisection contraction tree (SSA pairs)."""
+    eps = 0.05 + 0.85 * rng.uniform()
+    cutoff = CUTOFFS[rng.next_u64() % 5]
+    n = len(leaves)
+    if n <= 1:
+        return []
+    open_set = set(open_set)
+    adj, holders = _leaf_graph(leaves, len(ext), open_set)
+    side = [-1] * n
+    pairs: List[Tuple[int, int]] = []
+    nxt = [n]
+
+    def build(nodes):
+        if len(nodes) == 1:
+            return nodes[0]
+        if len(nodes) <= cutoff:
+            inset = set(nodes)
+            keep = set(open_set)
+            for v in nodes:
+                for l in leaves[v]:
+                    if any(h not in inset for h in holders[l]):
+                        keep.add(l)
+            gp = greedy_path([leaves[v] for v in nodes], ext, keep)
+            ids = list(nodes)
+            for (i, j) in gp:
+                pairs.append((ids[i], ids[j]))
+                ids.append(nxt[0])
+                nxt[0] += 1
+            return ids[-1]
+        p0, p1 = _bisect(adj, nodes, eps, rng, side)
+        a = build(p0)
+        b = build(p1)
+        pairs.append((a, b))
+        nxt[0] += 1
+        return nxt[0] - 1
+
+    build(list(range(n)))
+    return pairs
+
+
+def partition_search(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
+                     budget_bytes: float = 0.0) -> List[Tuple[int, int]]:
+    """Best of the plain greedy path and `trials` bisection trees by sliced
+    (total flops, peak), earlier candidates winning ties."""
+    cands = [greedy_path(leaves, ext, open_set)]
+    for r in range(trials):
+        g = SplitMix64((seed + r * GOLDEN) & MASK64)
+        cands.append(partition_path(leaves, ext, open_set, SplitMix64(g.next_u64())))
+    best = None
+    for i, p in enumerate(cands):
+        try:
+            sl = slice_path(leaves, ext, p, open_set, budget_bytes) if budget_bytes > 0 else []
+        except ValueError:
+            continue
+        s = path_stats(leaves, ext, p, open_set, sl)
+        key = (s["total_flops"], s["peak"], i)
+        if best is None or key < best[0]:
+            best = (key, i)
+    return cands[0 if best is None else best[1]]
