@@ -132,7 +132,7 @@ tn_status tn_network_output_labels(const tn_network* n, int32_t* labels);
 typedef struct tn_path tn_path;
 typedef struct tn_model tn_model;
 
-enum { TN_PATH_GREEDY = 0, TN_PATH_RANDOM_GREEDY = 1, TN_PATH_LEARNED = 2 };
+enum { TN_PATH_GREEDY = 0, TN_PATH_RANDOM_GREEDY = 1, TN_PATH_LEARNED = 2, TN_PATH_PARTITION = 3 };
 
 typedef struct {
   int32_t algo;               /* TN_PATH_*                                  */
@@ -168,7 +168,18 @@ typedef struct {
  * (flops, peak); with a budget, the 16 best by (flops, peak) are sliced and
  * the lowest (total flops, peak) is kept.  Slicing adds, while 8*peak >
  * budget, the label of the peak step that minimises (peak, total flops,
- * label).  Host only.
+ * label).
+ * PARTITION (Sec. 3.1 names graph partitioning plus heuristics): trial r
+ * (stream seeded as above) draws an imbalance eps = 0.05 + 0.85 u and a
+ * cutoff from {2, 4, 8, 16, 32}, then bisects the leaf graph (edges = labels
+ * shared by two leaves) recursively: part 0 grows from a random seed leaf by
+ * most links into it (ties: smallest id) to half the set, and
+ * Fiduccia-Mattheyses passes move the unlocked leaf of largest cut gain
+ * (ties: smallest id) within part sizes [max(1, floor((1-eps)n/2)),
+ * n - that], keeping the best prefix, until a pass stops lowering the cut;
+ * sets of at most `cutoff` leaves are ordered by greedy, the two halves are
+ * contracted last.  The plain greedy path and the trials are each sliced to
+ * the budget and the lowest (total flops, peak, index) wins.  Host only.
  * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */
 tn_status tn_find_path(const tn_network* n, const tn_path_opts* o,
                        tn_path** out, tn_path_cost* cost);

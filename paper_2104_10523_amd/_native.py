@@ -22,7 +22,7 @@ GATE_IDS = {
 }
 
 PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3, "f16x3": 4}
-PATH_ALGO = {"greedy": 0, "random_greedy": 1, "learned": 2}
+PATH_ALGO = {"greedy": 0, "random_greedy": 1, "learned": 2, "partition": 3}
 PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 
 

@@ -226,7 +226,8 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
   return guarded([&] {
     TN_REQUIRE(n && out, TN_ERR_ARG, "null argument");
     const int algo = o ? o->algo : TN_PATH_GREEDY;
-    TN_REQUIRE(algo == TN_PATH_GREEDY || algo == TN_PATH_RANDOM_GREEDY || algo == TN_PATH_LEARNED,
+    TN_REQUIRE(algo == TN_PATH_GREEDY || algo == TN_PATH_RANDOM_GREEDY || algo == TN_PATH_LEARNED ||
+                   algo == TN_PATH_PARTITION,
                TN_ERR_ARG, "unknown path algorithm");
     const auto open_q = read_open(n->net, o ? o->open_mask : nullptr);
     const PathProblem pr = make_problem(n->net, open_q);
@@ -236,6 +237,9 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
     } else if (algo == TN_PATH_RANDOM_GREEDY) {
       TN_REQUIRE(o->trials >= 0 && o->temperature > 0, TN_ERR_ARG, "bad random-greedy options");
       pairs = random_greedy_path(pr, o->seed, o->trials, o->temperature, o->mem_budget_bytes);
+    } else if (algo == TN_PATH_PARTITION) {
+      TN_REQUIRE(o->trials >= 0, TN_ERR_ARG, "bad partition options");
+      pairs = partition_search(pr, o->seed, o->trials, o->mem_budget_bytes);
     } else {
       TN_REQUIRE(o->model != nullptr, TN_ERR_STATE, "learned path needs a model");
       int used = TN_PATH_GREEDY;

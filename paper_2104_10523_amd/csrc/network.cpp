@@ -376,6 +376,212 @@ std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint6
   return std::move(paths[order[win < 0 ? 0 : win]]);
 }
 
+// ------------------------------------------- recursive-bisection search
+
+namespace {
+
+// Leaf graph: one adjacency entry per label shared by exactly two leaves
+// (open labels excluded), both directions, in ascending label order.
+struct LeafGraph {
+  std::vector<std::vector<int>> adj;
+  std::vector<std::vector<int>> holders;   // per label
+};
+
+LeafGraph leaf_graph(const PathProblem& pr) {
+  LeafGraph g;
+  const int n = int(pr.leaves.size());
+  g.adj.assign(n, {});
+  g.holders.assign(pr.ext.size(), {});
+  for (int i = 0; i < n; ++i)
+    for (int l : pr.leaves[i]) g.holders[l].push_back(i);
+  for (size_t l = 0; l < g.holders.size(); ++l) {
+    const auto& h = g.holders[l];
+    if (h.size() == 2 && !pr.open[l]) {
+      g.adj[h[0]].push_back(h[1]);
+      g.adj[h[1]].push_back(h[0]);
+    }
+  }
+  return g;
+}
+
+struct Bisector {
+  const PathProblem& pr;
+  const LeafGraph& g;
+  double eps;
+  int cutoff;
+  uint64_t* rng;
+  std::vector<int> side;      // -1 outside the current node set
+  std::vector<int> aux;       // links into part 0 / gains
+  std::vector<char> locked;
+  std::vector<std::pair<int, int>> pairs;
+  int next_id;
+
+  Bisector(const PathProblem& p, const LeafGraph& gr, double e, int c, uint64_t* r)
+      : pr(p), g(gr), eps(e), cutoff(c), rng(r), side(p.leaves.size(), -1), aux(p.leaves.size(), 0),
+        locked(p.leaves.size(), 0), next_id(int(p.leaves.size())) {}
+
+  // Splits `nodes` (ascending) in two: part 0 grown from a random seed leaf
+  // by most links into it (ties: smallest id) to half the set, then
+  // Fiduccia-Mattheyses passes: move the unlocked leaf of largest cut gain
+  // (ties: smallest id) that keeps both parts within [lo, hi], keep the
+  // best prefix of moves, stop when a pass no longer lowers the cut.
+  void bisect(const std::vector<int>& nodes, std::vector<int>& p0, std::vector<int>& p1) {
+    const int n = int(nodes.size());
+    for (int v : nodes) {
+      side[v] = 1;
+      aux[v] = 0;
+    }
+    const int seed = nodes[splitmix64_next(rng) % uint64_t(n)];
+    auto add0 = [&](int v) {
+      side[v] = 0;
+      for (int u : g.adj[v])
+        if (side[u] >= 0) ++aux[u];
+    };
+    add0(seed);
+    for (int na = 1; na < n / 2; ++na) {
+      int pick = -1;
+      for (int v : nodes)
+        if (side[v] == 1 && aux[v] > 0 && (pick < 0 || aux[v] > aux[pick])) pick = v;
+      if (pick < 0)
+        for (int v : nodes)
+          if (side[v] == 1) { pick = v; break; }
+      add0(pick);
+    }
+    const int lo = std::max(1, int(std::floor((1.0 - eps) * n / 2.0))), hi = n - lo;
+    auto cut_of = [&]() {
+      int c = 0;
+      for (int v : nodes)
+        for (int u : g.adj[v])
+          if (side[u] >= 0 && side[u] != side[v]) ++c;
+      return c / 2;
+    };
+    int cut = cut_of();
+    for (int pass = 0; pass < 6; ++pass) {
+      int sizes[2] = {0, 0};
+      for (int v : nodes) {
+        ++sizes[side[v]];
+        locked[v] = 0;
+        int gn = 0;
+        for (int u : g.adj[v])
+          if (side[u] >= 0) gn += side[u] != side[v] ? 1 : -1;
+        aux[v] = gn;
+      }
+      int cur = cut, best_c = cut, best_k = 0;
+      std::vector<int> moved;
+      for (int k = 0; k < n; ++k) {
+        int pick = -1;
+        for (int v : nodes) {
+          if (locked[v] || sizes[side[v]] - 1 < lo || sizes[1 - side[v]] + 1 > hi) continue;
+          if (pick < 0 || aux[v] > aux[pick]) pick = v;
+        }
+        if (pick < 0) break;
+        const int s0 = side[pick];
+        side[pick] = 1 - s0;
+        --sizes[s0];
+        ++sizes[1 - s0];
+        cur -= aux[pick];
+        aux[pick] = -aux[pick];
+        locked[pick] = 1;
+        moved.push_back(pick);
+        for (int u : g.adj[pick])
+          if (side[u] >= 0) aux[u] += side[u] == s0 ? 2 : -2;
+        if (cur < best_c) {
+          best_c = cur;
+          best_k = k + 1;
+        }
+      }
+      for (int k = int(moved.size()) - 1; k >= best_k; --k) side[moved[k]] = 1 - side[moved[k]];
+      if (best_c >= cut) break;
+      cut = best_c;
+    }
+    p0.clear();
+    p1.clear();
+    for (int v : nodes) (side[v] == 0 ? p0 : p1).push_back(v);
+    for (int v : nodes) side[v] = -1;
+  }
+
+  // Contraction tree of `nodes`: the two halves' results contracted last;
+  // sets of at most `cutoff` leaves ordered by greedy, keeping the labels
+  // they share with the rest of the network.  Returns the result's SSA id.
+  int build(const std::vector<int>& nodes) {
+    if (nodes.size() == 1) return nodes[0];
+    if (int(nodes.size()) <= cutoff) {
+      PathProblem sub;
+      sub.ext = pr.ext;
+      sub.open = pr.open;
+      for (int v : nodes) side[v] = 0;
+      for (int v : nodes)
+        for (int l : pr.leaves[v])
+          for (int h : g.holders[l])
+            if (side[h] < 0) sub.open[l] = 1;
+      for (int v : nodes) side[v] = -1;
+      for (int v : nodes) sub.leaves.push_back(pr.leaves[v]);
+      const auto gp = greedy_path(sub, nullptr, 1.0);
+      std::vector<int> ids(nodes);
+      for (const auto& st : gp) {
+        pairs.push_back({ids[st.first], ids[st.second]});
+        ids.push_back(next_id++);
+      }
+      return ids.back();
+    }
+    std::vector<int> p0, p1;
+    bisect(nodes, p0, p1);
+    const int a = build(p0);
+    const int b = build(p1);
+    pairs.push_back({a, b});
+    return next_id++;
+  }
+};
+
+}  // namespace
+
+std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t* rng) {
+  static const int kCutoffs[5] = {2, 4, 8, 16, 32};
+  const double eps = 0.05 + 0.85 * splitmix64_uniform(rng);
+  const int cutoff = kCutoffs[splitmix64_next(rng) % 5];
+  const int n = int(pr.leaves.size());
+  if (n <= 1) return {};
+  const LeafGraph g = leaf_graph(pr);
+  Bisector b(pr, g, eps, cutoff, rng);
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  b.build(all);
+  return std::move(b.pairs);
+}
+
+std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
+                                                  double budget_bytes) {
+  // Candidates: the plain greedy path (index 0) and `trials` bisection trees
+  // (trial r seeded like the randomised greedy).  Each is sliced to the
+  // budget (if any) and the lowest (total flops, peak, index) wins.
+  trials = std::max(trials, 0);
+  std::vector<std::vector<std::pair<int, int>>> paths(trials + 1);
+  std::vector<double> tf(trials + 1, 0.0), tp(trials + 1, 0.0);
+  std::vector<char> ok(trials + 1, 0);
+  auto score = [&](int i) {
+    try {
+      const PathStats s = path_stats(pr, paths[i], slice_path(pr, paths[i], budget_bytes));
+      tf[i] = s.total_flops;
+      tp[i] = s.peak;
+      ok[i] = 1;
+    } catch (const Error& e) {
+      if (e.code != TN_ERR_BUDGET) throw;
+    }
+  };
+  paths[0] = greedy_path(pr, nullptr, 1.0);
+  score(0);
+  parallel_for(trials, [&](int r) {
+    uint64_t gs = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
+    uint64_t st = splitmix64_next(&gs);
+    paths[r + 1] = partition_path(pr, &st);
+    score(r + 1);
+  });
+  int win = -1;
+  for (int i = 0; i <= trials; ++i)
+    if (ok[i] && (win < 0 || tf[i] < tf[win] || (tf[i] == tf[win] && tp[i] < tp[win]))) win = i;
+  return std::move(paths[win < 0 ? 0 : win]);
+}
+
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
                             double budget_bytes) {
   std::vector<int> sliced;

@@ -77,6 +77,12 @@ std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint6
                                                     double budget_bytes = 0.0);
 PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
                      const std::vector<int>& sliced);
+// One recursive-bisection contraction tree (parameters and seed leaves drawn
+// from the SplitMix64 stream `rng`), and the best of greedy + `trials` such
+// trees by sliced (total flops, peak).
+std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t* rng);
+std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
+                                                  double budget_bytes);
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
                             double budget_bytes);
 uint64_t splitmix64_next(uint64_t* state);

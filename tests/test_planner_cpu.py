@@ -14,7 +14,8 @@ import pytest
 
 import paper_2104_10523_amd as tn
 from oracle.network import build_network
-from oracle.paths import greedy_path, path_stats, random_greedy_path, slice_path
+from oracle.paths import (SplitMix64, greedy_path, partition_path, partition_search, path_stats,
+                          random_greedy_path, slice_path)
 from workloads import Op, grid_random_circuit, chain_random_circuit, cat_circuit, qft_circuit
 
 HEADER = Path(__file__).resolve().parent.parent / "include" / "tn.h"
@@ -227,3 +228,67 @@ def test_identity_coupled_7x7_has_benchmark_path():
     p = tn.tn_find_path(tn.tn_build_network(n, ops), "random_greedy", **opts)
     p0 = tn.tn_find_path(tn.tn_build_network(n, ops0), "random_greedy", **opts)
     assert p.pairs == p0.pairs and p.sliced == p0.sliced and p.cost.n_sliced == 7
+
+
+
+# ---- recursive-bisection path search -------------------------------------
+
+@pytest.mark.parametrize("name,make", CIRCUITS, ids=[c[0] for c in CIRCUITS])
+def test_partition_search_matches_oracle(name, make):
+    """Library and oracle build the same bisection trees and pick the same
+    winner (trials on host threads), with open legs and without."""
+    n, ops = make()
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    for open_q in ((), (0, n - 1)):
+        mask = [1 if q in open_q else 0 for q in range(n)]
+        leaves, ext, opened = _oracle_leaves(onet, open_q)
+        p = tn.tn_find_path(lnet, "partition", trials=12, seed=3, open_mask=mask)
+        po = partition_search(leaves, ext, opened, seed=3, trials=12)
+        assert p.pairs == po
+
+
+def test_partition_trials_match_one_by_one():
+    """Every single trial of the library equals the oracle's tree: with one
+    trial the winner is that tree unless greedy is cheaper."""
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    onet = build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    for r in range(6):
+        from oracle.paths import GOLDEN, MASK64
+        g = SplitMix64((11 + r * GOLDEN) & MASK64)
+        tree = partition_path(leaves, ext, opened, SplitMix64(g.next_u64()))
+        st = path_stats(leaves, ext, tree, opened)       # a valid path over all leaves
+        assert len(tree) == len(leaves) - 1
+        lib = tn.tn_path_from_pairs(tn.tn_build_network(n, ops), tree)
+        assert lib.cost.flops_per_slice == st["flops"]
+
+
+def test_partition_with_budget_matches_oracle():
+    n, ops = grid_random_circuit(4, 5, 12, 7)
+    onet = build_network(n, ops)
+    lnet = tn.tn_build_network(n, ops)
+    leaves, ext, opened = _oracle_leaves(onet)
+    unsliced = path_stats(leaves, ext, partition_search(leaves, ext, opened, seed=2, trials=8), opened)
+    budget = 8.0 * unsliced["peak"] / 16
+    p = tn.tn_find_path(lnet, "partition", trials=8, seed=2, mem_budget_bytes=budget)
+    po = partition_search(leaves, ext, opened, seed=2, trials=8, budget_bytes=budget)
+    assert p.pairs == po
+    assert p.sliced == slice_path(leaves, ext, po, opened, budget)
+    assert 8.0 * p.cost.peak_elems <= budget
+
+
+def test_partition_tree_contracts_to_the_amplitude():
+    """The oracle's own bisection tree, contracted by the oracle, gives the
+    state-vector amplitude (the tree is a valid complete contraction)."""
+    from oracle import statevector as sv
+    from oracle.contract import contract_path
+    from oracle.network import fix_outputs
+    n, ops = grid_random_circuit(3, 3, 6, 5)
+    onet = build_network(n, ops)
+    bits = [1, 0, 1, 1, 0, 0, 1, 0, 1]
+    tensors, labels, open_l = fix_outputs(onet, bits)
+    for r in range(3):
+        tree = partition_path([list(l) for l in labels], onet.extents(), set(), SplitMix64(100 + r))
+        amp = complex(contract_path(tensors, labels, tree, []))
+        assert abs(amp - sv.amplitudes(n, ops, bits)[0]) < 1e-12
