@@ -2,8 +2,8 @@
 fSim(pi/2, pi/6)) on one MI355X.
 
 Workload: 64 seeded uniform bit-strings; the contraction path is the best of
-greedy and 1024 randomised-greedy trials (run on host threads); indices are sliced so that the live
-set of one slice fits the memory budget.  One *step* is one job of the hot
+greedy and 1024 recursive-bisection trees (run on host threads), each sliced
+so that the live set of one slice fits the memory budget.  One *step* is one job of the hot
 path: one bit-string x one slice, from the leaf gather through every
 pairwise contraction to the FP64 accumulation of the amplitude.  The whole
 job (64 bit-strings x 2^k slices) cannot run in minutes, so `value` is the
@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--precision", default="f16x3", choices=["bf16x3", "bf16x6", "f16x3", "fp32", "auto"])
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time FP32 steps")
     ap.add_argument("--budget-gib", type=float, default=160.0)
-    ap.add_argument("--trials", type=int, default=1024, help="randomised-greedy path search trials")
+    ap.add_argument("--trials", type=int, default=1024, help="path search trials")
+    ap.add_argument("--path", default="partition", choices=["partition", "random_greedy"],
+                    help="path search for the 7x7 workload")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=7)
@@ -98,8 +100,11 @@ def make_workload(a):
     bits = random_bitstrings(64, n, 12345)
     net = tn.tn_build_network(n, ops)
     t0 = time.time()
-    path = tn.tn_find_path(net, "random_greedy", trials=a.trials, seed=1, temperature=0.5,
-                           mem_budget_bytes=a.budget_gib * 2 ** 30)
+    if a.path == "partition":
+        path = tn.tn_find_path(net, "partition", trials=a.trials, seed=1, mem_budget_bytes=a.budget_gib * 2 ** 30)
+    else:
+        path = tn.tn_find_path(net, "random_greedy", trials=a.trials, seed=1, temperature=0.5,
+                               mem_budget_bytes=a.budget_gib * 2 ** 30)
     t_path = time.time() - t0
     return n, ops, bits, net, path, t_path
 
@@ -702,9 +707,10 @@ def main():
                   "fp32": "c64 fp32", "auto": "c64 auto"}[a.precision],
         "data": "synthetic",
         "config": {"workload": f"{a.rows}x{a.cols} grid random circuit, {a.cycles} cycles, fSim(pi/2,pi/6), "
-                               f"64 bit-strings, randomised-greedy path ({a.trials} trials), 2^{path.cost.n_sliced} slices "
+                               f"64 bit-strings, {'recursive-bisection' if a.path == 'partition' else 'randomised-greedy'} "
+                               f"path ({a.trials} trials), 2^{path.cost.n_sliced} slices "
                                f"({a.budget_gib:g} GiB budget); value extrapolated from timed slices",
-                   "qubits": n, "bitstrings": 64, "slices": ns,
+                   "qubits": n, "bitstrings": 64, "slices": ns, "path_search_seconds": t_path,
                    "flops_per_step": flops_job, "flops_per_amplitude": flops_job * ns,
                    "complex_tflops": flops_job / T / 1e12, "precision": a.precision},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",

@@ -28,7 +28,7 @@ from workloads import grid_random_circuit, random_bitstrings
 
 pytestmark = pytest.mark.gpu
 
-PATH_OPTS = dict(trials=1024, seed=1, temperature=0.5, mem_budget_bytes=160.0 * 2 ** 30)
+PATH_OPTS = dict(trials=1024, seed=1, mem_budget_bytes=160.0 * 2 ** 30)   # the benchmark's plan
 
 
 @pytest.fixture(scope="module")
@@ -36,7 +36,7 @@ def identity_coupled():
     import paper_2104_10523_amd as tn
     n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim", fsim_params=(0.0, 0.0))
     net = tn.tn_build_network(n, ops)
-    return n, ops, net, tn.tn_find_path(net, "random_greedy", **PATH_OPTS)
+    return n, ops, net, tn.tn_find_path(net, "partition", **PATH_OPTS)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3"])
@@ -45,17 +45,28 @@ def test_rqc_7x7_14_full_size_slices(gpu, workspace, identity_coupled, precision
     import paper_2104_10523_amd as tn
     n, ops, net, path = identity_coupled
     ns = path.cost.n_sliced
-    assert ns == 7
+    assert ns == 5
     floor = 2.0 ** (-(n + ns) / 2)
     rnd = random_bitstrings(1, n, 12345)[0]
     need = tn.tn_amplitudes_workspace(net, path, 2, precision)
     big = torch.empty(need, dtype=torch.uint8, device=gpu)
     tn.tn_set_workspace(big)
+    # Test slices: the first ones (from slice 1 on) whose largest amplitude
+    # reaches the floor.  Some slices are exactly zero (a sliced bond fixed
+    # to a value the wire's state has no component on); their computed value
+    # is rounding noise of the other wires' product, which can exceed the
+    # floor by 10^4, so a relative error means nothing there.
+    def slice_vals(s):
+        return {l: (s >> (ns - 1 - i)) & 1 for i, l in enumerate(path.sliced)}
+    chosen = [s for s in range(1, 2 ** ns)
+              if abs(separable_slice_amplitude(n, ops, dominant_bits(n, ops, slice_vals(s)), slice_vals(s))) >= floor]
+    chosen = chosen[:2] if precision == "f16x3" else chosen[:1]
+    assert chosen
     try:
         # two slices for the benchmark's precision, one for the others (an
-        # FP32 slice takes ~21 s per bit-string at this size)
-        for s in ((1, 101) if precision == "f16x3" else (1,)):
-            vals = {l: (s >> (ns - 1 - i)) & 1 for i, l in enumerate(path.sliced)}
+        # FP32 slice takes ~6 s per bit-string at this size)
+        for s in chosen:
+            vals = slice_vals(s)
             # the slice's largest amplitude (typical magnitude, so the relative
             # error means something) and one uniform bit-string
             bits = np.array([dominant_bits(n, ops, vals), rnd], dtype=np.int8)
