@@ -436,7 +436,7 @@ def bench_expval(a):
     codes[24] = codes[25] = 3
     net, kept = tn.tn_build_expectation_network(n, ops, codes)
     t0 = time.time()
-    path = tn.tn_find_path(net, "random_greedy", trials=1024, seed=1, mem_budget_bytes=160 * 2 ** 30)
+    path = tn.tn_find_path(net, "partition", trials=1024, seed=1, mem_budget_bytes=160 * 2 ** 30)
     t_path = time.time() - t0
     ns = int(path.cost.n_slices)
     need = max(tn.tn_amplitudes_workspace(net, path, 1, p) for p in ("fp32", a.precision))
@@ -510,7 +510,8 @@ def bench_expval(a):
     return {"metric": "Pauli expectation values/s, <Z24 Z25> on a 49-qubit depth-10 grid (conjugate network)",
             "value": 1.0 / T, "unit": "expectation values/s", "dtype": f"{a.precision} c64, fp64 slice sum",
             "config": {"workload": "7x7 grid, 10 cycles, fSim(pi/2,pi/6), seed 2; double-depth network after "
-                                   "light-cone collapse; randomised-greedy path (1024 trials), 160 GiB budget",
+                                   "light-cone collapse; recursive-bisection path (1024 trials), 160 GiB budget",
+                       "path_search_seconds": t_path,
                        "kept_gates": kept, "gates": len(ops), "slices": ns, "seconds": T,
                        "flops": flops_total, "complex_tflops": flops_total / T / 1e12,
                        "value": [value.real, value.imag], "fp32_value": [v32.real, v32.imag],
