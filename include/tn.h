@@ -177,6 +177,7 @@ typedef struct {
  * Fiduccia-Mattheyses passes move the unlocked leaf of largest cut gain
  * (ties: smallest id) within part sizes [max(1, floor((1-eps)n/2)),
  * n - that], keeping the best prefix, until a pass stops lowering the cut;
+ * each split keeps the lowest cut of 8 such bisections (first on ties);
  * sets of at most `cutoff` leaves are ordered by greedy, the two halves are
  * contracted last.  The plain greedy path and the trials are each sliced to
  * the budget and the lowest (total flops, peak, index) wins.  Host only.

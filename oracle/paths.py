@@ -48,7 +48,9 @@ this is one reading of that, not the paper's partitioner)
     (at most 6): repeatedly move the unlocked leaf of largest cut gain (ties:
     smallest id) whose move keeps both parts within [lo, n - lo], lo =
     max(1, floor((1 - eps) n / 2)); keep the shortest prefix of moves with
-    the lowest cut; stop when a pass does not lower the cut.  The plain greedy
+    the lowest cut; stop when a pass does not lower the cut.  Each split
+    runs this 8 times (the seed leaf drawn anew each time) and keeps the
+    lowest final cut, the first on ties.  The plain greedy
     path and every trial are sliced to the budget, and the lowest (total
     flops, peak, index) wins.
 
@@ -268,6 +270,7 @@ def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:
 # ---------------------------------------------------------------- bisection
 
 CUTOFFS = (2, 4, 8, 16, 32)
+RESTARTS = 8   # bisections tried per split, the lowest cut kept
 
 
 def _leaf_graph(leaves, n_labels, open_set):
@@ -285,6 +288,17 @@ def _leaf_graph(leaves, n_labels, open_set):
 
 
 def _bisect(adj, nodes, eps, rng, side):
+    """The lowest cut of RESTARTS bisections (each from its own seed leaf;
+    the first on ties)."""
+    best = None
+    for _ in range(RESTARTS):
+        p0, p1, cut = _bisect_once(adj, nodes, eps, rng, side)
+        if best is None or cut < best[2]:
+            best = (p0, p1, cut)
+    return best[0], best[1]
+
+
+def _bisect_once(adj, nodes, eps, rng, side):
     n = len(nodes)
     aux = {}
     for v in nodes:
@@ -350,7 +364,7 @@ def _bisect(adj, nodes, eps, rng, side):
     p1 = [v for v in nodes if side[v] == 1]
     for v in nodes:
         side[v] = -1
-    return p0, p1
+    return p0, p1, cut
 
 
 def partition_path(leaves, ext, open_set, rng: SplitMix64) -> List[Tuple[int, int]]:

@@ -404,6 +404,8 @@ LeafGraph leaf_graph(const PathProblem& pr) {
   return g;
 }
 
+constexpr int kRestarts = 8;
+
 struct Bisector {
   const PathProblem& pr;
   const LeafGraph& g;
@@ -420,12 +422,28 @@ struct Bisector {
       : pr(p), g(gr), eps(e), cutoff(c), rng(r), side(p.leaves.size(), -1), aux(p.leaves.size(), 0),
         locked(p.leaves.size(), 0), next_id(int(p.leaves.size())) {}
 
-  // Splits `nodes` (ascending) in two: part 0 grown from a random seed leaf
-  // by most links into it (ties: smallest id) to half the set, then
+  // Splits `nodes` in two: the lowest cut of kRestarts bisections (each
+  // from its own seed leaf; the first on ties).
+  void bisect(const std::vector<int>& nodes, std::vector<int>& p0, std::vector<int>& p1) {
+    int best = -1;
+    std::vector<int> a, b;
+    for (int r = 0; r < kRestarts; ++r) {
+      const int c = bisect_once(nodes, a, b);
+      if (best < 0 || c < best) {
+        best = c;
+        p0 = a;
+        p1 = b;
+      }
+    }
+  }
+
+  // One bisection of `nodes` (ascending): part 0 grown from a random seed
+  // leaf by most links into it (ties: smallest id) to half the set, then
   // Fiduccia-Mattheyses passes: move the unlocked leaf of largest cut gain
   // (ties: smallest id) that keeps both parts within [lo, hi], keep the
   // best prefix of moves, stop when a pass no longer lowers the cut.
-  void bisect(const std::vector<int>& nodes, std::vector<int>& p0, std::vector<int>& p1) {
+  // Returns the final cut.
+  int bisect_once(const std::vector<int>& nodes, std::vector<int>& p0, std::vector<int>& p1) {
     const int n = int(nodes.size());
     for (int v : nodes) {
       side[v] = 1;
@@ -498,6 +516,7 @@ struct Bisector {
     p1.clear();
     for (int v : nodes) (side[v] == 0 ? p0 : p1).push_back(v);
     for (int v : nodes) side[v] = -1;
+    return cut;
   }
 
   // Contraction tree of `nodes`: the two halves' results contracted last;
