@@ -50,7 +50,15 @@ this is one reading of that, not the paper's partitioner)
     max(1, floor((1 - eps) n / 2)); keep the shortest prefix of moves with
     the lowest cut; stop when a pass does not lower the cut.  Each split
     runs this 8 times (the seed leaf drawn anew each time) and keeps the
-    lowest final cut, the first on ties.  The plain greedy
+    lowest final cut, the first on ties.  Each tree is then reconfigured:
+    for every internal node in creation order, the frontier of its subtree
+    grows to at most 8 tensors by expanding the internal frontier node of
+    largest result size (ties: smallest id); the cheapest pairwise order of
+    that frontier (exact search over subsets, the lowest-bit subset of a
+    split first, splits in descending subset order, strict improvement;
+    kept labels = the node's result) replaces the subtree when it costs
+    strictly fewer flops, the freed internal ids reused in ascending order in
+    post-order.  The plain greedy
     path and every trial are sliced to the budget, and the lowest (total
     flops, peak, index) wins.
 
@@ -271,6 +279,7 @@ def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:
 
 CUTOFFS = (2, 4, 8, 16, 32)
 RESTARTS = 8   # bisections tried per split, the lowest cut kept
+RECONF = 8     # frontier size of the subtree reconfiguration
 
 
 def _leaf_graph(leaves, n_labels, open_set):
@@ -408,6 +417,127 @@ def partition_path(leaves, ext, open_set, rng: SplitMix64) -> List[Tuple[int, in
     return pairs
 
 
+def reconfigure_path(leaves, ext, open_set, path) -> List[Tuple[int, int]]:
+    """Subtree reconfiguration of a complete SSA path (see the header)."""
+    open_set = set(open_set)
+    n = len(leaves)
+    total = n + len(path)
+    ca, cb = [-1] * total, [-1] * total
+    for t, (i, j) in enumerate(path):
+        ca[n + t], cb[n + t] = i, j
+    holders: Dict[int, int] = {}
+    for ls in leaves:
+        for l in ls:
+            holders[l] = holders.get(l, 0) + 1
+    cnt: List[Dict[int, int]] = [dict() for _ in range(total)]
+    sets: List[List[int]] = [[] for _ in range(total)]
+    for i in range(n):
+        for l in leaves[i]:
+            cnt[i][l] = 1
+        sets[i] = sorted(leaves[i])
+    for v in range(n, total):
+        c = dict(cnt[ca[v]])
+        for l, k in cnt[cb[v]].items():
+            c[l] = c.get(l, 0) + k
+        cnt[v] = c
+        sets[v] = sorted(l for l, k in c.items() if l in open_set or k < holders[l])
+
+    def flops_of(a, b):
+        return 8.0 * size_of(set(a) | set(b), ext)
+
+    cost = [0.0] * total
+    for v in range(n, total):
+        cost[v] = flops_of(sets[ca[v]], sets[cb[v]])
+    for v in range(n, total):
+        F = [ca[v], cb[v]]
+        region = [v]
+        while len(F) < RECONF:
+            pick = None
+            for k, u in enumerate(F):
+                if u < n:
+                    continue
+                su = size_of(sets[u], ext)
+                if pick is None or su > size_of(sets[F[pick]], ext) or \
+                        (su == size_of(sets[F[pick]], ext) and u < F[pick]):
+                    pick = k
+            if pick is None:
+                break
+            u = F[pick]
+            region.append(u)
+            del F[pick]
+            F.append(ca[u])
+            F.append(cb[u])
+        if len(F) < 3:
+            continue
+        cur = 0.0
+        for u in region:
+            cur += cost[u]
+        m = len(F)
+        full = (1 << m) - 1
+        keep_v = set(sets[v])
+        rs: List[List[int]] = [[] for _ in range(full + 1)]
+        for S in range(1, full + 1):
+            if S & (S - 1) == 0:
+                rs[S] = sets[F[(S & -S).bit_length() - 1]]
+                continue
+            u_set, out_set = set(), set()
+            for k in range(m):
+                (u_set if S >> k & 1 else out_set).update(sets[F[k]])
+            rs[S] = sorted(l for l in u_set if l in keep_v or l in out_set)
+        best = [0.0] * (full + 1)
+        split = [0] * (full + 1)
+        for S in range(1, full + 1):
+            if S & (S - 1) == 0:
+                continue
+            low = S & -S
+            bv, bs = -1.0, 0
+            A = (S - 1) & S
+            while A > 0:
+                if A & low:
+                    B = S ^ A
+                    c = best[A] + best[B] + flops_of(rs[A], rs[B])
+                    if bv < 0 or c < bv:
+                        bv, bs = c, A
+                A = (A - 1) & S
+            best[S], split[S] = bv, bs
+        if not best[full] < cur:
+            continue
+        ids = [region[0]] + sorted(region[1:])
+        nxt = [1]
+
+        def make(S):
+            if S & (S - 1) == 0:
+                return F[(S & -S).bit_length() - 1]
+            A = split[S]
+            x = make(A)
+            y = make(S ^ A)
+            if S == full:
+                node = v
+            else:
+                node = ids[nxt[0]]
+                nxt[0] += 1
+            ca[node], cb[node] = x, y
+            sets[node] = rs[S]
+            cost[node] = flops_of(sets[x], sets[y])
+            return node
+
+        make(full)
+    out: List[Tuple[int, int]] = []
+    nid = [n]
+
+    def emit(u):
+        if u < n:
+            return u
+        x = emit(ca[u])
+        y = emit(cb[u])
+        out.append((x, y))
+        nid[0] += 1
+        return nid[0] - 1
+
+    emit(total - 1)
+    return out
+
+
 def partition_search(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
                      budget_bytes: float = 0.0) -> List[Tuple[int, int]]:
     """Best of the plain greedy path and `trials` bisection trees by sliced
@@ -415,7 +545,8 @@ def partition_search(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
     cands = [greedy_path(leaves, ext, open_set)]
     for r in range(trials):
         g = SplitMix64((seed + r * GOLDEN) & MASK64)
-        cands.append(partition_path(leaves, ext, open_set, SplitMix64(g.next_u64())))
+        cands.append(reconfigure_path(leaves, ext, open_set,
+                                      partition_path(leaves, ext, open_set, SplitMix64(g.next_u64()))))
     best = None
     for i, p in enumerate(cands):
         try:
