@@ -179,8 +179,13 @@ typedef struct {
  * n - that], keeping the best prefix, until a pass stops lowering the cut;
  * each split keeps the lowest cut of 8 such bisections (first on ties);
  * sets of at most `cutoff` leaves are ordered by greedy, the two halves are
- * contracted last.  The plain greedy path and the trials are each sliced to
- * the budget and the lowest (total flops, peak, index) wins.  Host only.
+ * contracted last.  Each tree is then reconfigured: for every internal node
+ * (creation order) the frontier of its subtree grows to at most 8 tensors by
+ * expanding the internal frontier node of largest result size (ties:
+ * smallest id), and the flop-optimal order of that frontier (exact search
+ * over subsets) replaces the subtree when strictly cheaper.  The plain
+ * greedy path and the trials are each sliced to the budget and the lowest
+ * (total flops, peak, index) wins.  Host only.
  * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */
 tn_status tn_find_path(const tn_network* n, const tn_path_opts* o,
                        tn_path** out, tn_path_cost* cost);

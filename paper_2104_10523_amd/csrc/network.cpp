@@ -9,6 +9,7 @@
 // Tensors: two-qubit gates in circuit order, then lone wires in qubit order.
 // Labels are handed out as legs are created (a's output, then b's).
 #include <algorithm>
+#include <functional>
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
@@ -568,6 +569,151 @@ std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t*
   return std::move(b.pairs);
 }
 
+// Subtree reconfiguration: for every internal node (in creation order) the
+// frontier of its subtree is grown to at most kReconf tensors by expanding
+// the largest internal frontier node (ties: smallest id); the cheapest order
+// of that frontier (exact search over subsets, flops 8*size(A u B) per step,
+// kept labels = the node's result) replaces the subtree when it is cheaper.
+constexpr int kReconf = 8;
+
+std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
+                                                  const std::vector<std::pair<int, int>>& path) {
+  const int n = int(pr.leaves.size());
+  const int total = n + int(path.size());
+  std::vector<int> ca(total, -1), cb(total, -1);
+  for (size_t t = 0; t < path.size(); ++t) {
+    ca[n + t] = path[t].first;
+    cb[n + t] = path[t].second;
+  }
+  // result label sets bottom-up (labels leaving the subtree, or open)
+  std::vector<int> holders_n(pr.ext.size(), 0);
+  for (const auto& L : pr.leaves)
+    for (int l : L) ++holders_n[l];
+  std::vector<std::vector<int>> sets(total);
+  // label counts inside each subtree as sorted (label, count) vectors
+  std::vector<std::vector<std::pair<int, int>>> cnt(total);
+  for (int i = 0; i < n; ++i) {
+    for (int l : pr.leaves[i]) cnt[i].push_back({l, 1});
+    sets[i] = pr.leaves[i];
+  }
+  auto merge_cnt = [](const std::vector<std::pair<int, int>>& x, const std::vector<std::pair<int, int>>& y) {
+    std::vector<std::pair<int, int>> r;
+    size_t i = 0, j = 0;
+    while (i < x.size() || j < y.size()) {
+      if (j == y.size() || (i < x.size() && x[i].first < y[j].first)) r.push_back(x[i++]);
+      else if (i == x.size() || y[j].first < x[i].first) r.push_back(y[j++]);
+      else { r.push_back({x[i].first, x[i].second + y[j].second}); ++i; ++j; }
+    }
+    return r;
+  };
+  for (int v = n; v < total; ++v) {
+    cnt[v] = merge_cnt(cnt[ca[v]], cnt[cb[v]]);
+    std::vector<int> r;
+    for (const auto& [l, c] : cnt[v])
+      if (pr.open[l] || c < holders_n[l]) r.push_back(l);
+    sets[v] = std::move(r);
+  }
+  auto flops_of = [&](const std::vector<int>& a, const std::vector<int>& b) {
+    return 8.0 * size_of(set_union(a, b), pr.ext);
+  };
+  std::vector<double> cost(total, 0.0);
+  for (int v = n; v < total; ++v) cost[v] = flops_of(sets[ca[v]], sets[cb[v]]);
+  for (int v = n; v < total; ++v) {
+    // frontier of v
+    std::vector<int> F = {ca[v], cb[v]};
+    std::vector<int> region = {v};
+    while (int(F.size()) < kReconf) {
+      int pick = -1;
+      for (size_t k = 0; k < F.size(); ++k) {
+        const int u = F[k];
+        if (u < n) continue;
+        if (pick < 0 || size_of(sets[u], pr.ext) > size_of(sets[F[pick]], pr.ext) ||
+            (size_of(sets[u], pr.ext) == size_of(sets[F[pick]], pr.ext) && u < F[pick]))
+          pick = int(k);
+      }
+      if (pick < 0) break;
+      const int u = F[pick];
+      region.push_back(u);
+      F.erase(F.begin() + pick);
+      F.push_back(ca[u]);
+      F.push_back(cb[u]);
+    }
+    if (F.size() < 3) continue;
+    double cur = 0.0;
+    for (int u : region) cur += cost[u];
+    // exact search over subsets of the frontier
+    const int m = int(F.size());
+    const int full = (1 << m) - 1;
+    // labels of each subset's result: labels in the subset's union that are in sets[v]
+    // or held by another frontier member
+    std::vector<std::vector<int>> rs(full + 1);
+    std::vector<double> best(full + 1, 0.0);
+    std::vector<int> split(full + 1, 0);
+    for (int S = 1; S <= full; ++S) {
+      std::vector<int> u;
+      for (int k = 0; k < m; ++k)
+        if (S >> k & 1) u = set_union(u, sets[F[k]]);
+      if ((S & (S - 1)) == 0) {
+        rs[S] = sets[F[__builtin_ctz(S)]];
+        continue;
+      }
+      std::vector<int> outside;
+      for (int k = 0; k < m; ++k)
+        if (!(S >> k & 1)) outside = set_union(outside, sets[F[k]]);
+      std::vector<int> r;
+      for (int l : u)
+        if (std::binary_search(sets[v].begin(), sets[v].end(), l) ||
+            std::binary_search(outside.begin(), outside.end(), l))
+          r.push_back(l);
+      rs[S] = std::move(r);
+    }
+    for (int S = 1; S <= full; ++S) {
+      if ((S & (S - 1)) == 0) continue;
+      const int low = S & -S;
+      double bv = -1.0;
+      int bs = 0;
+      for (int A = (S - 1) & S; A > 0; A = (A - 1) & S) {
+        if (!(A & low)) continue;
+        const int B = S ^ A;
+        const double c = best[A] + best[B] + flops_of(rs[A], rs[B]);
+        if (bv < 0 || c < bv) { bv = c; bs = A; }
+      }
+      best[S] = bv;
+      split[S] = bs;
+    }
+    if (!(best[full] < cur)) continue;
+    // rebuild the region: reuse the region's node ids for the new internal nodes
+    std::vector<int> ids(region);   // v stays the root
+    std::sort(ids.begin() + 1, ids.end());
+    int next = 1;
+    std::function<int(int)> make = [&](int S) -> int {
+      if ((S & (S - 1)) == 0) return F[__builtin_ctz(S)];
+      const int A = split[S], B = S ^ A;
+      const int x = make(A), y = make(B);
+      const int node = S == full ? v : ids[next++];
+      ca[node] = x;
+      cb[node] = y;
+      sets[node] = rs[S];
+      cost[node] = flops_of(sets[x], sets[y]);
+      return node;
+    };
+    make(full);
+  }
+  // emit SSA pairs in a post-order of the new tree
+  std::vector<std::pair<int, int>> out;
+  std::vector<int> ssa(total, -1);
+  for (int i = 0; i < n; ++i) ssa[i] = i;
+  int nid = n;
+  std::function<int(int)> emit = [&](int u) -> int {
+    if (u < n) return u;
+    const int x = emit(ca[u]), y = emit(cb[u]);
+    out.push_back({x, y});
+    return nid++;
+  };
+  emit(total - 1);
+  return out;
+}
+
 std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
                                                   double budget_bytes) {
   // Candidates: the plain greedy path (index 0) and `trials` bisection trees
@@ -592,7 +738,7 @@ std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_
   parallel_for(trials, [&](int r) {
     uint64_t gs = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
     uint64_t st = splitmix64_next(&gs);
-    paths[r + 1] = partition_path(pr, &st);
+    paths[r + 1] = reconfigure_path(pr, partition_path(pr, &st));
     score(r + 1);
   });
   int win = -1;

@@ -81,6 +81,10 @@ PathStats path_stats(const PathProblem& pr, const std::vector<std::pair<int, int
 // from the SplitMix64 stream `rng`), and the best of greedy + `trials` such
 // trees by sliced (total flops, peak).
 std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t* rng);
+// Subtree reconfiguration of a complete path: every internal node's subtree
+// frontier (at most kReconf tensors) is reordered optimally by flops.
+std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
+                                                  const std::vector<std::pair<int, int>>& path);
 std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
                                                   double budget_bytes);
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

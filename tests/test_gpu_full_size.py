@@ -45,7 +45,7 @@ def test_rqc_7x7_14_full_size_slices(gpu, workspace, identity_coupled, precision
     import paper_2104_10523_amd as tn
     n, ops, net, path = identity_coupled
     ns = path.cost.n_sliced
-    assert ns == 3
+    assert ns == 5
     floor = 2.0 ** (-(n + ns) / 2)
     rnd = random_bitstrings(1, n, 12345)[0]
     need = tn.tn_amplitudes_workspace(net, path, 2, precision)

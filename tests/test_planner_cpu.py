@@ -15,7 +15,7 @@ import pytest
 import paper_2104_10523_amd as tn
 from oracle.network import build_network
 from oracle.paths import (SplitMix64, greedy_path, partition_path, partition_search, path_stats,
-                          random_greedy_path, slice_path)
+                          random_greedy_path, reconfigure_path, slice_path)
 from workloads import Op, grid_random_circuit, chain_random_circuit, cat_circuit, qft_circuit
 
 HEADER = Path(__file__).resolve().parent.parent / "include" / "tn.h"
@@ -288,7 +288,19 @@ def test_partition_tree_contracts_to_the_amplitude():
     onet = build_network(n, ops)
     bits = [1, 0, 1, 1, 0, 0, 1, 0, 1]
     tensors, labels, open_l = fix_outputs(onet, bits)
+    improved = 0
     for r in range(3):
-        tree = partition_path([list(l) for l in labels], onet.extents(), set(), SplitMix64(100 + r))
+        ls = [list(l) for l in labels]
+        tree = partition_path(ls, onet.extents(), set(), SplitMix64(100 + r))
         amp = complex(contract_path(tensors, labels, tree, []))
         assert abs(amp - sv.amplitudes(n, ops, bits)[0]) < 1e-12
+        # the reconfigured tree is complete, never costs more, and contracts
+        # to the same amplitude
+        rt = reconfigure_path(ls, onet.extents(), set(), tree)
+        f0 = path_stats(ls, onet.extents(), tree)["flops"]
+        f1 = path_stats(ls, onet.extents(), rt)["flops"]
+        assert f1 <= f0
+        improved += f1 < f0
+        amp_r = complex(contract_path(tensors, labels, rt, []))
+        assert abs(amp_r - sv.amplitudes(n, ops, bits)[0]) < 1e-12
+    assert improved >= 1
