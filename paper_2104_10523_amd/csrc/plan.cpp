@@ -305,7 +305,12 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   int transA = 0, transB = 0;
   TRef Ap = A, Bp = B;
   int prec = resolve_precision(precision, Mn, Nn, Kn);
-  const bool packable = Kn % 4 == 0 && !(Mn == 1 && Nn == 1);
+  // packed planes are addressed with 32-bit panel offsets: a 256-row panel
+  // of one plane (4 bytes per entry) must stay below 2 GiB, so K <= 2^20;
+  // longer contractions run on the FP32 kernel at every precision
+  const bool long_k = Kn > (int64_t(1) << 20);
+  const bool packable = Kn % 4 == 0 && !long_k && !(Mn == 1 && Nn == 1);
+  if (long_k) prec = TN_PREC_FP32;
   // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
   if (prec == TN_PREC_F16X3 && !packable) prec = TN_PREC_FP32;
   const bool packed = (prec == TN_PREC_BF16X3 || prec == TN_PREC_BF16X6 || prec == TN_PREC_F16X3) && packable;

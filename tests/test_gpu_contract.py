@@ -71,6 +71,7 @@ CASES = [
     ("gemm_n16", dict(nm=11, nk=7, nn=4 + 1)),
     ("gemm_n32", dict(nm=10, nk=8, nn=5)),
     ("gemm_splitk", dict(nm=6, nk=14, nn=6)),
+    ("gemm_k_beyond_packed_panels", dict(nm=2, nk=21, nn=2)),   # K = 2^21: packed planes would overflow
     ("gemm_batch", dict(nb=3, nm=7, nk=6, nn=6)),
     ("gemm_wide_extents", dict(nm=5, nk=3, nn=6, wide=8)),
     ("outer_product", dict(nm=8, nk=0, nn=6)),
@@ -93,7 +94,12 @@ def test_contract_pair(gpu, workspace, name, kw, precision):
     ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
     assert np.all(np.isfinite(got))
     err = l2_rel(got, ref)
-    assert err <= TOL[precision], (name, precision, err)
+    tol = TOL[precision]
+    if name == "gemm_k_beyond_packed_panels":
+        # K = 2^21 runs on the FP32 kernel at every precision: 4096-long FP32
+        # chains plus 512 chunk additions, 2^-24 * sqrt(4096 + 512) ~ 4e-6
+        tol = max(tol, 4e-6)
+    assert err <= tol, (name, precision, err)
 
 
 def test_contract_pair_unshuffled_orders(gpu, workspace):
