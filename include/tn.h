@@ -422,6 +422,19 @@ tn_status tn_build_expectation_network(const tn_circuit* c, const int8_t* pauli,
 tn_status tn_build_density_network(const tn_circuit* c, const int8_t* pauli,
                                    tn_network** out, int64_t* kept_ops);
 
+/* Samples from a marginal wave-function slice (Sec. 4.4; Table 1's
+ * sampling from partial state vectors): psi is a device array of n complex128
+ * amplitudes (e.g. one tn_amplitudes output row with open qubits), uniforms
+ * m host values in [0, 1).  out[s] (host) receives the first index k with
+ * C(k) > u_s * C(n-1), C the inclusive cumulative sum of |psi|^2 (FP64,
+ * summed chunk by chunk of 4096 entries, chunks in index order), i.e. a
+ * draw with probability |psi_k|^2 / sum |psi|^2; total (host, may be NULL)
+ * receives sum |psi|^2.  Allocates a small device scratch and synchronises
+ * the stream.  Errors: TN_ERR_ARG (null, sizes, a uniform outside [0, 1),
+ * all amplitudes zero), TN_ERR_UNSUPPORTED, TN_ERR_DEVICE. */
+tn_status tn_sample_amplitudes(const void* psi, int64_t n, const double* uniforms,
+                               int64_t m, int64_t* out, double* total, void* stream);
+
 /* <P> by wave-function slicing: `psi` is the device output of tn_amplitudes
  * for the n_slices bit-strings `bits` (host, n_slices x n_qubits, 0 / 1 for
  * projected qubits, -1 for the open qubits, the same open set in every row),

@@ -19,7 +19,7 @@ from ._native import (GATE_IDS, PATH_ALGO, PAULI, PREC, TnCircuit, TnExecOpts, T
 __all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
            "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
            "tn_amplitudes_workspace", "tn_build_expectation_network", "tn_build_density_network",
-           "tn_pauli_expectation",
+           "tn_pauli_expectation", "tn_sample_amplitudes",
            "tn_mps_create", "tn_mps_apply_gate", "tn_run_trajectories", "PREC", "lib"]
 
 
@@ -266,6 +266,20 @@ def tn_build_density_network(n_qubits: int, ops, pauli):
     check(lib().tn_build_density_network(C.byref(ca.circ), p.ctypes.data_as(C.POINTER(C.c_int8)),
                                          C.byref(h), C.byref(kept)))
     return Network(h.value, 0), int(kept.value)
+
+
+def tn_sample_amplitudes(psi, uniforms, stream=None):
+    """Indices drawn with probability |psi_k|^2 / sum |psi|^2 at the given
+    uniforms (psi: a contiguous complex128 CUDA tensor).  Returns
+    (indices int64 array, sum |psi|^2)."""
+    u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1))
+    out = np.zeros(u.size, dtype=np.int64)
+    assert psi.is_contiguous() and psi.dtype.is_complex
+    tot = C.c_double()
+    check(lib().tn_sample_amplitudes(C.c_void_p(psi.data_ptr()), psi.numel(), u.ctypes.data_as(C.POINTER(C.c_double)),
+                                     u.size, out.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(tot),
+                                     C.c_void_p(_stream_ptr(stream))))
+    return out, float(tot.value)
 
 
 def tn_pauli_expectation(psi, bits, pauli, stream=None) -> complex:

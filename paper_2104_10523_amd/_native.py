@@ -103,6 +103,7 @@ SIGNATURES = {
     "tn_build_expectation_network": (I32, [C.POINTER(TnCircuit), PI8, PP, C.POINTER(C.c_int64)]),
     "tn_build_density_network": (I32, [C.POINTER(TnCircuit), PI8, PP, C.POINTER(C.c_int64)]),
     "tn_pauli_expectation": (I32, [P, PI8, I64, I32, PI8, PD, P]),
+    "tn_sample_amplitudes": (I32, [P, I64, PD, I64, C.POINTER(C.c_int64), PD, P]),
     "tn_mps_create": (I32, [I32, I32, P, PP]),
     "tn_mps_destroy": (I32, [P]),
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),

@@ -14,6 +14,10 @@
 // every op as its superoperator on (ket, bra) legs, closed by P; a closed
 // network with no output legs, contracted on the same engine.
 //
+// Sampling from a marginal slice (Sec. 4.4 slices as sampling input):
+// bit-strings drawn with probability |psi_x|^2 / sum |psi|^2 by inverting
+// the cumulative distribution (FP64) at caller-given uniforms.
+//
 // Wave-function slicing: the amplitudes of every projection of the closed
 // qubits (tn_amplitudes with the open set left open) are reduced on the
 // device as sum_s sum_x conj(psi_s[x]) (P psi_s)[x] in FP64.  X and Y
@@ -83,6 +87,58 @@ __global__ void pauli_final_kernel(const double2* __restrict__ part, int n, doub
     im += __shfl_xor(im, o);
   }
   if (threadIdx.x == 0) *out = make_double2(re, im);
+}
+
+constexpr int kSampleChunk = 4096;   // amplitudes per block of the sampler
+
+// Sum of |psi|^2 over each chunk of kSampleChunk entries (FP64).
+__global__ __launch_bounds__(256) void chunk_prob_kernel(const double2* __restrict__ psi, int64_t n,
+                                                         double* __restrict__ chunk) {
+  __shared__ double red[4];
+  const int64_t base = int64_t(blockIdx.x) * kSampleChunk;
+  double acc = 0;
+  for (int i = threadIdx.x; i < kSampleChunk; i += 256) {
+    const int64_t k = base + i;
+    if (k < n) acc += psi[k].x * psi[k].x + psi[k].y * psi[k].y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) chunk[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// In-place inclusive prefix sum of the chunk sums, in index order (one thread).
+__global__ void chunk_scan_kernel(double* __restrict__ chunk, int64_t nc) {
+  double acc = 0;
+  for (int64_t i = 0; i < nc; ++i) {
+    acc += chunk[i];
+    chunk[i] = acc;
+  }
+}
+
+// Sample s: the first index k with (prefix of chunks before k's chunk) +
+// (|psi|^2 summed over k's chunk up to k) > u_s * total.
+__global__ void sample_kernel(const double2* __restrict__ psi, int64_t n, const double* __restrict__ cum,
+                              int64_t nc, const double* __restrict__ u, int64_t m,
+                              int64_t* __restrict__ out) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const double target = u[s] * cum[nc - 1];
+  int64_t lo = 0, hi = nc - 1;           // first chunk whose inclusive sum exceeds target
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (cum[mid] > target) hi = mid;
+    else lo = mid + 1;
+  }
+  double acc = lo > 0 ? cum[lo - 1] : 0.0;
+  const int64_t b0 = lo * kSampleChunk, b1 = min(n, b0 + kSampleChunk);
+  int64_t pick = b1 - 1;
+  for (int64_t k = b0; k < b1; ++k) {
+    acc += psi[k].x * psi[k].x + psi[k].y * psi[k].y;
+    if (acc > target) { pick = k; break; }
+  }
+  out[s] = pick;
 }
 
 }  // namespace
@@ -295,6 +351,49 @@ tn_status tn_build_density_network(const tn_circuit* c, const int8_t* pauli, tn_
     auto n = std::make_unique<tn_network>();
     n->net = build_density_network(*c, pauli, kept_ops);
     *out = n.release();
+  });
+}
+
+tn_status tn_sample_amplitudes(const void* psi, int64_t n, const double* uniforms, int64_t m, int64_t* out,
+                               double* total, void* stream) {
+  return guarded([&] {
+    TN_REQUIRE(psi && uniforms && out && n >= 1 && m >= 0, TN_ERR_ARG, "bad argument");
+    for (int64_t s = 0; s < m; ++s)
+      TN_REQUIRE(uniforms[s] >= 0.0 && uniforms[s] < 1.0, TN_ERR_ARG, "uniforms must lie in [0, 1)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nc = (n + kSampleChunk - 1) / kSampleChunk;
+    TN_REQUIRE(nc <= (int64_t(1) << 31) - 1, TN_ERR_UNSUPPORTED, "too many amplitudes");
+    double *cum = nullptr, *du = nullptr;
+    int64_t* dout = nullptr;
+    auto cleanup = [&]() {
+      for (void* p : {(void*)cum, (void*)du, (void*)dout})
+        if (p) (void)hipFree(p);
+    };
+    try {
+      TN_HIP(hipMalloc(&cum, size_t(nc) * sizeof(double)));
+      TN_HIP(hipMalloc(&du, size_t(std::max<int64_t>(m, 1)) * sizeof(double)));
+      TN_HIP(hipMalloc(&dout, size_t(std::max<int64_t>(m, 1)) * sizeof(int64_t)));
+      chunk_prob_kernel<<<unsigned(nc), 256, 0, st>>>(static_cast<const double2*>(psi), n, cum);
+      TN_HIP(hipGetLastError());
+      chunk_scan_kernel<<<1, 1, 0, st>>>(cum, nc);
+      TN_HIP(hipGetLastError());
+      if (m > 0) {
+        TN_HIP(hipMemcpyAsync(du, uniforms, size_t(m) * sizeof(double), hipMemcpyHostToDevice, st));
+        sample_kernel<<<unsigned((m + 255) / 256), 256, 0, st>>>(static_cast<const double2*>(psi), n, cum, nc,
+                                                                  du, m, dout);
+        TN_HIP(hipGetLastError());
+        TN_HIP(hipMemcpyAsync(out, dout, size_t(m) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      }
+      double tot = 0;
+      TN_HIP(hipMemcpyAsync(&tot, cum + nc - 1, sizeof(double), hipMemcpyDeviceToHost, st));
+      TN_HIP(hipStreamSynchronize(st));
+      TN_REQUIRE(tot > 0, TN_ERR_ARG, "all amplitudes are zero");
+      if (total) *total = tot;
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    cleanup();
   });
 }
 
