@@ -49,6 +49,8 @@ def kernel_name(precision, tile, packed):
         f16 = "true" if precision == "f16x3" else "false"
         return f"{kern}<{bm}, {bn}, {bk}, {wm}, {wn}, {np_}, {f16}>"
     bm, bn = UNPACKED_TILES[tile]
+    if precision == "f16x3":
+        precision = "fp32"        # split FP16 exists only on packed planes
     bk = 8 if precision == "fp32" else 16
     wm, wn = (2, 2) if bn >= 64 else (4, 1)
     return f"gemm_mfma_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {precision}>"
