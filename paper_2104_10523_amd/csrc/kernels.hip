@@ -109,13 +109,16 @@ __device__ __forceinline__ float operand_scale(const uint32_t* smax) {
 
 // ------------------------------------------------------------------ permute
 
+constexpr int kPermBits = 12;                 // tile = 6 input + 6 output bits
+constexpr int kPermTile = 1 << kPermBits;
+
 struct PermArgs {
   int tb, rb;
   int64_t n_tiles;
   int64_t plane;
-  int8_t tpos[10];
-  int8_t opos[10];
-  int8_t map[10];
+  int8_t tpos[kPermBits];
+  int8_t opos[kPermBits];
+  int8_t map[kPermBits];
   int8_t r_in[kMaxBits];
   int8_t r_out[kMaxBits];
 };
@@ -125,24 +128,24 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
                                                             void* __restrict__ out, PermArgs P,
                                                             const uint32_t* __restrict__ smax) {
   const float scale = NP == kF16 ? operand_scale(smax) : 1.f;
-  __shared__ int64_t s_in_lo[32], s_in_hi[32], s_out_lo[32], s_out_hi[32];
-  __shared__ int s_l_lo[32], s_l_hi[32];
-  __shared__ float2 tile[1024 + 32];
+  __shared__ int64_t s_in_lo[64], s_in_hi[64], s_out_lo[64], s_out_hi[64];
+  __shared__ int s_l_lo[64], s_l_hi[64];
+  __shared__ float2 tile[kPermTile + kPermTile / 64];
   const int t = threadIdx.x;
-  if (t < 32) {
+  if (t < 64) {
     int64_t il = 0, ih = 0, ol = 0, oh = 0;
     int ll = 0, lh = 0;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
       if (!((t >> i) & 1)) continue;
       if (i < P.tb) {
         il |= int64_t(1) << P.tpos[i];
         ol |= int64_t(1) << P.opos[i];
         ll |= 1 << P.map[i];
       }
-      if (i + 5 < P.tb) {
-        ih |= int64_t(1) << P.tpos[i + 5];
-        oh |= int64_t(1) << P.opos[i + 5];
-        lh |= 1 << P.map[i + 5];
+      if (i + 6 < P.tb) {
+        ih |= int64_t(1) << P.tpos[i + 6];
+        oh |= int64_t(1) << P.opos[i + 6];
+        lh |= 1 << P.map[i + 6];
       }
     }
     s_in_lo[t] = il; s_in_hi[t] = ih;
@@ -160,11 +163,11 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
       }
     }
     for (int e = t; e < tsize; e += 256)
-      tile[e + (e >> 5)] = in[ib + s_in_lo[e & 31] + s_in_hi[e >> 5]];
+      tile[e + (e >> 6)] = in[ib + s_in_lo[e & 63] + s_in_hi[e >> 6]];
     __syncthreads();
     for (int f = t; f < tsize; f += 256) {
-      const int e = s_l_lo[f & 31] | s_l_hi[f >> 5];
-      put<NP>(out, P.plane, ob + s_out_lo[f & 31] + s_out_hi[f >> 5], tile[e + (e >> 5)], scale);
+      const int e = s_l_lo[f & 63] | s_l_hi[f >> 6];
+      put<NP>(out, P.plane, ob + s_out_lo[f & 63] + s_out_hi[f >> 6], tile[e + (e >> 6)], scale);
     }
     __syncthreads();
   }
@@ -226,15 +229,15 @@ static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d,
     TN_HIP(hipGetLastError());
     return;
   }
-  // tile bits: the 5 lowest input bits and the input bits of the 5 lowest
-  // output bits, padded with the next lowest input bits up to 10.
+  // tile bits: the 6 lowest input bits and the input bits of the 6 lowest
+  // output bits, padded with the next lowest input bits up to 12.
   std::vector<char> inT(nb, 0);
-  const int a = std::min(5, nb);
+  const int a = std::min(kPermBits / 2, nb);
   for (int i = 0; i < a; ++i) inT[i] = 1;
   for (int j = 0; j < a; ++j) inT[d.src[j]] = 1;
   int cnt = 0;
   for (int i = 0; i < nb; ++i) cnt += inT[i];
-  const int want = std::min(10, nb);
+  const int want = std::min(kPermBits, nb);
   for (int i = 0; i < nb && cnt < want; ++i)
     if (!inT[i]) { inT[i] = 1; ++cnt; }
   PermArgs P;
