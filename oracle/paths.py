@@ -58,7 +58,8 @@ this is one reading of that, not the paper's partitioner)
     split first, splits in descending subset order, strict improvement;
     kept labels = the node's result) replaces the subtree when it costs
     strictly fewer flops, the freed internal ids reused in ascending order in
-    post-order.  The plain greedy
+    post-order; passes repeat (at most 8) until one no longer lowers the
+    tree's flops.  The plain greedy
     path and every trial are sliced to the budget, and the lowest (total
     flops, peak, index) wins.
 
@@ -280,6 +281,7 @@ def slice_path(leaves, ext, path, open_set, budget_bytes: float) -> List[int]:
 CUTOFFS = (2, 4, 8, 16, 32)
 RESTARTS = 8   # bisections tried per split, the lowest cut kept
 RECONF = 8     # frontier size of the subtree reconfiguration
+RECONF_PASSES = 8   # reconfiguration passes, until one no longer lowers the flops
 
 
 def _leaf_graph(leaves, n_labels, open_set):
@@ -545,8 +547,16 @@ def partition_search(leaves, ext, open_set=(), seed: int = 0, trials: int = 32,
     cands = [greedy_path(leaves, ext, open_set)]
     for r in range(trials):
         g = SplitMix64((seed + r * GOLDEN) & MASK64)
-        cands.append(reconfigure_path(leaves, ext, open_set,
-                                      partition_path(leaves, ext, open_set, SplitMix64(g.next_u64()))))
+        cur = partition_path(leaves, ext, open_set, SplitMix64(g.next_u64()))
+        fl = path_stats(leaves, ext, cur, open_set)["flops"]
+        for _ in range(RECONF_PASSES):
+            nxt = reconfigure_path(leaves, ext, open_set, cur)
+            f2 = path_stats(leaves, ext, nxt, open_set)["flops"]
+            cur = nxt
+            if not f2 < fl:
+                break
+            fl = f2
+        cands.append(cur)
     best = None
     for i, p in enumerate(cands):
         try:
