@@ -183,7 +183,8 @@ typedef struct {
  * (creation order) the frontier of its subtree grows to at most 8 tensors by
  * expanding the internal frontier node of largest result size (ties:
  * smallest id), and the flop-optimal order of that frontier (exact search
- * over subsets) replaces the subtree when strictly cheaper.  The plain
+ * over subsets) replaces the subtree when strictly cheaper; passes repeat
+ * (at most 8) until one no longer lowers the tree's flops.  The plain
  * greedy path and the trials are each sliced to the budget and the lowest
  * (total flops, peak, index) wins.  Host only.
  * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */

@@ -575,6 +575,7 @@ std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t*
 // of that frontier (exact search over subsets, flops 8*size(A u B) per step,
 // kept labels = the node's result) replaces the subtree when it is cheaper.
 constexpr int kReconf = 8;
+constexpr int kReconfPasses = 8;   // passes until one no longer lowers the flops
 
 std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
                                                   const std::vector<std::pair<int, int>>& path) {
@@ -738,7 +739,18 @@ std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_
   parallel_for(trials, [&](int r) {
     uint64_t gs = seed + uint64_t(r) * 0x9E3779B97F4A7C15ull;
     uint64_t st = splitmix64_next(&gs);
-    paths[r + 1] = reconfigure_path(pr, partition_path(pr, &st));
+    {
+      auto cur = partition_path(pr, &st);
+      double fl = path_stats(pr, cur, {}).flops;
+      for (int pass = 0; pass < kReconfPasses; ++pass) {
+        auto nxt = reconfigure_path(pr, cur);
+        const double f2 = path_stats(pr, nxt, {}).flops;
+        cur = std::move(nxt);
+        if (!(f2 < fl)) break;
+        fl = f2;
+      }
+      paths[r + 1] = std::move(cur);
+    }
     score(r + 1);
   });
   int win = -1;
