@@ -1126,13 +1126,13 @@ __global__ __launch_bounds__(256) void reduce_splitk_kernel(const float2* __rest
                                                             float2* __restrict__ C, int ksplit,
                                                             int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    float2 s = part[i];
-    for (int k = 1; k < ksplit; ++k) {
+    double sx = 0.0, sy = 0.0;     // FP64: up to 32768 partials per entry
+    for (int k = 0; k < ksplit; ++k) {
       const float2 v = part[int64_t(k) * n + i];
-      s.x += v.x;
-      s.y += v.y;
+      sx += v.x;
+      sy += v.y;
     }
-    C[i] = s;
+    C[i] = make_float2(float(sx), float(sy));
   }
 }
 
@@ -1182,6 +1182,12 @@ int choose_ksplit(const GemmDesc& g, int id, int64_t* kchunk) {
   const int64_t minsteps = g.packed ? 8 : 16;
   int ks = 1;
   while (tiles * ks < 1024 && ksteps / (ks * 2) >= minsteps && ks < 256) ks *= 2;
+  // once split, keep every block's FP32 chain within kAccChunk complex k
+  // (few-tile GEMMs with very long K), up to 32768 splits per launch
+  if (ks > 1)
+    while (ceil_div(ksteps, ks) * bk > kAccChunk && ksteps / (ks * 2) >= minsteps &&
+           g.batch * ks * 2 <= 32768)
+      ks *= 2;
   *kchunk = ceil_div(ksteps, ks) * bk;
   return int(ceil_div(g.K, *kchunk));
 }
