@@ -560,7 +560,7 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
           r[1] = int64_t(1) << op.ap.nn;
           r[2] = int64_t(1) << op.ap.nk;
         } else if (op.kind == OP_DOT) {
-          r[2] = op.dot_k; r[3] = op.dot_batch;
+          r[2] = op.dot_k; r[3] = op.dot_batch * op.dot_m * op.dot_n;
         } else {
           r[0] = int64_t(1) << op.pm.nb;
         }

@@ -1384,11 +1384,13 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
 
 __global__ __launch_bounds__(256) void dot_partial_kernel(const float2* __restrict__ A,
                                                           const float2* __restrict__ B,
-                                                          double2* __restrict__ part, int64_t K) {
+                                                          double2* __restrict__ part, int64_t K,
+                                                          int64_t m, int64_t n) {
   __shared__ double2 red[256];
-  const int64_t b = blockIdx.y;
-  const float2* a = A + b * K;
-  const float2* bb = B + b * K;
+  const int64_t b = blockIdx.y;                 // output (batch, row of A, row of B)
+  const int64_t bi = b / (m * n), mi = (b / n) % m, ni = b % n;
+  const float2* a = A + (bi * m + mi) * K;
+  const float2* bb = B + (bi * n + ni) * K;
   double sr = 0.0, si = 0.0;
   for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < K; k += int64_t(gridDim.x) * 256) {
     const float2 x = a[k], y = bb[k];
@@ -1425,15 +1427,17 @@ size_t dot_workspace_bytes(int64_t K, int64_t batch) {
   return size_t(dot_parts(K)) * size_t(batch) * sizeof(double2);
 }
 
-void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, void* work,
-                hipStream_t s) {
+void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, int64_t m,
+                int64_t n, void* work, hipStream_t s) {
   TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "dot needs workspace");
-  TN_REQUIRE(batch <= 65535, TN_ERR_UNSUPPORTED, "dot batch too large");
+  TN_REQUIRE(m >= 1 && n >= 1, TN_ERR_ARG, "dot row counts must be positive");
+  const int64_t outs = batch * m * n;
+  TN_REQUIRE(outs <= 65535, TN_ERR_UNSUPPORTED, "dot batch too large");
   const int parts = dot_parts(K);
-  dot_partial_kernel<<<dim3(parts, unsigned(batch)), 256, 0, s>>>(A, B, static_cast<double2*>(work), K);
+  dot_partial_kernel<<<dim3(parts, unsigned(outs)), 256, 0, s>>>(A, B, static_cast<double2*>(work), K, m, n);
   TN_HIP(hipGetLastError());
-  dot_final_kernel<<<dim3(unsigned(ceil_div(batch, 256))), 256, 0, s>>>(static_cast<double2*>(work), C,
-                                                                       parts, batch);
+  dot_final_kernel<<<dim3(unsigned(ceil_div(outs, 256))), 256, 0, s>>>(static_cast<double2*>(work), C,
+                                                                      parts, outs);
   TN_HIP(hipGetLastError());
 }
 

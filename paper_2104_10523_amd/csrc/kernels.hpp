@@ -104,8 +104,10 @@ void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* p
 
 // Dot products (M = N = 1) with split-K; result written as complex64.
 size_t dot_workspace_bytes(int64_t K, int64_t batch);
-void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, void* work,
-                hipStream_t s);
+// C[b][m][n] = sum_k A[b][m][k] B[b][n][k] (complex, FP64 accumulation);
+// m = n = 1 is the plain batched dot.
+void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, int64_t m,
+                int64_t n, void* work, hipStream_t s);
 
 // Sets *flag to 1 if any entry of x is non-finite.
 void launch_nonfinite(const double2* x, int64_t n, int* flag, hipStream_t s);

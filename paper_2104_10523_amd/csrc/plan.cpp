@@ -309,7 +309,11 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   // of one plane (4 bytes per entry) must stay below 2 GiB, so K <= 2^20;
   // longer contractions run on the FP32 kernel at every precision
   const bool long_k = Kn > (int64_t(1) << 20);
-  const bool packable = Kn % 4 == 0 && !long_k && !(Mn == 1 && Nn == 1);
+  // a few outputs over a long contraction: one FP64-accumulated dot product
+  // per (m, n) pair of k-contiguous rows (an MFMA tile would mostly idle)
+  const bool dot_mn = !(Mn == 1 && Nn == 1) && Mn * Nn <= 16 && Kn >= (int64_t(1) << 16) &&
+                      Bn * Mn * Nn <= 4096;
+  const bool packable = Kn % 4 == 0 && !long_k && !dot_mn && !(Mn == 1 && Nn == 1);
   if (long_k) prec = TN_PREC_FP32;
   // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
   if (prec == TN_PREC_F16X3 && !packable) prec = TN_PREC_FP32;
@@ -325,6 +329,10 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     const auto fa = cat({b_o, k_o});
     if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
     if (B.labels != fa) Bp = emit_permute(B, fa, arena, ops, scratch);
+  } else if (dot_mn) {
+    const auto fa = cat({b_o, m_o, k_o}), fb = cat({b_o, n_o, k_o});
+    if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
+    if (B.labels != fb) Bp = emit_permute(B, fb, arena, ops, scratch);
   } else {
     const auto fa0 = cat({b_o, m_o, k_o}), fa1 = cat({b_o, k_o, m_o});
     if (A.labels == fa0) transA = 0;
@@ -358,11 +366,13 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   op.b_off = Bp.off;
   op.c_buf = out.buf;
   op.c_off = out.off;
-  if (Mn == 1 && Nn == 1) {
+  if ((Mn == 1 && Nn == 1) || dot_mn) {
     op.kind = OP_DOT;
     op.dot_k = Kn;
     op.dot_batch = Bn;
-    op.work_elems = int64_t((dot_workspace_bytes(Kn, Bn) + 7) / 8);
+    op.dot_m = Mn;
+    op.dot_n = Nn;
+    op.work_elems = int64_t((dot_workspace_bytes(Kn, Bn * Mn * Nn) + 7) / 8);
     op.work_off = arena.alloc(op.work_elems);
     scratch->push_back(op.work_off);
   } else {
@@ -417,7 +427,7 @@ void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t 
       case OP_APPLY: launch_apply_small(a, b, c, op.ap, s); break;
       case OP_PERMUTE: launch_permute(a, c, op.pm, slot(bufs, op.smax), s); break;
       case OP_GEMM: launch_gemm(a, b, c, op.gm, w, slot(bufs, op.smax_a), slot(bufs, op.smax_b), s); break;
-      case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, w, s); break;
+      case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, op.dot_m, op.dot_n, w, s); break;
     }
   }
 }

@@ -35,6 +35,7 @@ struct PlanOp {
   PermuteDesc pm;
   GemmDesc gm;
   int64_t dot_k = 0, dot_batch = 0;
+  int64_t dot_m = 1, dot_n = 1;   // DOT over all (m, n) row pairs of [b][m][k] x [b][n][k]
   double flops = 0, bytes = 0;
 };
 

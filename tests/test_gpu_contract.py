@@ -72,6 +72,8 @@ CASES = [
     ("gemm_n32", dict(nm=10, nk=8, nn=5)),
     ("gemm_splitk", dict(nm=6, nk=14, nn=6)),
     ("gemm_k_beyond_packed_panels", dict(nm=2, nk=21, nn=2)),   # K = 2^21: packed planes would overflow
+    ("dot_small_mn", dict(nm=2, nk=17, nn=2)),          # 4 x 4 outputs, K = 2^17: dot per (m, n) pair
+    ("dot_small_mn_batch", dict(nb=2, nm=1, nk=16, nn=3)),
     ("gemm_batch", dict(nb=3, nm=7, nk=6, nn=6)),
     ("gemm_wide_extents", dict(nm=5, nk=3, nn=6, wide=8)),
     ("outer_product", dict(nm=8, nk=0, nn=6)),
