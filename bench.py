@@ -42,6 +42,8 @@ UNPACKED_TILES = {0: (256, 16), 1: (128, 32), 2: (128, 64), 3: (64, 64)}
 
 
 def kernel_name(precision, tile, packed):
+    if precision == "auto":       # packed GEMMs run split FP16x3, the others FP32
+        precision = "f16x3" if packed else "fp32"
     if packed:
         np_ = 3 if precision == "bf16x6" else 2
         bm, bn, bk, wm, wn = PACKED_TILES[np_][tile]
@@ -75,7 +77,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="f16x3", choices=["bf16x3", "bf16x6", "f16x3", "fp32", "auto"])
+    ap.add_argument("--precision", default="auto", choices=["bf16x3", "bf16x6", "f16x3", "fp32", "auto"],
+                    help="auto: scaled split-FP16x3 for GEMMs with K >= 64, M >= 1024, N >= 64, FP32 otherwise")
     ap.add_argument("--compare-fp32", type=int, default=1, help="also time FP32 steps")
     ap.add_argument("--budget-gib", type=float, default=160.0)
     ap.add_argument("--trials", type=int, default=1024, help="path search trials")
@@ -660,7 +663,9 @@ def main():
     g_flops = float(fl[sel].sum()) * a.steps
     g_time = float(op_sec[sel].sum())
     g_bytes = float(by[sel].sum()) * a.steps
-    peak = PEAKS[a.precision] if a.precision in PEAKS else PEAKS["bf16x3"]
+    # MFMA peak of the dominant kernel's own arithmetic (packed split-16-bit or FP32)
+    peak = PEAKS["fp32"] if dom.startswith("gemm_mfma_kernel") and dom.endswith("fp32>") else \
+        (PEAKS[a.precision] if a.precision in PEAKS else PEAKS["f16x3"])
     traffic, traffic_src = recorded_traffic(dom)
     achieved = g_flops / g_time if g_time > 0 else 0.0
     # the bound follows the kernel's algorithmic intensity: below the
@@ -717,7 +722,9 @@ def main():
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16x3-split c64, fp32 accumulate", "bf16x6": "bf16x6-split c64, fp32 accumulate",
                   "f16x3": "scaled f16x3-split c64, fp32 accumulate",
-                  "fp32": "c64 fp32", "auto": "c64 auto"}[a.precision],
+                  "fp32": "c64 fp32",
+                  "auto": "c64: scaled f16x3-split MFMA for large GEMMs, fp32 MFMA otherwise, "
+                          "fp32 accumulate"}[a.precision],
         "data": "synthetic",
         "config": {"workload": f"{a.rows}x{a.cols} grid random circuit, {a.cycles} cycles, fSim(pi/2,pi/6), "
                                f"64 bit-strings, {'recursive-bisection' if a.path == 'partition' else 'randomised-greedy'} "

@@ -39,7 +39,7 @@ def identity_coupled():
     return n, ops, net, tn.tn_find_path(net, "partition", **PATH_OPTS)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3", "auto"])
 def test_rqc_7x7_14_full_size_slices(gpu, workspace, identity_coupled, precision):
     import torch
     import paper_2104_10523_amd as tn
