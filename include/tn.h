@@ -272,8 +272,11 @@ enum { TN_C64 = 0, TN_C128 = 1 };
  * a power of two chosen from its largest entry (so it spans [2^14, 2^15)),
  * split as hi + lo fp16, three products, FP32 accumulation, scales undone
  * exactly (about 2^-21 relative per GEMM at the speed of BF16X3).  AUTO: the
- * library picks per contraction (F16X3 for large contractions, FP32
- * elsewhere). */
+ * library picks per contraction: F16X3 when K >= 64, M >= 1024 and N >= 64,
+ * FP32 elsewhere.  At every precision, a contraction longer than 2^20 runs on
+ * the FP32 kernel (split-K chains of at most 4096, partials summed in FP64),
+ * and one with at most 16 outputs per batch entry and K >= 2^16 as FP64
+ * dot products. */
 enum { TN_PREC_FP32 = 0, TN_PREC_BF16X3 = 1, TN_PREC_BF16X6 = 2,
        TN_PREC_AUTO = 3, TN_PREC_F16X3 = 4 };
 
