@@ -482,6 +482,15 @@ tn_status tn_mps_apply_gate(tn_mps* m, int32_t site, const double* gate,
                             double* discarded, void* stream);
 /* Bond dimensions (n_sites - 1 ints, host). */
 tn_status tn_mps_bond_dims(const tn_mps* m, int32_t* dims);
+/* Singular values of bond `bond` (between sites bond and bond+1) from the
+ * last two-qubit gate on that bond (Sec. 3.2: the kept values of its SVD
+ * after truncation and renormalisation to unit norm, descending; {1} before
+ * any gate).  *count receives their number; `values` (host, may be NULL to
+ * query the count) must hold `capacity` >= count doubles.  Gates on other
+ * bonds after that one do not update it.  Host only.
+ * Errors: TN_ERR_ARG, TN_ERR_SITE. */
+tn_status tn_mps_bond_spectrum(const tn_mps* m, int32_t bond, double* values,
+                               int32_t capacity, int32_t* count);
 /* <Z_i> for every site (host array of n_sites doubles).  Synchronises. */
 tn_status tn_mps_expect_z(tn_mps* m, double* out, void* stream);
 /* Amplitudes of n_bs 0/1 bit-strings (host int8 n_bs x n_sites) into host

@@ -27,6 +27,7 @@ singular-value weight (Eckart-Young); the norm stays 1.
 
 from __future__ import annotations
 
+import math
 from typing import List
 
 import numpy as np
@@ -43,6 +44,11 @@ class MPS:
             A[0, 0, 0] = 1.0
             self.sites.append(A)
         self.center = 0
+        # bond i: kept, renormalised singular values of its last SVD, and
+        # per two-qubit gate the relative gap s_keep / s_(keep+1) - 1 at the
+        # truncation cut (inf when nothing was cut)
+        self.spectra: List[np.ndarray] = [np.ones(1) for _ in range(n - 1)]
+        self.cut_gaps: List[float] = []
 
     # ---------------------------------------------------------------- gauge
     def _move_right(self, c: int):
@@ -91,6 +97,8 @@ class MPS:
         kept = float(np.sum(S[:keep] ** 2))
         discarded = (total - kept) / total if total > 0 else 0.0
         Sk = S[:keep] / np.sqrt(kept)
+        self.spectra[site] = Sk.copy()
+        self.cut_gaps.append(float(S[keep - 1] / S[keep] - 1.0) if keep < S.size and S[keep] > 0 else math.inf)
         if right:
             self.sites[site] = Um[:, :keep].reshape(l, 2, keep)
             self.sites[site + 1] = (Sk[:, None] * Vh[:keep]).reshape(keep, 2, r)
@@ -116,16 +124,16 @@ class MPS:
         n = self.n
         Ls = [np.ones((1, 1), dtype=np.complex128)]
         for A in self.sites:
-            Ls.append(np.einsum("ab,asr,bst->rt", Ls[-1], A.conj(), A))
+            Ls.append(np.einsum("ab,asr,bst->rt", Ls[-1], A.conj(), A, optimize=True))
         Rs = [np.ones((1, 1), dtype=np.complex128)]
         for A in reversed(self.sites):
-            Rs.append(np.einsum("asr,bst,rt->ab", A.conj(), A, Rs[-1]))
+            Rs.append(np.einsum("asr,bst,rt->ab", A.conj(), A, Rs[-1], optimize=True))
         Rs = Rs[::-1]
         norm = Ls[-1][0, 0].real
         z = np.empty(n)
         zsign = np.array([1.0, -1.0])
         for i, A in enumerate(self.sites):
-            z[i] = np.einsum("ab,asr,bst,rt,s->", Ls[i], A.conj(), A, Rs[i + 1], zsign).real / norm
+            z[i] = np.einsum("ab,asr,bst,rt,s->", Ls[i], A.conj(), A, Rs[i + 1], zsign, optimize=True).real / norm
         return z
 
     def to_statevector(self) -> np.ndarray:

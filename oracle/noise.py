@@ -53,8 +53,11 @@ def dm_expect_z(rho: np.ndarray, n: int) -> np.ndarray:
     return z
 
 
-def trajectory(n: int, ops, uniforms) -> tuple:
-    """One trajectory: returns (final normalised state, branch list)."""
+def trajectory(n: int, ops, uniforms, margins: list | None = None) -> tuple:
+    """One trajectory: returns (final normalised state, branch list).  If
+    `margins` is a list, the distance of each event's uniform from the
+    nearest cumulative-probability boundary is appended to it (a small
+    margin means a lower-precision run may pick the neighbouring branch)."""
     psi = np.zeros((2,) * n, dtype=np.complex128)
     psi[(0,) * n] = 1.0
     e = 0
@@ -75,6 +78,9 @@ def trajectory(n: int, ops, uniforms) -> tuple:
             if u < acc:
                 k = i
                 break
+        if margins is not None:
+            cdf = np.cumsum(probs)[:-1]
+            margins.append(float(np.min(np.abs(u - cdf))) if cdf.size else 1.0)
         branches.append(k)
         psi = cands[k] / np.sqrt(probs[k] * norm2)
     return psi, branches

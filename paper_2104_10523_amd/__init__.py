@@ -14,7 +14,7 @@ from typing import Iterable, List, Optional, Sequence
 import numpy as np
 
 from ._native import (GATE_IDS, PATH_ALGO, PAULI, PREC, TnCircuit, TnExecOpts, TnNetworkInfo, TnOp,
-                      TnPathCost, TnPathOpts, TnReport, TnTensor, TnError, check, lib)
+                      TnPathCost, TnPathOpts, TnPlanInfo, TnReport, TnTensor, TnError, check, lib)
 
 __all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
            "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
@@ -200,6 +200,25 @@ def tn_amplitudes_autotune(net: Network, path: Path, precision: str = "fp32", re
                                        C.c_void_p(_stream_ptr(stream))))
 
 
+def tn_amplitudes_plan_info(net: Network, path: Path, precision: str = "fp32"):
+    """Summary of one job's kernel sequence (a TnPlanInfo struct)."""
+    info = TnPlanInfo()
+    check(lib().tn_amplitudes_plan_info(net.h, path.h, PREC[precision], C.byref(info)))
+    return info
+
+
+def tn_amplitudes_plan_ops(net: Network, path: Path, precision: str = "fp32"):
+    """Per-op detail of one job: (kind, flops, bytes, shape) numpy arrays,
+    shape n_ops x 8 (m, n, k, batch, block-tile id, packed, launches, 0)."""
+    n_ops = tn_amplitudes_plan_info(net, path, precision).n_ops
+    kind = (C.c_int32 * n_ops)()
+    fl = (C.c_double * n_ops)()
+    by = (C.c_double * n_ops)()
+    shape = (C.c_int64 * (8 * n_ops))()
+    check(lib().tn_amplitudes_plan_ops(net.h, path.h, PREC[precision], kind, fl, by, shape))
+    return (np.array(kind), np.array(fl), np.array(by), np.array(shape).reshape(n_ops, 8))
+
+
 def tn_amplitudes(net: Network, path: Path, bits, out=None, precision: str = "fp32",
                   use_graph: bool = False, slice_begin: int = 0, slice_count: int = -1,
                   accumulate: bool = False, sync: bool = True, stream=None):
@@ -320,6 +339,15 @@ class Mps:
         out = (C.c_int32 * max(self.n - 1, 1))()
         check(lib().tn_mps_bond_dims(self.h, out))
         return list(out)[:self.n - 1]
+
+    def bond_spectrum(self, bond: int) -> np.ndarray:
+        """Kept, renormalised singular values of the last gate on `bond`."""
+        cnt = C.c_int32()
+        check(lib().tn_mps_bond_spectrum(self.h, int(bond), None, 0, C.byref(cnt)))
+        out = np.zeros(max(cnt.value, 1))
+        check(lib().tn_mps_bond_spectrum(self.h, int(bond), out.ctypes.data_as(C.POINTER(C.c_double)),
+                                         cnt.value, C.byref(cnt)))
+        return out[:cnt.value]
 
     def expect_z(self, stream=None) -> np.ndarray:
         out = np.zeros(self.n)

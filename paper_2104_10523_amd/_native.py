@@ -109,6 +109,7 @@ SIGNATURES = {
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),
     "tn_mps_apply_gate": (I32, [P, I32, PD, I32, D, PD, P]),
     "tn_mps_bond_dims": (I32, [P, PI32]),
+    "tn_mps_bond_spectrum": (I32, [P, I32, PD, I32, PI32]),
     "tn_mps_expect_z": (I32, [P, PD, P]),
     "tn_mps_amplitudes": (I32, [P, PI8, I64, PD, P]),
     "tn_run_trajectories": (I32, [C.POINTER(C.POINTER(TnCircuit)), I32, I32, PD, I64, PD,

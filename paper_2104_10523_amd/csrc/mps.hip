@@ -437,6 +437,7 @@ using namespace tn;
 struct tn_mps {
   int n = 0, cmax = 0, center = 0, dev = 0;
   std::vector<int> chi;            // bond i between sites i and i+1
+  std::vector<std::vector<double>> spec;   // bond i: kept, renormalised values of its last SVD
   std::vector<float2*> site;       // capacity cmax * 2 * cmax each
   float2* theta = nullptr;         // (2 cmax) x (2 cmax) complex64
   float2* tmp = nullptr;           // site-sized scratch
@@ -578,6 +579,7 @@ tn_status tn_mps_create(int32_t n_sites, int32_t chi_max, void* stream, tn_mps**
     m->cmax = chi_max;
     TN_HIP(hipGetDevice(&m->dev));
     m->chi.assign(n_sites - 1, 1);
+    m->spec.assign(n_sites - 1, std::vector<double>(1, 1.0));
     const size_t cap = size_t(chi_max) * 2 * chi_max;
     const size_t big = size_t(2 * chi_max) * size_t(2 * chi_max);
     for (int i = 0; i < n_sites; ++i) {
@@ -614,6 +616,18 @@ tn_status tn_mps_bond_dims(const tn_mps* m, int32_t* dims) {
   return guarded([&] {
     TN_REQUIRE(m && dims, TN_ERR_ARG, "null argument");
     for (int i = 0; i < m->n - 1; ++i) dims[i] = m->chi[i];
+  });
+}
+
+tn_status tn_mps_bond_spectrum(const tn_mps* m, int32_t bond, double* values, int32_t capacity,
+                                int32_t* count) {
+  return guarded([&] {
+    TN_REQUIRE(m && count, TN_ERR_ARG, "null argument");
+    TN_REQUIRE(bond >= 0 && bond < m->n - 1, TN_ERR_SITE, "bond out of range");
+    const auto& v = m->spec[bond];
+    *count = int32_t(v.size());
+    TN_REQUIRE(values == nullptr || capacity >= int32_t(v.size()), TN_ERR_ARG, "capacity below the bond dimension");
+    if (values) std::copy(v.begin(), v.end(), values);
   });
 }
 
@@ -701,6 +715,8 @@ tn_status tn_mps_apply_gate(tn_mps* m, int32_t site, const double* gate, int32_t
     TN_HIP(hipStreamSynchronize(s));
     (void)hipEventDestroy(ev);
     m->chi[site] = keep;
+    m->spec[site].resize(keep);
+    for (int k = 0; k < keep; ++k) m->spec[site][k] = S[order[k]] * scale;
     m->center = right ? site + 1 : site;
   });
 }

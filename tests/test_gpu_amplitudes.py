@@ -149,3 +149,46 @@ def test_autotuned_plan_keeps_parity(gpu, workspace):
         tn.tn_amplitudes_autotune(net, path, prec, reps=1)
         got, _ = tn.tn_amplitudes(net, path, bits, precision=prec)
         check_amps(got.cpu().numpy()[0], ref, n, tol=1e-5 if prec == "fp32" else 1e-4)
+
+
+@pytest.fixture(scope="module")
+def rqc_4x5_14():
+    """Random fSim(pi/2, pi/6) grid circuit (the benchmark's gate family) on
+    4x5 qubits, 14 cycles, every output leg open; the state-vector oracle
+    gives all 2^20 amplitudes."""
+    n, ops = grid_random_circuit(4, 5, 14, 2, two_qubit="fsim")
+    return n, ops, sv.simulate(n, ops).reshape(-1)
+
+
+@pytest.mark.parametrize("precision", ["auto", "f16x3", "fp32", "bf16x3"])
+def test_random_fsim_circuit_through_the_large_gemm_kernel(gpu, workspace, rqc_4x5_14, precision):
+    """The greedy plan of this circuit runs six GEMMs on the direct-to-LDS
+    256x128 split kernel (block tile 5; e.g. 65536 x 1024 x 256) at auto and
+    f16x3, so a random circuit's amplitudes reach the benchmark's large-GEMM
+    kernel.  Bound: 1e-5 floored and L2 (split-BF16x3: 4x its a-priori
+    estimate, 16 significant bits)."""
+    import paper_2104_10523_amd as tn
+    n, ops, ref = rqc_4x5_14
+    net = tn.tn_build_network(n, ops)
+    path = tn.tn_find_path(net, "greedy", open_mask=[1] * n)
+    kind, _, _, shape = tn.tn_amplitudes_plan_ops(net, path, precision)
+    tiles = shape[kind == 2][:, 4]
+    n_dma = int(np.sum(tiles == 5))
+    print(f"{precision}: {int(np.sum(kind == 2))} GEMMs, {n_dma} on the direct-to-LDS kernel", flush=True)
+    if precision in ("auto", "f16x3", "bf16x3"):
+        assert n_dma >= 6
+    import torch
+    big = torch.empty(tn.tn_amplitudes_workspace(net, path, 1, precision), dtype=torch.uint8, device=gpu)
+    tn.tn_set_workspace(big)
+    try:
+        out, rep = tn.tn_amplitudes(net, path, np.full((1, n), -1, np.int8), precision=precision)
+        got = out.cpu().numpy()[0]
+    finally:
+        tn.tn_set_workspace(workspace)
+        del big
+    assert rep.nonfinite == 0
+    e1 = floored_rel(got, ref, 2.0 ** (-n / 2))
+    e2 = l2_rel(got, ref)
+    tol = 4 * rep.err_bound if precision == "bf16x3" else 1e-5
+    print(f"{precision}: floored {e1:.2e} l2 {e2:.2e} (estimate {rep.err_bound:.1e})", flush=True)
+    assert e1 <= tol and e2 <= tol, (e1, e2, tol)

@@ -55,6 +55,50 @@ def test_mps_truncated_matches_oracle(gpu):
     assert np.abs(m.expect_z() - ref.expect_z()).max() <= 1e-4
 
 
+@pytest.mark.timeout(400)
+def test_c42_full_size_matches_oracle(gpu):
+    """The MPS row's workload at full size: 40-site chain, 20 cycles of
+    fSim(pi/2, pi/6) on alternating bonds, chi_max 256, cutoff 1e-12, against
+    the complex128 MPS oracle (O5) gate by gate.  Compared: bond dimensions,
+    the cumulative discarded weight, the last spectrum of every bond, <Z_i>
+    and 16 amplitudes.  Truncated cuts whose singular values are degenerate
+    (relative gap below 1e-10) would make the kept subspace ambiguous; the
+    oracle reports their gaps, and none occurs here."""
+    n, ops = chain_random_circuit(40, 20, 5)
+    chi = 256
+    ref, dref = run_circuit(n, ops, chi_max=chi)
+    gaps = np.array(ref.cut_gaps)
+    print(f"oracle: {len(gaps)} gates, smallest cut gap {gaps.min():.2e}, discarded {dref:.6f}", flush=True)
+    assert gaps.min() > 1e-10
+    m, d = gpu_run(n, ops, chi_max=chi)
+    assert m.bond_dims() == ref.bond_dims()
+    assert max(m.bond_dims()) == chi
+    ed = abs(d - dref) / dref
+    es = max(float(np.abs(m.bond_spectrum(b) - ref.spectra[b]).max()) for b in range(n - 1))
+    ez = float(np.abs(m.expect_z() - ref.expect_z()).max())
+    rng = np.random.default_rng(6)
+    bits = rng.integers(0, 2, size=(16, n)).astype(np.int8)
+    got = m.amplitudes(bits)
+    want = np.array([ref.amplitude(b) for b in bits])
+    ea = float(np.abs(got - want).max() / np.sqrt(np.mean(np.abs(want) ** 2)))
+    print(f"discarded rel {ed:.2e}, spectra {es:.2e}, <Z> {ez:.2e}, amplitudes (rel to rms) {ea:.2e}", flush=True)
+    # complex64 sites and FP32 theta perturb each gate by ~1e-7; the kept
+    # singular vectors at a cut with relative gap g rotate by ~1e-7 / g
+    # (smallest gap here 5e-4), which individual amplitudes feel most
+    assert ed <= 1e-6 and es <= 1e-5 and ez <= 1e-5 and ea <= 2e-3
+
+
+def test_mps_bond_spectrum_matches_oracle(gpu):
+    n, ops = chain_random_circuit(12, 8, 4)
+    ref, _ = run_circuit(n, ops, chi_max=8)
+    m, _ = gpu_run(n, ops, chi_max=8)
+    for b in range(n - 1):
+        s = m.bond_spectrum(b)
+        assert s.shape == ref.spectra[b].shape
+        assert np.abs(s - ref.spectra[b]).max() <= 1e-5
+        assert abs(np.sum(s ** 2) - 1) <= 1e-12
+
+
 def test_mps_errors(gpu):
     import paper_2104_10523_amd as tn
     m = tn.tn_mps_create(4, 4)
@@ -64,3 +108,5 @@ def test_mps_errors(gpu):
         tn.tn_mps_apply_gate(m, 0, np.eye(4), 0)
     with pytest.raises(tn.TnError, match="ARG"):
         tn.tn_mps_create(1, 4)
+    with pytest.raises(tn.TnError, match="SITE"):
+        m.bond_spectrum(3)

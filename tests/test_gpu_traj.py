@@ -87,3 +87,54 @@ def test_trajectories_wide_registers(gpu, rows, cols, depth):
     z, _ = run_gpu(circuits, tpc, U)
     zo = noise.trajectories_expect_z(circuits, tpc, U)
     assert np.abs(z - zo).max() <= 5e-5
+
+
+def _c41_ensemble():
+    """The trajectory row's ensemble: 32 circuits on a 4x5 grid (CZ) of
+    depth 10 + round(20 c / 31), depolarising 1e-3 / 1e-2 and damping 5e-3
+    after every gate, 32 trajectories each, uniforms from seed 4."""
+    circuits = []
+    for c in range(32):
+        n, ops = grid_random_circuit(4, 5, 10 + round(20 * c / 31), 40 + c)
+        circuits.append((n, noisy_ops(ops, 1e-3, 1e-2, 5e-3)))
+    ev = max(count_channel_events(o) for _, o in circuits)
+    return circuits, 32, trajectory_uniforms(32 * 32, ev, 4)
+
+
+@pytest.fixture(scope="module")
+def c41_run(gpu):
+    circuits, tpc, U = _c41_ensemble()
+    z, rep = run_gpu(circuits, tpc, U)
+    assert z.shape == (1024, 20)
+    return circuits, tpc, U, z
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("circ", [0, 31], ids=["depth10", "depth30"])
+def test_c41_full_size_trajectories_match_oracle(c41_run, circ):
+    """Full-size ensemble (1024 trajectories of 20 qubits in one call): the
+    first 4 trajectories of the depth-10 and of the depth-30 circuit against
+    the trajectory oracle on the same uniform rows.  A trajectory whose
+    uniforms all sit more than 1e-8 from a branch boundary must take the
+    oracle's branches (complex64 state, FP64 branch probabilities); its <Z_q>
+    then agrees to 1e-5 (the state carries ~1e-7 of complex64 rounding per
+    pass over ~10^3 passes, renormalised in FP64)."""
+    circuits, tpc, U, z = c41_run
+    n, ops = circuits[circ]
+    compared = 0
+    for j in range(4):
+        row = circ * tpc + j
+        margins = []
+        psi, _ = noise.trajectory(n, ops, U[row], margins)
+        zo = sv_expect_z(psi)
+        err = float(np.abs(z[row] - zo).max())
+        print(f"circuit {circ} trajectory {j}: min margin {min(margins):.2e} max |dZ| {err:.2e}", flush=True)
+        if min(margins) > 1e-8:
+            assert err <= 1e-5, (circ, j, err)
+            compared += 1
+    assert compared >= 3
+
+
+def sv_expect_z(psi):
+    from oracle.statevector import expect_z
+    return expect_z(psi)

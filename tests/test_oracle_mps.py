@@ -41,3 +41,20 @@ def test_single_truncation_eckart_young():
     assert abs(overlap - (1 - disc)) <= 1e-12
     assert abs(np.linalg.norm(after) - 1) <= 1e-12
     assert m.bond_dims()[3] == chi
+
+
+@pytest.mark.parametrize("n,cyc", [(8, 5), (10, 6)])
+def test_untruncated_bond_spectra_are_schmidt_coefficients(n, cyc):
+    """Without truncation the recorded spectrum of every bond is the list of
+    Schmidt coefficients of the final state across that cut (gates on other
+    bonds act unitarily on one side and leave them unchanged), found here by
+    an SVD of the state vector reshaped to 2^(b+1) x 2^(n-b-1)."""
+    _, ops = chain_random_circuit(n, cyc, 40 + n)
+    m, _ = run_circuit(n, ops, chi_max=1 << (n // 2), cutoff=1e-13)
+    psi = sv.simulate(n, ops)
+    for b in range(n - 1):
+        s = np.linalg.svd(psi.reshape(2 ** (b + 1), -1), compute_uv=False)
+        s = s[s > 1e-13 * s[0]]
+        assert m.spectra[b].shape == s.shape, (b, m.spectra[b].shape, s.shape)
+        assert np.abs(m.spectra[b] - s).max() <= 1e-12
+    assert all(g == np.inf or g > 0 for g in m.cut_gaps)
