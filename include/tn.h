@@ -306,6 +306,25 @@ tn_status tn_contract_pair(const tn_tensor* A, const int32_t* modesA,
                            tn_tensor* C, const int32_t* modesC,
                            int32_t precision, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * contraction, same arguments, kernels and results as tn_contract_pair, but
+ * its scratch (permuted operands, split-precision planes and scale slots,
+ * split-K partials) comes from a fixed 64 MiB device array inside the
+ * library instead of tn_set_workspace.  The call allocates nothing: no
+ * hipMalloc or hipFree, on the first call on a device included (each GPU
+ * holds its own copy of the array from the library's load until the
+ * process ends).  Every call on one GPU shares that array and leaves its
+ * contents behind, so calls that overlap on one device (different streams
+ * or threads, without ordering between them) race; calls ordered on one
+ * stream are safe.
+ * Errors: as tn_contract_pair, plus TN_ERR_WORKSPACE when the contraction
+ * needs more than 64 MiB of scratch. */
+tn_status tn_contract_pair_noalloc(const tn_tensor* A, const int32_t* modesA,
+                                   const tn_tensor* B, const int32_t* modesB,
+                                   tn_tensor* C, const int32_t* modesC,
+                                   int32_t precision, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Amplitudes (Eq. 1; batches, Sec. 3.1; marginal slices, Sec. 4.4)       */
 /* ---------------------------------------------------------------------- */

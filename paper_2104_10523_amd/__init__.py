@@ -174,17 +174,21 @@ def _tensor(t, extents=None) -> tuple:
     return T, arr
 
 
-def tn_contract_pair(A, modesA, B, modesB, Cout, modesC, precision: str = "fp32", stream=None):
-    """Cout[modesC] = sum A[modesA] * B[modesB] (einsum semantics), on the GPU."""
+def tn_contract_pair(A, modesA, B, modesB, Cout, modesC, precision: str = "fp32", stream=None,
+                     noalloc: bool = False):
+    """Cout[modesC] = sum A[modesA] * B[modesB] (einsum semantics), on the GPU.
+    noalloc=True calls tn_contract_pair_noalloc (scratch inside the library,
+    at most 64 MiB, no workspace needed)."""
     TA, ka = _tensor(A)
     TB, kb = _tensor(B)
     TC, kc = _tensor(Cout)
     ma = (C.c_int32 * max(len(modesA), 1))(*modesA)
     mb = (C.c_int32 * max(len(modesB), 1))(*modesB)
     mc = (C.c_int32 * max(len(modesC), 1))(*modesC)
-    check(lib().tn_contract_pair(C.byref(TA), ma, C.byref(TB), mb, C.byref(TC), mc,
-                                 PREC[precision] if isinstance(precision, str) else int(precision),
-                                 C.c_void_p(_stream_ptr(stream))))
+    fn = lib().tn_contract_pair_noalloc if noalloc else lib().tn_contract_pair
+    check(fn(C.byref(TA), ma, C.byref(TB), mb, C.byref(TC), mc,
+             PREC[precision] if isinstance(precision, str) else int(precision),
+             C.c_void_p(_stream_ptr(stream))))
 
 
 def tn_amplitudes_workspace(net: Network, path: Path, n_bs: int, precision: str = "fp32") -> int:

@@ -95,6 +95,8 @@ SIGNATURES = {
     "tn_set_workspace": (I32, [P, C.c_size_t]),
     "tn_contract_pair": (I32, [C.POINTER(TnTensor), PI32, C.POINTER(TnTensor), PI32,
                                C.POINTER(TnTensor), PI32, I32, P]),
+    "tn_contract_pair_noalloc": (I32, [C.POINTER(TnTensor), PI32, C.POINTER(TnTensor), PI32,
+                                       C.POINTER(TnTensor), PI32, I32, P]),
     "tn_amplitudes": (I32, [P, P, PI8, I64, C.POINTER(TnExecOpts), P, C.POINTER(TnReport), P]),
     "tn_amplitudes_workspace": (I32, [P, P, I64, I32, C.POINTER(C.c_size_t)]),
     "tn_amplitudes_plan_info": (I32, [P, P, I32, C.POINTER(TnPlanInfo)]),

@@ -171,6 +171,46 @@ std::vector<int> bit_labels(const tn_tensor* T, const int32_t* modes, std::map<i
 
 }  // namespace
 
+namespace tn {
+
+PairPlan compile_contract_pair(const tn_tensor* A, const int32_t* modesA, const tn_tensor* B,
+                               const int32_t* modesB, const tn_tensor* C, const int32_t* modesC,
+                               int32_t precision) {
+  TN_REQUIRE(A && B && C, TN_ERR_ARG, "null tensor");
+  TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+  std::map<int32_t, int> ids;
+  std::map<int32_t, int64_t> ext;
+  TRef X, Y;
+  X.buf = BUF_EXT_A;
+  Y.buf = BUF_EXT_B;
+  X.labels = bit_labels(A, modesA, ids, ext);
+  Y.labels = bit_labels(B, modesB, ids, ext);
+  std::map<int32_t, int64_t> ext_in = ext;
+  std::map<int32_t, int> ids_in = ids;
+  // output labels must come from the inputs, with the same extents
+  for (int i = 0; i < C->rank; ++i)
+    TN_REQUIRE(modesC && ids_in.count(modesC[i]), TN_ERR_MODES, "output label not in A or B");
+  std::vector<int> want = bit_labels(C, modesC, ids, ext);
+  TN_REQUIRE(ids.size() == ids_in.size(), TN_ERR_MODES, "output label not in A or B");
+  for (auto& kv : ext_in) TN_REQUIRE(ext[kv.first] == kv.second, TN_ERR_EXTENT, "label extents differ");
+  TN_REQUIRE(A->data && B->data && C->data, TN_ERR_ARG, "null data pointer");
+  Arena arena;
+  PairPlan pp;
+  std::vector<int64_t> scratch;
+  compile_pair(X, Y, want, &want, BUF_EXT_C, 0, arena, precision, pp.ops, &scratch);
+  pp.scratch_bytes = size_t(arena.high_water()) * sizeof(float2);
+  return pp;
+}
+
+void run_contract_pair(const PairPlan& pp, const tn_tensor* A, const tn_tensor* B, tn_tensor* C, void* scratch,
+                       float2* one, hipStream_t stream) {
+  float2* bufs[6] = {nullptr, static_cast<float2*>(scratch), static_cast<float2*>(A->data),
+                     static_cast<float2*>(B->data), static_cast<float2*>(C->data), one};
+  run_ops(pp.ops, bufs, stream);
+}
+
+}  // namespace tn
+
 extern "C" {
 
 const char* tn_last_error(void) { return g_last_error.c_str(); }
@@ -291,35 +331,11 @@ tn_status tn_contract_pair(const tn_tensor* A, const int32_t* modesA, const tn_t
                            const int32_t* modesB, tn_tensor* C, const int32_t* modesC,
                            int32_t precision, void* stream) {
   return guarded([&] {
-    TN_REQUIRE(A && B && C, TN_ERR_ARG, "null tensor");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
-    std::map<int32_t, int> ids;
-    std::map<int32_t, int64_t> ext;
-    TRef X, Y;
-    X.buf = BUF_EXT_A;
-    Y.buf = BUF_EXT_B;
-    X.labels = bit_labels(A, modesA, ids, ext);
-    Y.labels = bit_labels(B, modesB, ids, ext);
-    std::map<int32_t, int64_t> ext_in = ext;
-    std::map<int32_t, int> ids_in = ids;
-    // output labels must come from the inputs, with the same extents
-    for (int i = 0; i < C->rank; ++i)
-      TN_REQUIRE(modesC && ids_in.count(modesC[i]), TN_ERR_MODES, "output label not in A or B");
-    std::vector<int> want = bit_labels(C, modesC, ids, ext);
-    TN_REQUIRE(ids.size() == ids_in.size(), TN_ERR_MODES, "output label not in A or B");
-    for (auto& kv : ext_in) TN_REQUIRE(ext[kv.first] == kv.second, TN_ERR_EXTENT, "label extents differ");
-    TN_REQUIRE(A->data && B->data && C->data, TN_ERR_ARG, "null data pointer");
-    Arena arena;
-    std::vector<PlanOp> ops;
-    std::vector<int64_t> scratch;
-    compile_pair(X, Y, want, &want, BUF_EXT_C, 0, arena, precision, ops, &scratch);
+    const PairPlan pp = compile_contract_pair(A, modesA, B, modesB, C, modesC, precision);
     const Workspace ws = get_ws();
-    const size_t need = size_t(arena.high_water()) * sizeof(float2);
-    TN_REQUIRE(need == 0 || (ws.ptr && ws.bytes >= need), TN_ERR_WORKSPACE,
-               "workspace too small: need " + std::to_string(need) + " bytes");
-    float2* bufs[6] = {nullptr, static_cast<float2*>(ws.ptr), static_cast<float2*>(A->data),
-                       static_cast<float2*>(B->data), static_cast<float2*>(C->data), device_one()};
-    run_ops(ops, bufs, static_cast<hipStream_t>(stream));
+    TN_REQUIRE(pp.scratch_bytes == 0 || (ws.ptr && ws.bytes >= pp.scratch_bytes), TN_ERR_WORKSPACE,
+               "workspace too small: need " + std::to_string(pp.scratch_bytes) + " bytes");
+    run_contract_pair(pp, A, B, C, ws.ptr, device_one(), static_cast<hipStream_t>(stream));
   });
 }
 

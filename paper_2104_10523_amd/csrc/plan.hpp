@@ -90,6 +90,22 @@ struct AmpPlan {
   int gemm_ops = 0;
 };
 
+// One pairwise contraction of caller-owned tensors (tn_contract_pair):
+// its kernel sequence and the scratch bytes that sequence needs.
+struct PairPlan {
+  std::vector<PlanOp> ops;
+  size_t scratch_bytes = 0;
+};
+// Validates labels, extents and dtypes (TN_ERR_MODES / _EXTENT / _ARG /
+// _UNSUPPORTED) and compiles the contraction; host only.
+PairPlan compile_contract_pair(const tn_tensor* A, const int32_t* modesA, const tn_tensor* B,
+                               const int32_t* modesB, const tn_tensor* C, const int32_t* modesC,
+                               int32_t precision);
+// Launches the compiled sequence on `stream`; `scratch` holds at least
+// scratch_bytes (256-byte aligned), `one` a device complex 1 + 0i.
+void run_contract_pair(const PairPlan& pp, const tn_tensor* A, const tn_tensor* B, tn_tensor* C, void* scratch,
+                       float2* one, hipStream_t stream);
+
 struct PathData;  // defined in api
 AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, int>>& path,
                            const std::vector<int>& sliced, const std::vector<char>& open_q,

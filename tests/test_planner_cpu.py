@@ -311,3 +311,31 @@ def test_partition_tree_contracts_to_the_amplitude():
         amp_r = complex(contract_path(tensors, labels, rt, []))
         assert abs(amp_r - sv.amplitudes(n, ops, bits)[0]) < 1e-12
     assert improved >= 1
+
+
+def test_noalloc_contract_pair_rejects_scratch_beyond_its_array():
+    """Host-side check of the allocation-free tn_contract_pair variant: a GEMM
+    whose 2^24-entry operand must be permuted needs 128 MiB of scratch, above
+    the fixed 64 MiB array, and is refused before any device call (the data
+    pointers are never dereferenced)."""
+    from paper_2104_10523_amd._native import TnTensor
+    TN_C64 = 0
+    rng = np.random.default_rng(0)
+    la = list(range(24))
+    rng.shuffle(la)                        # labels 0..13 free, 14..23 contracted
+    lb = list(range(14, 24)) + list(range(100, 106))
+    lc = list(range(14)) + list(range(100, 106))
+
+    def tensor(labels):
+        ext = (ctypes.c_int64 * len(labels))(*([2] * len(labels)))
+        return TnTensor(ctypes.c_void_p(0x1000), len(labels), TN_C64, ext), ext
+
+    (TA, ea), (TB, eb), (TC, ec) = tensor(la), tensor(lb), tensor(lc)
+    arr = lambda v: (ctypes.c_int32 * len(v))(*v)
+    code = tn.lib().tn_contract_pair_noalloc(ctypes.byref(TA), arr(la), ctypes.byref(TB), arr(lb),
+                                              ctypes.byref(TC), arr(lc), 0, None)
+    assert code != 0
+    msg = tn.lib().tn_last_error().decode()
+    assert "67108864" in msg and "needs" in msg, msg
+    with pytest.raises(tn.TnError, match="WORKSPACE"):
+        tn._native.check(code)
