@@ -10,8 +10,10 @@ job (64 bit-strings x 2^k slices) cannot run in minutes, so `value` is the
 whole-job amplitude rate extrapolated from the timed steps (every slice has
 the same shapes): amplitudes/s = 1 / (2^k x seconds per step).
 
-The dominant kernel is the complex MFMA GEMM; its roofline entry is
-computed from HIP events around every op of the timed steps.
+The timed region replays the job's captured hipGraph (the production path).
+A profiled pass after it times every op with HIP events; the kernel with the
+largest share of a step is the roofline entry (HBM-bound unless it is a GEMM
+whose intensity reaches the balance point of its own arithmetic).
 """
 
 from __future__ import annotations
@@ -55,7 +57,8 @@ def kernel_name(precision, tile, packed):
         precision = "fp32"        # split FP16 exists only on packed planes
     bk = 8 if precision == "fp32" else 16
     wm, wn = (2, 2) if bn >= 64 else (4, 1)
-    return f"gemm_mfma_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {precision}>"
+    prec_id = {"fp32": 0, "bf16x3": 1, "bf16x6": 2}[precision]      # TN_PREC_* template argument
+    return f"gemm_mfma_kernel<{bm}, {bn}, {bk}, {wm}, {wn}, {prec_id}>"
 
 
 def recorded_traffic(kernel):
@@ -84,13 +87,18 @@ def parse():
     ap.add_argument("--trials", type=int, default=1024, help="path search trials")
     ap.add_argument("--path", default="partition", choices=["partition", "random_greedy"],
                     help="path search for the 7x7 workload")
+    ap.add_argument("--rank", default="time", choices=["time", "flops"],
+                    help="partition search: re-rank the best candidates by modelled kernel time (default) "
+                         "or keep the flop-minimal tree")
+    ap.add_argument("--profile-steps", type=int, default=1,
+                    help="jobs run once more with HIP events around every kernel, after the timed region")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=7)
     ap.add_argument("--cols", type=int, default=7)
     ap.add_argument("--cycles", type=int, default=14)
-    ap.add_argument("--autotune", action="store_true",
-                    help="run the GEMM tile autotuner first (its proxy launches then appear in kernel traces)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="run the GEMM tile autotuner before the warmup (its trial launches appear in kernel traces)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "learned", "expval", "dm"],
                     help="c2 (default) is the benchmark line; the others measure the remaining rows")
     ap.add_argument("--calib-copy", action="store_true",
@@ -106,7 +114,8 @@ def make_workload(a):
     net = tn.tn_build_network(n, ops)
     t0 = time.time()
     if a.path == "partition":
-        path = tn.tn_find_path(net, "partition", trials=a.trials, seed=1, mem_budget_bytes=a.budget_gib * 2 ** 30)
+        path = tn.tn_find_path(net, "partition", trials=a.trials, seed=1, mem_budget_bytes=a.budget_gib * 2 ** 30,
+                               rank=a.rank, rank_precision=a.precision)
     else:
         path = tn.tn_find_path(net, "random_greedy", trials=a.trials, seed=1, temperature=0.5,
                                mem_budget_bytes=a.budget_gib * 2 ** 30)
@@ -600,6 +609,74 @@ def bench_dm(a):
             "cpu_baseline": cpu}
 
 
+def run_graph(net, path, bits, slice_id, precision):
+    """All rows of `bits` at one slice in one tn_amplitudes call: the job's
+    kernel sequence is captured once as a hipGraph and replayed per job.
+    Returns (amplitudes, device seconds)."""
+    import torch
+    import paper_2104_10523_amd as tn
+    bits = np.ascontiguousarray(bits)
+    out = torch.zeros((len(bits), 1), dtype=torch.complex128, device="cuda")
+    _, rep = tn.tn_amplitudes(net, path, bits, out=out, precision=precision, use_graph=True,
+                              slice_begin=slice_id, slice_count=1, sync=True)
+    if rep.nonfinite:
+        raise RuntimeError("non-finite amplitude")
+    return out.cpu().numpy()[:, 0], rep.seconds
+
+
+def op_kernel_name(precision, k, sh):
+    """The kernel an op of the plan launches (rocprofv3's name, without
+    arguments)."""
+    if k == 2:
+        return kernel_name(precision, int(sh[4]), int(sh[5]))
+    if k == 0:
+        return f"apply_small_kernel<{int(sh[1])}>"
+    if k == 3:
+        return f"skinny_partial_kernel<{int(sh[0])}, {int(sh[1])}>" if sh[5] else "dot_partial_kernel"
+    np_ = 4 if sh[2] else int(sh[1])
+    return {0: "device copy", 1: f"permute_simple_kernel<{np_}>", 2: f"permute_tiled_kernel<{np_}>",
+            3: "maxabs_kernel", 4: f"permute_pipe_kernel<{np_}>"}[int(sh[3])]
+
+
+def kernel_table(precision, kind, fl, by, shape, op_sec, jobs):
+    """Per kernel: seconds, launches, algorithmic flops and bytes over `jobs`
+    profiled jobs."""
+    out = {}
+    for k in range(len(kind)):
+        nm = op_kernel_name(precision, int(kind[k]), shape[k])
+        e = out.setdefault(nm, {"seconds": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        e["seconds"] += float(op_sec[k])
+        e["launches"] += int(shape[k, 6]) * jobs
+        e["flops"] += float(fl[k]) * jobs
+        e["bytes"] += float(by[k]) * jobs
+    return out
+
+
+def roofline_entry(kernel, flops, bytes_, seconds, precision):
+    """Roofline of one launch: a GEMM whose algorithmic intensity reaches the
+    balance point of its own arithmetic (split products: 3 or 6 MFMA
+    products per multiply-add, so the ridge sits at peak / 3 or / 6 over HBM
+    bandwidth) is priced against its dtype's MFMA peak; everything else
+    against HBM bandwidth."""
+    if kernel.startswith("gemm"):
+        if kernel.startswith("gemm_mfma_kernel") and kernel.endswith(", 0>"):      # FP32 MFMA
+            peak, eff = PEAKS["fp32"], PEAKS["fp32"]
+        elif kernel.startswith("gemm_mfma_kernel"):                              # split in LDS
+            peak = 2.5e15
+            eff = peak / (6 if kernel.endswith(", 2>") else 3)
+        else:                                                                    # packed planes
+            np_ = 3 if kernel.endswith(", 3, false>") else 2
+            peak = 2.5e15
+            eff = peak / (6 if np_ == 3 else 3)
+        if bytes_ > 0 and flops / bytes_ >= eff / HBM_PEAK:
+            return {"bound": "mfma", "achieved": flops / seconds / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                    "frac": flops / seconds / peak, "algorithmic_peak": eff / 1e12,
+                    "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": bytes_}
+    return {"bound": "hbm", "achieved": bytes_ / seconds / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": bytes_ / seconds / HBM_PEAK, "algorithmic_flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": bytes_}
+
+
 ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "learned": bench_learned,
         "expval": bench_expval, "dm": bench_dm}
 
@@ -624,7 +701,7 @@ def main():
         del x, y
     n, ops, bits, net, path, t_path = make_workload(a)
     ns = path.cost.n_slices
-    need = max(tn.tn_amplitudes_workspace(net, path, 1, p) for p in ("fp32", a.precision))
+    need = max(tn.tn_amplitudes_workspace(net, path, max(a.steps, a.warmup, 1), p) for p in ("fp32", a.precision))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     tn.tn_set_workspace(ws)
     t0 = time.time()
@@ -633,70 +710,57 @@ def main():
             tn.tn_amplitudes_autotune(net, path, p, reps=2)
     t_tune = time.time() - t0
     rng = np.random.default_rng(7)
-    total = a.warmup + a.steps
-    jobs = [(int(rng.integers(0, 64)), int(rng.integers(0, int(ns)))) for _ in range(total)]
-    print(f"# workload 7x7x14 fSim: slices 2^{path.cost.n_sliced}, per-slice flops 2^{math.log2(path.cost.flops_per_slice):.2f}, "
-          f"workspace {need / 2**30:.1f} GiB, path search {t_path:.1f}s, autotune {t_tune:.1f}s", file=sys.stderr, flush=True)
-    # warmup
+    slice_warm, slice_timed, slice_prof = (int(x) for x in rng.integers(0, int(ns), 3))
+    rows = rng.permutation(64)
+    print(f"# workload {a.rows}x{a.cols}x{a.cycles} fSim: slices 2^{path.cost.n_sliced}, per-slice flops "
+          f"2^{math.log2(path.cost.flops_per_slice):.2f}, workspace {need / 2**30:.1f} GiB, path search "
+          f"{t_path:.1f}s, autotune {t_tune:.1f}s", file=sys.stderr, flush=True)
+    # warmup, then the timed region: one tn_amplitudes call per region whose
+    # (bit-string, slice) jobs replay one captured hipGraph of the job's
+    # kernel sequence (the production path)
     if a.warmup:
-        time_steps(net, path, bits, a.precision, jobs[:a.warmup], stream)
+        run_graph(net, path, bits[rows[:a.warmup]], slice_warm, a.precision)
     print("# warmup done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    per_job, op_sec, (info, kind, fl, by, shape), amps = time_steps(net, path, bits, a.precision,
-                                                                     jobs[a.warmup:], stream)
+    amps, dev_s = run_graph(net, path, bits[rows[a.warmup:a.warmup + a.steps]], slice_timed, a.precision)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # the host clock around the timed steps (device events per job agree to
-    # within the per-call setup of a few milliseconds)
     T = wall / a.steps
-    flops_job = float(fl.sum())
     amps_per_s = 1.0 / (ns * T)
-    # dominant kernel: the GEMM instantiation (tile shape) with the most time
-    names = {}
-    for k in np.nonzero(kind == 2)[0]:
-        names.setdefault(kernel_name(a.precision, int(shape[k, 4]), int(shape[k, 5])), []).append(k)
-    dom = max(names, key=lambda nm: op_sec[names[nm]].sum())
-    sel = np.array(names[dom])
-    # kernel launches: a long GEMM runs as several K-chunk launches
-    n_launch = int(shape[sel, 6].sum()) * a.steps
-    g_flops = float(fl[sel].sum()) * a.steps
-    g_time = float(op_sec[sel].sum())
-    g_bytes = float(by[sel].sum()) * a.steps
-    # MFMA peak of the dominant kernel's own arithmetic (packed split-16-bit or FP32)
-    peak = PEAKS["fp32"] if dom.startswith("gemm_mfma_kernel") and dom.endswith("fp32>") else \
-        (PEAKS[a.precision] if a.precision in PEAKS else PEAKS["f16x3"])
+    # profiled pass (after the timed region): HIP events around every op
+    prof_jobs = [(int(rows[(a.warmup + a.steps + j) % 64]), slice_prof) for j in range(a.profile_steps)]
+    _, op_sec, (info, kind, fl, by, shape), _ = time_steps(net, path, bits, a.precision, prof_jobs, stream)
+    P = max(1, a.profile_steps)
+    flops_job = float(fl.sum())
+    kern = kernel_table(a.precision, kind, fl, by, shape, op_sec, P)
+    dom = max(kern, key=lambda k: kern[k]["seconds"])
+    d = kern[dom]
+    step_kernel_s = sum(v["seconds"] for v in kern.values()) / P
     traffic, traffic_src = recorded_traffic(dom)
-    achieved = g_flops / g_time if g_time > 0 else 0.0
-    # the bound follows the kernel's algorithmic intensity: below the
-    # MFMA / HBM balance point it is priced against HBM bandwidth
-    hbm_bound = g_bytes > 0 and g_flops / g_bytes < peak / HBM_PEAK
-    if hbm_bound:
-        roof = {"bound": "hbm", "achieved": g_bytes / g_time / 1e9 if g_time > 0 else 0.0,
-                "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": (g_bytes / g_time if g_time > 0 else 0.0) / HBM_PEAK}
-    else:
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak}
-    t_by_kind = {k: float(op_sec[kind == i].sum()) / a.steps
-                 for i, k in enumerate(("apply", "permute", "gemm", "dot"))}
-    print(f"# per step {T:.3f}s (device events {per_job.mean():.3f}s); time by kind {t_by_kind}",
+    avg_s = d["seconds"] / d["launches"]
+    fl_launch, by_launch = d["flops"] / d["launches"], d["bytes"] / d["launches"]
+    roof = roofline_entry(dom, fl_launch, by_launch, avg_s, a.precision)
+    t_by_kind = {k: float(op_sec[kind == i].sum()) / P for i, k in enumerate(("apply", "permute", "gemm", "dot"))}
+    print(f"# per step {T:.3f}s (graph replays; device {dev_s / a.steps:.3f}s); profiled step {step_kernel_s:.3f}s "
+          f"by kind {t_by_kind}; dominant {dom} {100 * d['seconds'] / P / step_kernel_s:.1f}%",
           file=sys.stderr, flush=True)
     fp32 = None
     if a.compare_fp32 and a.precision != "fp32":
-        pj, os32, (_, k32, f32, _, _), a32 = time_steps(net, path, bits, "fp32", jobs[a.warmup:a.warmup + 1],
-                                                         stream)
-        b32 = k32 == 2
-        fp32 = {"seconds_per_step": float(pj.mean()),
-                "amplitudes_per_s": 1.0 / (ns * float(pj.mean())),
-                "gemm_tflops": float(f32[b32].sum()) / float(os32[b32].sum()) / 1e12,
-                "speedup_of_split": float(pj.mean()) / T,
-                "slice_amplitude_rel_diff": float(abs(amps[0] - a32[0]) / max(abs(a32[0]), 1e-300)),
+        k32 = 2
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        a32, _ = run_graph(net, path, bits[rows[a.warmup:a.warmup + k32]], slice_timed, "fp32")
+        torch.cuda.synchronize()
+        T32 = (time.perf_counter() - t1) / k32
+        fp32 = {"seconds_per_step": T32, "amplitudes_per_s": 1.0 / (ns * T32), "speedup_of_split": T32 / T,
+                # same (bit-string, slice) jobs as the first timed ones
+                "slice_amplitude_rel_diff": float(np.max(np.abs(amps[:k32] - a32) / np.maximum(np.abs(a32), 1e-300))),
                 # floor: the RMS amplitude of one slice of a normalised state
-                "slice_amplitude_floored_diff": float(abs(amps[0] - a32[0]) /
-                                                      max(abs(a32[0]), 2.0 ** (-(n + path.cost.n_sliced) / 2))),
-                "slice_amplitude_over_floor": float(abs(a32[0]) / 2.0 ** (-(n + path.cost.n_sliced) / 2))}
-        print(f"# fp32 step {pj.mean():.3f}s", file=sys.stderr, flush=True)
+                "slice_amplitude_floored_diff": float(np.max(np.abs(amps[:k32] - a32) /
+                                                             np.maximum(np.abs(a32), 2.0 ** (-(n + path.cost.n_sliced) / 2)))),
+                "slice_amplitude_over_floor": float(np.min(np.abs(a32)) / 2.0 ** (-(n + path.cost.n_sliced) / 2))}
+        print(f"# fp32 step {T32:.3f}s", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
         from oracle.network import build_network
@@ -716,7 +780,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": T * 1e3,
-        "median_ms_per_step_device": float(np.median(per_job)) * 1e3,
+        "device_ms_per_step": dev_s / a.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -728,20 +792,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.rows}x{a.cols} grid random circuit, {a.cycles} cycles, fSim(pi/2,pi/6), "
                                f"64 bit-strings, {'recursive-bisection' if a.path == 'partition' else 'randomised-greedy'} "
-                               f"path ({a.trials} trials), 2^{path.cost.n_sliced} slices "
-                               f"({a.budget_gib:g} GiB budget); value extrapolated from timed slices",
+                               f"path ({a.trials} trials, ranked by {a.rank if a.path == 'partition' else 'flops'}), "
+                               f"2^{path.cost.n_sliced} slices ({a.budget_gib:g} GiB budget); value extrapolated "
+                               f"from timed (bit-string, slice) jobs",
                    "qubits": n, "bitstrings": 64, "slices": ns, "path_search_seconds": t_path,
+                   "autotune_seconds": t_tune,
                    "flops_per_step": flops_job, "flops_per_amplitude": flops_job * ns,
-                   "complex_tflops": flops_job / T / 1e12, "precision": a.precision},
+                   "bytes_per_step": float(by.sum()),
+                   "complex_tflops": flops_job / T / 1e12, "hbm_tbs": float(by.sum()) / T / 1e12,
+                   "precision": a.precision},
         "roofline": {**roof, "traffic": traffic,
                      "traffic_unit": "bytes/launch", "traffic_source": traffic_src,
                      "kernel": dom,
-                     "launches": n_launch,
-                     "algorithmic_flops_per_launch": g_flops / max(1, n_launch),
-                     "avg_launch_ms": 1e3 * g_time / max(1, n_launch),
-                     "algorithmic_bytes_per_launch": g_bytes / max(1, n_launch),
+                     "launches": d["launches"],
+                     "avg_launch_ms": 1e3 * avg_s,
+                     "share_of_step": d["seconds"] / P / step_kernel_s,
                      "step_seconds_by_kind": t_by_kind,
-                     "note": "kernel = the GEMM instantiation with the most time in a step"},
+                     "kernels": {k: {"share": v["seconds"] / P / step_kernel_s,
+                                     "avg_launch_ms": 1e3 * v["seconds"] / v["launches"],
+                                     "gbs": v["bytes"] / v["seconds"] / 1e9 if v["seconds"] > 0 else 0.0}
+                                 for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["seconds"])[:8]},
+                     "note": "kernel = the kernel with the largest share of a step (HIP events around every "
+                             "op of the profiled jobs that follow the timed graph replays)"},
         "fp32_comparison": fp32,
         "cpu_baseline": cpu,
     }

@@ -146,7 +146,13 @@ typedef struct {
                               /* takes the highest-scoring candidate each   */
                               /* step and falls back to greedy when greedy  */
                               /* is cheaper (flops, then peak)              */
+  int32_t rank;               /* TN_PATH_PARTITION: TN_RANK_FLOPS (default) */
+                              /* or TN_RANK_TIME (see tn_find_path)         */
+  int32_t rank_precision;     /* TN_RANK_TIME: TN_PREC_* of the modelled    */
+                              /* amplitude plan                             */
 } tn_path_opts;
+
+enum { TN_RANK_FLOPS = 0, TN_RANK_TIME = 1 };
 
 typedef struct {
   double flops_per_slice;     /* 8 * sum over steps of prod(extents A u B)  */
@@ -186,7 +192,14 @@ typedef struct {
  * over subsets) replaces the subtree when strictly cheaper; passes repeat
  * (at most 8) until one no longer lowers the tree's flops.  The plain
  * greedy path and the trials are each sliced to the budget and the lowest
- * (total flops, peak, index) wins.  Host only.
+ * (total flops, peak, index) wins.  With rank = TN_RANK_TIME the 16 lowest
+ * by that key are compiled into amplitude plans (all legs projected unless
+ * open_mask says otherwise, precision rank_precision) and the one of least
+ * modelled time wins (earlier on ties): n_slices x the sum over kernels of
+ * max(flops / F, bytes / 4.0e12 B/s) + 5 us per launch, F = 350e12 flop/s
+ * for split-precision GEMMs and 120e12 for the rest (sustained rates of
+ * these kernels on MI355X); the contraction is memory-bound on this GPU, so
+ * the flop count alone misranks trees.  Host only.
  * Errors: TN_ERR_ARG, TN_ERR_BUDGET, TN_ERR_STATE (LEARNED without model). */
 tn_status tn_find_path(const tn_network* n, const tn_path_opts* o,
                        tn_path** out, tn_path_cost* cost);
@@ -387,7 +400,11 @@ tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p,
  * block-tile id, packed flag, GEMM kernel launches (K-chunked accumulation:
  * ceil(k / 4096) unless split-K is used), 0 — for GEMMs; other kinds give
  * 1, 1, 1, 1, -1, 0, 1, 0 except APPLY: rows, 2^#N, 2^#K in the first three,
- * DOT: k and batch in the third and fourth. */
+ * DOT: m, n, k, batch, and in the sixth 1 for the skinny long-K kernel
+ * (batch 1, both operands read once) or 0 for one dot per (m, n), PERMUTE: output entries, planes
+ * (0 = complex64, 2 or 3 split planes), fp16 flag and the kernel (0 device
+ * copy, 1 permute_simple_kernel, 2 permute_tiled_kernel, 3 the max-abs
+ * pre-pass of an fp16 operand, 4 permute_pipe_kernel) in the first four. */
 tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p,
                                  int32_t precision, int32_t* kind,
                                  double* flops, double* bytes, int64_t* shape);

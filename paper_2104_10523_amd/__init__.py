@@ -139,8 +139,13 @@ def _path_opts(n_qubits, algo, trials, seed, temperature, budget, open_mask):
 
 def tn_find_path(net: Network, algo: str = "greedy", trials: int = 32, seed: int = 0,
                  temperature: float = 1.0, mem_budget_bytes: float = 0.0,
-                 open_mask: Optional[Sequence[int]] = None) -> Path:
+                 open_mask: Optional[Sequence[int]] = None, rank: str = "flops",
+                 rank_precision: str = "auto") -> Path:
+    """rank = "time" re-ranks the partition search's best candidates by the
+    modelled kernel time of their amplitude plans at rank_precision."""
     o, _keep = _path_opts(net.n_qubits, algo, trials, seed, temperature, mem_budget_bytes, open_mask)
+    o.rank = {"flops": 0, "time": 1}[rank]
+    o.rank_precision = PREC[rank_precision]
     h = C.c_void_p()
     cost = TnPathCost()
     check(lib().tn_find_path(net.h, C.byref(o), C.byref(h), C.byref(cost)))

@@ -279,7 +279,33 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
       pairs = random_greedy_path(pr, o->seed, o->trials, o->temperature, o->mem_budget_bytes);
     } else if (algo == TN_PATH_PARTITION) {
       TN_REQUIRE(o->trials >= 0, TN_ERR_ARG, "bad partition options");
-      pairs = partition_search(pr, o->seed, o->trials, o->mem_budget_bytes);
+      TN_REQUIRE(o->rank == TN_RANK_FLOPS || o->rank == TN_RANK_TIME, TN_ERR_ARG, "bad rank");
+      if (o->rank == TN_RANK_FLOPS) {
+        pairs = partition_search(pr, o->seed, o->trials, o->mem_budget_bytes);
+      } else {
+        TN_REQUIRE(o->rank_precision >= TN_PREC_FP32 && o->rank_precision <= TN_PREC_F16X3, TN_ERR_ARG,
+                   "bad rank precision");
+        auto cands = partition_candidates(pr, o->seed, o->trials, o->mem_budget_bytes, 16);
+        int best = -1;
+        double best_t = 0;
+        for (size_t c = 0; c < cands.size(); ++c) {
+          std::vector<int> sl;
+          try {
+            sl = slice_path(pr, cands[c], o->mem_budget_bytes);
+          } catch (const Error& e) {
+            if (e.code != TN_ERR_BUDGET) throw;
+            continue;
+          }
+          const PathStats ps = path_stats(pr, cands[c], sl);
+          const AmpPlan plan = compile_amplitudes(n->net, cands[c], sl, open_q, o->rank_precision);
+          const double t = ps.n_slices * modelled_job_seconds(plan);
+          if (best < 0 || t < best_t) {
+            best = int(c);
+            best_t = t;
+          }
+        }
+        pairs = std::move(cands[best < 0 ? 0 : best]);
+      }
     } else {
       TN_REQUIRE(o->model != nullptr, TN_ERR_STATE, "learned path needs a model");
       int used = TN_PATH_GREEDY;
@@ -576,9 +602,13 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
           r[1] = int64_t(1) << op.ap.nn;
           r[2] = int64_t(1) << op.ap.nk;
         } else if (op.kind == OP_DOT) {
-          r[2] = op.dot_k; r[3] = op.dot_batch * op.dot_m * op.dot_n;
+          r[0] = op.dot_m; r[1] = op.dot_n; r[2] = op.dot_k; r[3] = op.dot_batch;
+          r[5] = op.skinny;
         } else {
           r[0] = int64_t(1) << op.pm.nb;
+          r[1] = op.pm.np;
+          r[2] = op.pm.f16;
+          r[3] = permute_variant(op.pm);
         }
       }
     }

@@ -173,6 +173,121 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
   }
 }
 
+// Pipelined variant for tensors of >= 2^12 entries with 16-byte aligned
+// buffers (the tile then has all 12 bits, input bits 0..5 and output bits
+// 0..5 among them).  Each thread moves 16 entries per tile: it loads them as
+// 8 x 16-byte pairs (input bit 0 inside a pair) and stores 4 x 4 consecutive
+// outputs (output bits 0 and 1 inside a group) with 16-byte stores, 32-byte
+// for complex64.  The loads of the next tile are issued before the current
+// tile leaves LDS, so a block keeps 32 KB of reads in flight while it writes.
+// Every per-thread offset inside a tile is the same for all tiles and is
+// computed once.
+constexpr int kPipePad = 2;   // float2 of padding per 64-entry LDS row (keeps 16-byte alignment)
+__device__ __forceinline__ int pipe_pos(int e) { return e + kPipePad * (e >> 6); }
+
+template <int NP>
+__global__ __launch_bounds__(256) void permute_pipe_kernel(const float2* __restrict__ in,
+                                                           void* __restrict__ out, PermArgs P,
+                                                           const uint32_t* __restrict__ smax) {
+  const float scale = NP == kF16 ? operand_scale(smax) : 1.f;
+  __shared__ int64_t s_in_lo[64], s_in_hi[64], s_out_lo[64], s_out_hi[64];
+  __shared__ int s_l_lo[64], s_l_hi[64];
+  __shared__ __align__(16) float2 tile[kPermTile + kPipePad * (kPermTile / 64)];
+  const int t = threadIdx.x;
+  if (t < 64) {
+    int64_t il = 0, ih = 0, ol = 0, oh = 0;
+    int ll = 0, lh = 0;
+    for (int i = 0; i < 6; ++i) {
+      if (!((t >> i) & 1)) continue;
+      il |= int64_t(1) << P.tpos[i];
+      ol |= int64_t(1) << P.opos[i];
+      ll |= 1 << P.map[i];
+      ih |= int64_t(1) << P.tpos[i + 6];
+      oh |= int64_t(1) << P.opos[i + 6];
+      lh |= 1 << P.map[i + 6];
+    }
+    s_in_lo[t] = il; s_in_hi[t] = ih;
+    s_out_lo[t] = ol; s_out_hi[t] = oh;
+    s_l_lo[t] = ll; s_l_hi[t] = lh;
+  }
+  __syncthreads();
+  int64_t ld_off[8], st_off[4];
+  int ld_pos[8], rd_pos[16];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = 2 * (t + 256 * i);
+    ld_off[i] = s_in_lo[e & 63] + s_in_hi[e >> 6];
+    ld_pos[i] = pipe_pos(e);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int f0 = 4 * (t + 256 * j);
+    st_off[j] = s_out_lo[f0 & 63] + s_out_hi[f0 >> 6];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = f0 + q;
+      rd_pos[4 * j + q] = pipe_pos(s_l_lo[f & 63] | s_l_hi[f >> 6]);
+    }
+  }
+  int64_t tau = blockIdx.x;
+  if (tau >= P.n_tiles) return;
+  auto deposit = [&](int64_t x, const int8_t* pos) {
+    int64_t r = 0;
+    for (int k = 0; k < P.rb; ++k)
+      if ((x >> k) & 1) r |= int64_t(1) << pos[k];
+    return r;
+  };
+  float4 v[8];
+  {
+    const int64_t ib = deposit(tau, P.r_in);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const float4*>(in + ib + ld_off[i]);
+  }
+  while (true) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(&tile[ld_pos[i]]) = v[i];
+    __syncthreads();
+    const int64_t ob = deposit(tau, P.r_out);
+    const int64_t nxt = tau + gridDim.x;
+    if (nxt < P.n_tiles) {
+      const int64_t ib = deposit(nxt, P.r_in);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const float4*>(in + ib + ld_off[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float2 x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = tile[rd_pos[4 * j + q]];
+      const int64_t o = ob + st_off[j];
+      if constexpr (NP == 0) {
+        float4* dst = reinterpret_cast<float4*>(static_cast<float2*>(out) + o);
+        dst[0] = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+        dst[1] = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
+      } else if constexpr (NP == kF16) {
+        uint32_t w[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split_c_f16(x[q], scale, w[q]);
+        uint32_t* dst = static_cast<uint32_t*>(out) + o;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          *reinterpret_cast<uint4*>(dst + p * P.plane) = make_uint4(w[0][p], w[1][p], w[2][p], w[3][p]);
+      } else {
+        uint32_t w[4][NP];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) split_c<NP>(x[q], w[q]);
+        uint32_t* dst = static_cast<uint32_t*>(out) + o;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          *reinterpret_cast<uint4*>(dst + p * P.plane) = make_uint4(w[0][p], w[1][p], w[2][p], w[3][p]);
+      }
+    }
+    __syncthreads();
+    if (nxt >= P.n_tiles) break;
+    tau = nxt;
+  }
+}
+
 struct PermSimpleArgs {
   int nb;
   int identity;
@@ -195,6 +310,12 @@ __global__ __launch_bounds__(256) void permute_simple_kernel(const float2* __res
     }
     put<NP>(out, P.plane, o, in[off], scale);
   }
+}
+
+// The pipelined permute handles full 12-bit tiles on 16-byte aligned buffers.
+static bool pipe_ok(const PermuteDesc& d, const void* in, const void* out) {
+  return d.nb >= kPermBits && (reinterpret_cast<uintptr_t>(in) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(out) & 15) == 0;
 }
 
 template <int NP>
@@ -265,7 +386,13 @@ static void launch_permute_np(const float2* in, void* out, const PermuteDesc& d,
   P.rb = rb;
   P.n_tiles = int64_t(1) << rb;
   const int64_t blocks = std::min<int64_t>(P.n_tiles, 256 * 32);
-  permute_tiled_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, smax);
+  if (pipe_ok(d, in, out)) {
+    TN_REQUIRE(P.tb == kPermBits && P.tpos[0] == 0 && P.opos[0] == 0 && P.opos[1] == 1, TN_ERR_ARG,
+               "internal: pipelined permute needs a full tile holding bits 0 and 1");
+    permute_pipe_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, smax);
+  } else {
+    permute_tiled_kernel<NP><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, out, P, smax);
+  }
   TN_HIP(hipGetLastError());
 }
 
@@ -289,15 +416,38 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const float2* __restrict__ 
     atomicMax(slot, __float_as_uint(fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]))));
 }
 
+int permute_variant(const PermuteDesc& d) {
+  if (d.maxabs) return 3;
+  const int nb = d.nb;
+  bool is_perm = d.nb_in == nb, ident = true;
+  std::vector<char> seen(std::max(nb, 1), 0);
+  for (int j = 0; j < nb && is_perm; ++j) {
+    if (d.src[j] < 0 || d.src[j] >= nb || seen[d.src[j]]) {
+      is_perm = false;
+      break;
+    }
+    seen[d.src[j]] = 1;
+    if (d.src[j] != j) ident = false;
+  }
+  const int np = d.f16 ? kF16 : d.np;
+  if (is_perm && ident && np == 0) return 0;
+  if (!is_perm || ident || nb < 6) return 1;
+  return nb >= kPermBits ? 4 : 2;   // plan buffers are 256-byte aligned
+}
+
 void launch_permute(const float2* in, void* out, const PermuteDesc& d, uint32_t* smax, hipStream_t s) {
   TN_REQUIRE(d.nb >= 0 && d.nb <= 62, TN_ERR_UNSUPPORTED, "tensor too large to permute");
-  if (d.f16) {
-    TN_REQUIRE(d.np == 2 && smax != nullptr, TN_ERR_ARG, "internal: fp16 planes need a scale slot");
+  if (d.maxabs) {
+    TN_REQUIRE(smax != nullptr, TN_ERR_ARG, "internal: the max-abs pre-pass needs a scale slot");
     const int64_t n_in = int64_t(1) << d.nb_in;
     scale_clear_kernel<<<1, 1, 0, s>>>(smax);
     const int64_t blocks = std::min<int64_t>(ceil_div(n_in, 256), grid_cap());
     maxabs_kernel<<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(in, n_in, smax);
     TN_HIP(hipGetLastError());
+    return;
+  }
+  if (d.f16) {
+    TN_REQUIRE(d.np == 2 && smax != nullptr, TN_ERR_ARG, "internal: fp16 planes need a scale slot");
     launch_permute_np<kF16>(in, out, d, smax, s);
     return;
   }
@@ -1438,6 +1588,117 @@ void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t 
   TN_HIP(hipGetLastError());
   dot_final_kernel<<<dim3(unsigned(ceil_div(outs, 256))), 256, 0, s>>>(static_cast<double2*>(work), C,
                                                                       parts, outs);
+  TN_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ skinny long-K GEMM
+
+// C[m][n] = sum_k A(m, k) B(k, n) for M, N <= 16 (M N <= 64) over a long K:
+// every thread accumulates all M x N outputs for its strided share of k in
+// FP32 registers, reading A and B once (M + N complex per k), so the pass
+// streams at HBM rate where an MFMA tile would mostly idle.  A(m, k) sits
+// at A[m * sam + k * sak], B(k, n) at B[k * sbk + n * sbn].  Block sums go
+// to `part` in FP64 and skinny_final_kernel adds them in FP64.
+constexpr int kSkinnyBlocks = 1024;
+
+template <int MM, int NN>
+__global__ __launch_bounds__(256) void skinny_partial_kernel(const float2* __restrict__ A,
+                                                             const float2* __restrict__ B,
+                                                             double2* __restrict__ part, int64_t K,
+                                                             int64_t sam, int64_t sak, int64_t sbk,
+                                                             int64_t sbn) {
+  float2 acc[MM][NN];
+#pragma unroll
+  for (int m = 0; m < MM; ++m)
+#pragma unroll
+    for (int n = 0; n < NN; ++n) acc[m][n] = make_float2(0.f, 0.f);
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < K; k += int64_t(gridDim.x) * 256) {
+    float2 a[MM], b[NN];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) a[m] = A[m * sam + k * sak];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) b[n] = B[k * sbk + n * sbn];
+#pragma unroll
+    for (int m = 0; m < MM; ++m)
+#pragma unroll
+      for (int n = 0; n < NN; ++n) cmac(acc[m][n], a[m], b[n]);
+  }
+  __shared__ double2 red[4][MM * NN];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int m = 0; m < MM; ++m)
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      double re = acc[m][n].x, im = acc[m][n].y;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (lane == 0) red[w][m * NN + n] = make_double2(re, im);
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < MM * NN; i += 256) {
+    const double2 v = make_double2(red[0][i].x + red[1][i].x + red[2][i].x + red[3][i].x,
+                                   red[0][i].y + red[1][i].y + red[2][i].y + red[3][i].y);
+    part[int64_t(blockIdx.x) * (MM * NN) + i] = v;
+  }
+}
+
+__global__ void skinny_final_kernel(const double2* __restrict__ part, float2* __restrict__ C, int nparts,
+                                    int outs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= outs) return;
+  double sr = 0.0, si = 0.0;
+  for (int p = 0; p < nparts; ++p) {
+    sr += part[int64_t(p) * outs + i].x;
+    si += part[int64_t(p) * outs + i].y;
+  }
+  C[i] = make_float2(float(sr), float(si));
+}
+
+static int skinny_blocks(int64_t K) {
+  return int(std::max<int64_t>(1, std::min<int64_t>(kSkinnyBlocks, ceil_div(K, 256 * 16))));
+}
+
+size_t skinny_workspace_bytes(int64_t K, int64_t m, int64_t n) {
+  return size_t(skinny_blocks(K)) * size_t(m * n) * sizeof(double2);
+}
+
+bool skinny_supported(int64_t m, int64_t n) {
+  auto p2 = [](int64_t x) { return x >= 1 && x <= 16 && (x & (x - 1)) == 0; };
+  return p2(m) && p2(n) && m * n <= 64 && m * n > 1;
+}
+
+template <int MM, int NN>
+static void launch_skinny_mn(const float2* A, const float2* B, double2* part, int64_t K, int64_t sam,
+                             int64_t sak, int64_t sbk, int64_t sbn, int blocks, hipStream_t s) {
+  skinny_partial_kernel<MM, NN><<<blocks, 256, 0, s>>>(A, B, part, K, sam, sak, sbk, sbn);
+}
+
+void launch_skinny(const float2* A, const float2* B, float2* C, int64_t K, int64_t m, int64_t n, int transA,
+                   int transB, void* work, hipStream_t s) {
+  TN_REQUIRE(work != nullptr, TN_ERR_WORKSPACE, "skinny GEMM needs workspace");
+  TN_REQUIRE(skinny_supported(m, n), TN_ERR_ARG, "internal: skinny GEMM shape");
+  // transA = 0: A[m][k]; 1: A[k][m].  transB = 0: B[k][n]; 1: B[n][k].
+  const int64_t sam = transA ? 1 : K, sak = transA ? m : 1;
+  const int64_t sbk = transB ? 1 : n, sbn = transB ? K : 1;
+  const int blocks = skinny_blocks(K);
+  double2* part = static_cast<double2*>(work);
+  const int key = int(m) * 32 + int(n);
+  switch (key) {
+#define TN_SKINNY(MM, NN) \
+  case MM * 32 + NN: launch_skinny_mn<MM, NN>(A, B, part, K, sam, sak, sbk, sbn, blocks, s); break;
+    TN_SKINNY(1, 2) TN_SKINNY(2, 1) TN_SKINNY(1, 4) TN_SKINNY(4, 1) TN_SKINNY(2, 2)
+    TN_SKINNY(1, 8) TN_SKINNY(8, 1) TN_SKINNY(2, 4) TN_SKINNY(4, 2) TN_SKINNY(1, 16) TN_SKINNY(16, 1)
+    TN_SKINNY(2, 8) TN_SKINNY(8, 2) TN_SKINNY(4, 4) TN_SKINNY(2, 16) TN_SKINNY(16, 2) TN_SKINNY(4, 8)
+    TN_SKINNY(8, 4) TN_SKINNY(4, 16) TN_SKINNY(16, 4) TN_SKINNY(8, 8)
+#undef TN_SKINNY
+    default: throw Error(TN_ERR_ARG, "internal: skinny GEMM shape");
+  }
+  TN_HIP(hipGetLastError());
+  const int outs = int(m * n);
+  skinny_final_kernel<<<dim3(unsigned(ceil_div(outs, 256))), 256, 0, s>>>(part, C, blocks, outs);
   TN_HIP(hipGetLastError());
 }
 

@@ -24,9 +24,14 @@ struct PermuteDesc {
   int nb_in = 0;
   int np = 0;
   int f16 = 0;
+  int maxabs = 0;          // 1: only the max-abs pre-pass of an fp16 operand (into smax)
   int8_t src[kMaxBits];
 };
 void launch_permute(const float2* in, void* out, const PermuteDesc& d, uint32_t* smax, hipStream_t s);
+// Which kernel launch_permute runs on 16-byte aligned buffers: 0 device
+// copy, 1 permute_simple_kernel, 2 permute_tiled_kernel (6..11 bits),
+// 3 maxabs_kernel (pre-pass), 4 permute_pipe_kernel (>= 12 bits).
+int permute_variant(const PermuteDesc& d);
 
 // C[m * 2^nn + n] = sum_k A[expand(m) + kscat(k)] * B[bscat(k, n)]
 //   A: `a_bits` bits; K bits of A at positions kpos (ascending), others are M.
@@ -104,6 +109,13 @@ void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* p
 
 // Dot products (M = N = 1) with split-K; result written as complex64.
 size_t dot_workspace_bytes(int64_t K, int64_t batch);
+// Long-K GEMM with few outputs (M, N powers of two <= 16, 1 < M N <= 64,
+// batch 1): A and B read once, FP32 per-thread sums, FP64 block sums.
+// transA = 0: A[m][k], 1: A[k][m]; transB = 0: B[k][n], 1: B[n][k].
+bool skinny_supported(int64_t m, int64_t n);
+size_t skinny_workspace_bytes(int64_t K, int64_t m, int64_t n);
+void launch_skinny(const float2* A, const float2* B, float2* C, int64_t K, int64_t m, int64_t n, int transA,
+                   int transB, void* work, hipStream_t s);
 // C[b][m][n] = sum_k A[b][m][k] B[b][n][k] (complex, FP64 accumulation);
 // m = n = 1 is the plain batched dot.
 void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t batch, int64_t m,

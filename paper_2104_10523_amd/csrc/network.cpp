@@ -9,6 +9,7 @@
 // Tensors: two-qubit gates in circuit order, then lone wires in qubit order.
 // Labels are handed out as legs are created (a's output, then b's).
 #include <algorithm>
+#include <numeric>
 #include <functional>
 #include <atomic>
 #include <cmath>
@@ -715,11 +716,12 @@ std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
   return out;
 }
 
-std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
-                                                  double budget_bytes) {
+std::vector<std::vector<std::pair<int, int>>> partition_candidates(const PathProblem& pr, uint64_t seed,
+                                                                  int trials, double budget_bytes, int keep) {
   // Candidates: the plain greedy path (index 0) and `trials` bisection trees
   // (trial r seeded like the randomised greedy).  Each is sliced to the
-  // budget (if any) and the lowest (total flops, peak, index) wins.
+  // budget (if any); the `keep` lowest by (total flops, peak, index) are
+  // returned in that order (the first is the search's winner).
   trials = std::max(trials, 0);
   std::vector<std::vector<std::pair<int, int>>> paths(trials + 1);
   std::vector<double> tf(trials + 1, 0.0), tp(trials + 1, 0.0);
@@ -753,10 +755,25 @@ std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_
     }
     score(r + 1);
   });
-  int win = -1;
-  for (int i = 0; i <= trials; ++i)
-    if (ok[i] && (win < 0 || tf[i] < tf[win] || (tf[i] == tf[win] && tp[i] < tp[win]))) win = i;
-  return std::move(paths[win < 0 ? 0 : win]);
+  // order by (total flops, peak, index); candidates the budget rejects go last
+  std::vector<int> order(trials + 1);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (ok[a] != ok[b]) return ok[a] > ok[b];
+    if (tf[a] != tf[b]) return tf[a] < tf[b];
+    return tp[a] < tp[b];
+  });
+  std::vector<std::vector<std::pair<int, int>>> out;
+  for (int k = 0; k < std::max(1, keep) && k <= trials; ++k) {
+    if (!ok[order[k]] && k > 0) break;
+    out.push_back(std::move(paths[order[k]]));
+  }
+  return out;
+}
+
+std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
+                                                  double budget_bytes) {
+  return std::move(partition_candidates(pr, seed, trials, budget_bytes, 1)[0]);
 }
 
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

@@ -85,6 +85,10 @@ std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t*
 // frontier (at most kReconf tensors) is reordered optimally by flops.
 std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
                                                   const std::vector<std::pair<int, int>>& path);
+// The `keep` best partition-search candidates by (total flops, peak, index),
+// best first (at least one: greedy when the budget rejects everything).
+std::vector<std::vector<std::pair<int, int>>> partition_candidates(const PathProblem& pr, uint64_t seed,
+                                                                  int trials, double budget_bytes, int keep);
 std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_t seed, int trials,
                                                   double budget_bytes);
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,

@@ -106,6 +106,15 @@ TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
     op.smax = arena.alloc(1);
     scratch->push_back(op.smax);
     out.smax = op.smax;
+    // the operand's largest |re|, |im| first (its own pass over the input)
+    PlanOp pre = op;
+    pre.pm.maxabs = 1;
+    pre.a_buf = in.buf;
+    pre.a_off = in.off;
+    pre.c_buf = out.buf;
+    pre.c_off = out.off;
+    pre.bytes = 8.0 * p2(op.pm.nb_in);
+    ops.push_back(pre);
   }
   op.a_buf = in.buf;
   op.a_off = in.off;
@@ -311,8 +320,10 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   const bool long_k = Kn > (int64_t(1) << 20);
   // a few outputs over a long contraction: one FP64-accumulated dot product
   // per (m, n) pair of k-contiguous rows (an MFMA tile would mostly idle)
-  const bool dot_mn = !(Mn == 1 && Nn == 1) && Mn * Nn <= 16 && Kn >= (int64_t(1) << 16) &&
-                      Bn * Mn * Nn <= 4096;
+  // batch 1: the skinny kernel reads A and B once for all (m, n)
+  const bool skinny = Bn == 1 && Kn >= (int64_t(1) << 16) && skinny_supported(Mn, Nn);
+  const bool dot_mn = skinny || (!(Mn == 1 && Nn == 1) && Mn * Nn <= 16 && Kn >= (int64_t(1) << 16) &&
+                                 Bn * Mn * Nn <= 4096);
   const bool packable = Kn % 4 == 0 && !long_k && !dot_mn && !(Mn == 1 && Nn == 1);
   if (long_k) prec = TN_PREC_FP32;
   // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
@@ -329,6 +340,22 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     const auto fa = cat({b_o, k_o});
     if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
     if (B.labels != fa) Bp = emit_permute(B, fa, arena, ops, scratch);
+  } else if (skinny) {
+    // either layout of each operand, as found (no permute when it already is one)
+    const auto fa0 = cat({m_o, k_o}), fa1 = cat({k_o, m_o});
+    if (A.labels == fa0) transA = 0;
+    else if (A.labels == fa1) transA = 1;
+    else {
+      transA = kset.count(lowest(A)) ? 0 : 1;
+      Ap = emit_permute(A, transA ? fa1 : fa0, arena, ops, scratch);
+    }
+    const auto fb0 = cat({k_o, n_o}), fb1 = cat({n_o, k_o});
+    if (B.labels == fb0) transB = 0;
+    else if (B.labels == fb1) transB = 1;
+    else {
+      transB = kset.count(lowest(B)) ? 1 : 0;
+      Bp = emit_permute(B, transB ? fb1 : fb0, arena, ops, scratch);
+    }
   } else if (dot_mn) {
     const auto fa = cat({b_o, m_o, k_o}), fb = cat({b_o, n_o, k_o});
     if (A.labels != fa) Ap = emit_permute(A, fa, arena, ops, scratch);
@@ -372,7 +399,10 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.dot_batch = Bn;
     op.dot_m = Mn;
     op.dot_n = Nn;
-    op.work_elems = int64_t((dot_workspace_bytes(Kn, Bn * Mn * Nn) + 7) / 8);
+    op.skinny = skinny ? 1 : 0;
+    op.dot_ta = transA;
+    op.dot_tb = transB;
+    op.work_elems = int64_t(((skinny ? skinny_workspace_bytes(Kn, Mn, Nn) : dot_workspace_bytes(Kn, Bn * Mn * Nn)) + 7) / 8);
     op.work_off = arena.alloc(op.work_elems);
     scratch->push_back(op.work_off);
   } else {
@@ -427,7 +457,10 @@ void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t 
       case OP_APPLY: launch_apply_small(a, b, c, op.ap, s); break;
       case OP_PERMUTE: launch_permute(a, c, op.pm, slot(bufs, op.smax), s); break;
       case OP_GEMM: launch_gemm(a, b, c, op.gm, w, slot(bufs, op.smax_a), slot(bufs, op.smax_b), s); break;
-      case OP_DOT: launch_dot(a, b, c, op.dot_k, op.dot_batch, op.dot_m, op.dot_n, w, s); break;
+      case OP_DOT:
+        if (op.skinny) launch_skinny(a, b, c, op.dot_k, op.dot_m, op.dot_n, op.dot_ta, op.dot_tb, w, s);
+        else launch_dot(a, b, c, op.dot_k, op.dot_batch, op.dot_m, op.dot_n, w, s);
+        break;
     }
   }
 }
@@ -642,6 +675,16 @@ AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, 
   }
   P.work_elems = arena.high_water();
   return P;
+}
+
+double modelled_job_seconds(const AmpPlan& P) {
+  constexpr double kSplitGemm = 350e12, kOther = 120e12, kHbm = 4.0e12, kLaunch = 5e-6;
+  double t = 0;
+  for (const PlanOp& op : P.ops) {
+    const double f = op.kind == OP_GEMM && op.gm.packed ? kSplitGemm : kOther;
+    t += std::max(op.flops / f, op.bytes / kHbm) + kLaunch;
+  }
+  return t;
 }
 
 }  // namespace tn

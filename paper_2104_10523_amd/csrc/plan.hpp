@@ -36,6 +36,8 @@ struct PlanOp {
   GemmDesc gm;
   int64_t dot_k = 0, dot_batch = 0;
   int64_t dot_m = 1, dot_n = 1;   // DOT over all (m, n) row pairs of [b][m][k] x [b][n][k]
+  int skinny = 0;                  // DOT as the skinny long-K GEMM (batch 1), layouts below
+  int dot_ta = 0, dot_tb = 1;      // skinny: transA / transB as for GEMMs
   double flops = 0, bytes = 0;
 };
 
@@ -110,5 +112,10 @@ struct PathData;  // defined in api
 AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, int>>& path,
                            const std::vector<int>& sliced, const std::vector<char>& open_q,
                            int precision);
+
+// Modelled seconds of one job of the plan: the sum over its kernels of
+// max(flops / F, bytes / B) plus a launch latency, F = 350e12 for
+// split-precision GEMMs and 120e12 otherwise, B = 4.0e12 B/s.
+double modelled_job_seconds(const AmpPlan& P);
 
 }  // namespace tn

@@ -74,6 +74,9 @@ CASES = [
     ("gemm_k_beyond_packed_panels", dict(nm=2, nk=21, nn=2)),   # K = 2^21: packed planes would overflow
     ("dot_small_mn", dict(nm=2, nk=17, nn=2)),          # 4 x 4 outputs, K = 2^17: dot per (m, n) pair
     ("dot_small_mn_batch", dict(nb=2, nm=1, nk=16, nn=3)),
+    ("skinny_8x8", dict(nm=3, nk=18, nn=3)),            # 8 x 8 outputs over K = 2^18: skinny kernel
+    ("skinny_16x4", dict(nm=4, nk=17, nn=2)),
+    ("skinny_2x1", dict(nm=1, nk=16, nn=0)),
     ("gemm_batch", dict(nb=3, nm=7, nk=6, nn=6)),
     ("gemm_wide_extents", dict(nm=5, nk=3, nn=6, wide=8)),
     ("outer_product", dict(nm=8, nk=0, nn=6)),
