@@ -630,7 +630,7 @@ def op_kernel_name(precision, k, sh):
     if k == 2:
         return kernel_name(precision, int(sh[4]), int(sh[5]))
     if k == 0:
-        return f"apply_small_kernel<{int(sh[1])}>"
+        return f"{'apply_tile_kernel' if sh[3] else 'apply_small_kernel'}<{int(sh[1])}>"
     if k == 3:
         return f"skinny_partial_kernel<{int(sh[0])}, {int(sh[1])}>" if sh[5] else "dot_partial_kernel"
     np_ = 4 if sh[2] else int(sh[1])

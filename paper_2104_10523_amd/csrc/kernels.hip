@@ -181,8 +181,12 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(const float2* __rest
 // for complex64.  The loads of the next tile are issued before the current
 // tile leaves LDS, so a block keeps 32 KB of reads in flight while it writes.
 // Every per-thread offset inside a tile is the same for all tiles and is
-// computed once.
-constexpr int kPipePad = 2;   // float2 of padding per 64-entry LDS row (keeps 16-byte alignment)
+// computed once.  LDS rows of 64 entries are padded by one float2 (an odd
+// stride of 130 dwords): reads that walk down a column then hit distinct
+// banks.  An even pad (16-byte aligned rows) measured 3.3-3.5 TB/s against
+// 4.8-5.1 TB/s for this layout on 2^30-entry permutations; the price is two
+// 8-byte LDS writes per 16-byte load.
+constexpr int kPipePad = 1;   // float2 of padding per 64-entry LDS row
 __device__ __forceinline__ int pipe_pos(int e) { return e + kPipePad * (e >> 6); }
 
 template <int NP>
@@ -245,7 +249,10 @@ __global__ __launch_bounds__(256) void permute_pipe_kernel(const float2* __restr
   }
   while (true) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(&tile[ld_pos[i]]) = v[i];
+    for (int i = 0; i < 8; ++i) {
+      tile[ld_pos[i]] = make_float2(v[i].x, v[i].y);
+      tile[ld_pos[i] + 1] = make_float2(v[i].z, v[i].w);
+    }
     __syncthreads();
     const int64_t ob = deposit(tau, P.r_out);
     const int64_t nxt = tau + gridDim.x;
@@ -477,6 +484,9 @@ __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(a.y, b.x, acc.y);
 }
 
+// One thread per output row, reading its K values of A in place.  (Staging
+// the block's outputs in LDS for 16-byte stores measured slower for NN = 16,
+// 2.9 against 3.3 TB/s: the extra LDS lowers occupancy to 3 waves per SIMD.)
 template <int NN>
 __global__ __launch_bounds__(256) void apply_small_kernel(const float2* __restrict__ A,
                                                           const float2* __restrict__ B,
@@ -529,6 +539,99 @@ __global__ __launch_bounds__(256) void apply_small_kernel(const float2* __restri
   }
 }
 
+// Variant for the case where the lowest bits of A are K bits (so a thread's
+// row is strided and its direct reads would touch a new 128-byte line per
+// lane) and the 256 rows of a block span one contiguous run of A (every K
+// bit below bit 8 + nk): the block reads that run with coalesced 16-byte
+// loads into LDS (rows of 64 entries padded by one float2), every thread
+// then takes its row's K values from LDS, and the results leave through the
+// same buffer as contiguous 16-byte stores.  Needs KK <= 16, NN <= 16, full
+// 256-row blocks and 16-byte aligned A and C.
+template <int NN>
+__global__ __launch_bounds__(256) void apply_tile_kernel(const float2* __restrict__ A,
+                                                         const float2* __restrict__ B,
+                                                         float2* __restrict__ C, ApplyArgs P) {
+  __shared__ float2 sB[16 * NN];
+  __shared__ int64_t s_koff[16];
+  __shared__ float2 tile[4096 + 64];
+  const int KK = 1 << P.nk;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < KK * NN; idx += 256) {
+    const int k = idx / NN, n = idx % NN;
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if (P.bk[i] >= 0 && ((k >> i) & 1)) off |= int64_t(1) << P.bk[i];
+    for (int i = 0; i < P.nn; ++i)
+      if ((n >> i) & 1) off |= int64_t(1) << P.bn[i];
+    float2 v = make_float2(0.f, 0.f);
+    for (int e = 0; e < (1 << P.n_b_extra); ++e) {
+      int64_t o2 = off;
+      for (int i = 0; i < P.n_b_extra; ++i)
+        if ((e >> i) & 1) o2 |= int64_t(1) << P.b_extra[i];
+      const float2 b = B[o2];
+      v.x += b.x;
+      v.y += b.y;
+    }
+    sB[idx] = v;
+  }
+  if (t < KK) {
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if ((t >> i) & 1) off |= int64_t(1) << P.kpos[i];
+    s_koff[t] = off;
+  }
+  auto expand = [&](int64_t m) {
+    for (int i = 0; i < P.nk; ++i) {
+      const int p = P.kpos[i];
+      m = ((m >> p) << (p + 1)) | (m & ((int64_t(1) << p) - 1));
+    }
+    return m;
+  };
+  auto pos = [](int x) { return x + (x >> 6); };
+  const int lb = int(expand(t));          // this row's offset inside the block's run
+  const int run = 256 * KK;               // entries of A per block
+  __syncthreads();
+  for (int64_t m0 = int64_t(blockIdx.x) * 256; m0 < P.n_rows; m0 += int64_t(gridDim.x) * 256) {
+    const float4* src = reinterpret_cast<const float4*>(A + expand(m0));
+    for (int g = t; g < run / 2; g += 256) {
+      const float4 v = src[g];
+      tile[pos(2 * g)] = make_float2(v.x, v.y);
+      tile[pos(2 * g + 1)] = make_float2(v.z, v.w);
+    }
+    __syncthreads();
+    float2 acc[NN];
+#pragma unroll
+    for (int n = 0; n < NN; ++n) acc[n] = make_float2(0.f, 0.f);
+    for (int k = 0; k < KK; ++k) {
+      const float2 a = tile[pos(lb + int(s_koff[k]))];
+#pragma unroll
+      for (int n = 0; n < NN; ++n) cmac(acc[n], a, sB[k * NN + n]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < NN; ++n) tile[pos(t * NN + n)] = acc[n];
+    __syncthreads();
+    float4* dst = reinterpret_cast<float4*>(C + m0 * NN);
+    for (int g = t; g < 128 * NN; g += 256) {
+      const float2 x0 = tile[pos(2 * g)], x1 = tile[pos(2 * g + 1)];
+      dst[g] = make_float4(x0.x, x0.y, x1.x, x1.y);
+    }
+    __syncthreads();
+  }
+}
+
+// The LDS-tiled apply: lowest A bit is a K bit, every K bit below 8 + nk
+// (a block's 256 rows are one run of A), KK <= 16, full blocks, and 16-byte
+// aligned A and C (the plan's buffers are).
+bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C) {
+  if (d.nk < 1 || d.nk > 4 || d.kpos[0] != 0 || d.a_bits - d.nk < 8) return false;
+  for (int i = 0; i < d.nk; ++i)
+    if (d.kpos[i] >= 8 + d.nk) return false;
+  if (A && (reinterpret_cast<uintptr_t>(A) & 15)) return false;
+  if (C && (reinterpret_cast<uintptr_t>(C) & 15)) return false;
+  return true;
+}
+
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
                         hipStream_t s) {
   TN_REQUIRE(d.nk >= 0 && d.nk <= 6 && d.nn >= 0 && d.nn <= 4 && d.n_b_extra <= 12,
@@ -547,6 +650,17 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
   for (int i = 0; i < 12; ++i) P.b_extra[i] = d.b_extra[i];
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
   const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
+  if (apply_tiled_ok(d, A, C)) {
+    switch (1 << d.nn) {
+      case 1: apply_tile_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 2: apply_tile_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 4: apply_tile_kernel<4><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 8: apply_tile_kernel<8><<<g, b, 0, s>>>(A, B, C, P); break;
+      default: apply_tile_kernel<16><<<g, b, 0, s>>>(A, B, C, P); break;
+    }
+    TN_HIP(hipGetLastError());
+    return;
+  }
   switch (1 << d.nn) {
     case 1: apply_small_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
     case 2: apply_small_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;

@@ -52,6 +52,9 @@ struct ApplySmallDesc {
 };
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
                         hipStream_t s);
+// Whether launch_apply_small runs apply_tile_kernel (A and C may be NULL:
+// then alignment is assumed, as for the plan's buffers).
+bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C);
 
 // Complex GEMM C[b][m][n] = sum_k A[b](m,k) * B[b](k,n), contiguous operands.
 // transA = 0: A[b][m][k]; 1: A[b][k][m].  transB = 0: B[b][k][n]; 1: B[b][n][k].

@@ -107,6 +107,17 @@ def test_contract_pair(gpu, workspace, name, kw, precision):
     assert err <= tol, (name, precision, err)
 
 
+@pytest.mark.parametrize("nk,nn", [(1, 0), (2, 2), (3, 3), (4, 4), (4, 2)])
+def test_contract_pair_apply_low_k_bits(gpu, workspace, nk, nn):
+    """A small operand contracted over A's lowest labels (the K bits sit
+    below every M bit): the LDS-tiled apply kernel reads each block's rows as
+    one contiguous run."""
+    A, la, B, lb, lc, shape_c = make_case(60 + 7 * nk + nn, nm=12, nk=nk, nn=nn, shuffle=False)
+    got = run(A, la, B, lb, lc, shape_c, "fp32")
+    ref = oracle_pair(A.astype(np.complex128), la, B.astype(np.complex128), lb, lc)
+    assert l2_rel(got, ref) <= 2e-6
+
+
 def test_contract_pair_unshuffled_orders(gpu, workspace):
     """Operands already in GEMM order (no permutation kernels)."""
     A, la, B, lb, lc, shape_c = make_case(7, nm=8, nk=6, nn=7, shuffle=False)
