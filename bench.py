@@ -90,6 +90,9 @@ def parse():
     ap.add_argument("--rank", default="time", choices=["time", "flops"],
                     help="partition search: re-rank the best candidates by modelled kernel time (default) "
                          "or keep the flop-minimal tree")
+    ap.add_argument("--validate", type=int, default=4,
+                    help="(bit-string, slice) jobs also run at the FP64 validation precision; the line reports "
+                         "the benchmark precision's and FP32's error against them")
     ap.add_argument("--profile-steps", type=int, default=1,
                     help="jobs run once more with HIP events around every kernel, after the timed region")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -761,6 +764,34 @@ def main():
                                                              np.maximum(np.abs(a32), 2.0 ** (-(n + path.cost.n_sliced) / 2)))),
                 "slice_amplitude_over_floor": float(np.min(np.abs(a32)) / 2.0 ** (-(n + path.cost.n_sliced) / 2))}
         print(f"# fp32 step {T32:.3f}s", file=sys.stderr, flush=True)
+    val = None
+    if a.validate > 0:
+        # jobs on distinct random slices: benchmark precision and FP32 first,
+        # then the timing workspace is released for the FP64 one (2x larger)
+        vjobs = [(int(rows[j % 64]), int(x)) for j, x in
+                 enumerate(rng.choice(int(ns), size=min(a.validate, int(ns)), replace=False))]
+        va = np.array([run_graph(net, path, bits[[b]], sl, a.precision)[0][0] for b, sl in vjobs])
+        v32 = np.array([run_graph(net, path, bits[[b]], sl, "fp32")[0][0] for b, sl in vjobs])
+        tn.tn_set_workspace(None)
+        del ws
+        torch.cuda.empty_cache()
+        need64 = tn.tn_amplitudes_workspace(net, path, 1, "fp64")
+        ws = torch.empty(need64, dtype=torch.uint8, device="cuda")
+        tn.tn_set_workspace(ws)
+        t64 = time.perf_counter()
+        v64 = np.array([run_graph(net, path, bits[[b]], sl, "fp64")[0][0] for b, sl in vjobs])
+        t64 = (time.perf_counter() - t64) / len(vjobs)
+        floor = 2.0 ** (-(n + path.cost.n_sliced) / 2)
+        den = np.maximum(np.abs(v64), floor)
+        val = {"jobs": [[b, sl] for b, sl in vjobs], "floor": floor,
+               "amplitude_over_floor": [float(x) for x in np.abs(v64) / floor],
+               f"{a.precision}_floored_err": [float(x) for x in np.abs(va - v64) / den],
+               "fp32_floored_err": [float(x) for x in np.abs(v32 - v64) / den],
+               f"{a.precision}_max": float(np.max(np.abs(va - v64) / den)),
+               "fp32_max": float(np.max(np.abs(v32 - v64) / den)),
+               "fp64_seconds_per_job": t64, "fp64_workspace_gib": need64 / 2 ** 30}
+        print(f"# fp64 validation: {a.precision} max {val[a.precision + '_max']:.2e}, fp32 max {val['fp32_max']:.2e} "
+              f"({t64:.2f} s per fp64 job)", file=sys.stderr, flush=True)
     cpu = None
     if not a.no_cpu:
         from oracle.network import build_network
@@ -815,6 +846,7 @@ def main():
                      "note": "kernel = the kernel with the largest share of a step (HIP events around every "
                              "op of the profiled jobs that follow the timed graph replays)"},
         "fp32_comparison": fp32,
+        "fp64_validation": val,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -289,14 +289,18 @@ enum { TN_C64 = 0, TN_C128 = 1 };
  * FP32 elsewhere.  At every precision, a contraction longer than 2^20 runs on
  * the FP32 kernel (split-K chains of at most 4096, partials summed in FP64),
  * and one with at most 16 outputs per batch entry and K >= 2^16 as FP64
- * dot products. */
+ * dot products.  FP64 is the validation precision: every tensor is
+ * complex128 (leaves from the FP64 gate matrices, FP64 multiply-adds
+ * throughout, twice the workspace), so other precisions' results can be
+ * compared with it on the device; tn_contract_pair takes it for TN_C128
+ * tensors (and only those). */
 enum { TN_PREC_FP32 = 0, TN_PREC_BF16X3 = 1, TN_PREC_BF16X6 = 2,
-       TN_PREC_AUTO = 3, TN_PREC_F16X3 = 4 };
+       TN_PREC_AUTO = 3, TN_PREC_F16X3 = 4, TN_PREC_FP64 = 5 };
 
 typedef struct {
   void* data;                 /* device pointer, row-major, caller-owned    */
   int32_t rank;               /* 0 .. 64                                    */
-  int32_t dtype;              /* TN_C64 (TN_C128 -> TN_ERR_UNSUPPORTED)     */
+  int32_t dtype;              /* TN_C64, or TN_C128 with TN_PREC_FP64       */
   const int64_t* extents;     /* host array of `rank` extents (>= 1)        */
 } tn_tensor;
 

@@ -172,10 +172,10 @@ def tn_set_workspace(buf) -> None:
 
 def _tensor(t, extents=None) -> tuple:
     import torch
-    assert t.dtype == torch.complex64 and t.is_cuda and t.is_contiguous()
+    assert t.dtype in (torch.complex64, torch.complex128) and t.is_cuda and t.is_contiguous()
     ext = list(t.shape) if extents is None else list(extents)
     arr = (C.c_int64 * max(len(ext), 1))(*ext)
-    T = TnTensor(C.c_void_p(t.data_ptr()), len(ext), 0, arr)
+    T = TnTensor(C.c_void_p(t.data_ptr()), len(ext), 0 if t.dtype == torch.complex64 else 1, arr)
     return T, arr
 
 

@@ -21,7 +21,7 @@ GATE_IDS = {
     "custom1": 40, "custom2": 41, "depol1": 60, "depol2": 61, "amp_damp": 62,
 }
 
-PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3, "f16x3": 4}
+PREC = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3, "f16x3": 4, "fp64": 5}
 PATH_ALGO = {"greedy": 0, "random_greedy": 1, "learned": 2, "partition": 3}
 PAULI = {"I": 0, "X": 1, "Y": 2, "Z": 3}
 

@@ -45,8 +45,13 @@ float2* device_one() {
   if (it != g_one.end()) return it->second;
   float2* p = nullptr;
   TN_HIP(hipMalloc(&p, 256));
+  // 1 + 0i as complex64 at byte 0 and as complex128 at byte 16
+  unsigned char host[32] = {};
   const float2 one = make_float2(1.f, 0.f);
-  TN_HIP(hipMemcpy(p, &one, sizeof(one), hipMemcpyHostToDevice));
+  const double2 one64 = make_double2(1.0, 0.0);
+  std::memcpy(host, &one, sizeof(one));
+  std::memcpy(host + 16, &one64, sizeof(one64));
+  TN_HIP(hipMemcpy(p, host, sizeof(host), hipMemcpyHostToDevice));
   g_one[d] = p;
   return p;
 }
@@ -116,7 +121,7 @@ WsLayout ws_layout(const AmpPlan& P, int64_t n_bs) {
   L.flag = o; o += 256;
   L.bits = o; o += align256(size_t(n_bs) * size_t(P.n_qubits));
   L.descs = o; o += align256(P.leaves.size() * sizeof(LeafDesc));
-  L.leaves = o; o += align256(size_t(P.leaf_elems) * sizeof(float2));
+  L.leaves = o; o += align256(size_t(P.leaf_elems) * (P.precision == TN_PREC_FP64 ? sizeof(double2) : sizeof(float2)));
   L.work = o; o += align256(size_t(P.work_elems) * sizeof(float2));
   L.total = o;
   return L;
@@ -138,6 +143,22 @@ float2* upload_leaves(tn_network* n) {
   return dptr;
 }
 
+double2* upload_leaves64(tn_network* n) {
+  const int d = current_device();
+  std::lock_guard<std::mutex> lk(n->mu);
+  auto it = n->dev_full64.find(d);
+  if (it != n->dev_full64.end()) return it->second;
+  std::vector<double2> host;
+  for (const auto& t : n->net.tensors)
+    for (const cd& v : t.data) host.push_back(make_double2(v.real(), v.imag()));
+  if (host.empty()) host.push_back(make_double2(0.0, 0.0));
+  double2* dptr = nullptr;
+  TN_HIP(hipMalloc(&dptr, host.size() * sizeof(double2)));
+  TN_HIP(hipMemcpy(dptr, host.data(), host.size() * sizeof(double2), hipMemcpyHostToDevice));
+  n->dev_full64[d] = dptr;
+  return dptr;
+}
+
 // Expands user labels into one-bit labels (extent 2^e -> e bits, most
 // significant first); label id * 64 + bit.
 std::vector<int> bit_labels(const tn_tensor* T, const int32_t* modes, std::map<int32_t, int>& ids,
@@ -145,7 +166,6 @@ std::vector<int> bit_labels(const tn_tensor* T, const int32_t* modes, std::map<i
   TN_REQUIRE(T->rank >= 0 && T->rank <= 64, TN_ERR_ARG, "rank out of range");
   TN_REQUIRE(T->rank == 0 || (modes && T->extents), TN_ERR_ARG, "null modes or extents");
   TN_REQUIRE(T->dtype == TN_C64 || T->dtype == TN_C128, TN_ERR_ARG, "bad dtype");
-  TN_REQUIRE(T->dtype == TN_C64, TN_ERR_UNSUPPORTED, "complex128 tensors are not supported on the GPU path");
   std::set<int32_t> seen;
   std::vector<int> out;
   for (int i = 0; i < T->rank; ++i) {
@@ -177,7 +197,7 @@ PairPlan compile_contract_pair(const tn_tensor* A, const int32_t* modesA, const 
                                const int32_t* modesB, const tn_tensor* C, const int32_t* modesC,
                                int32_t precision) {
   TN_REQUIRE(A && B && C, TN_ERR_ARG, "null tensor");
-  TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+  TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
   std::map<int32_t, int> ids;
   std::map<int32_t, int64_t> ext;
   TRef X, Y;
@@ -194,6 +214,9 @@ PairPlan compile_contract_pair(const tn_tensor* A, const int32_t* modesA, const 
   TN_REQUIRE(ids.size() == ids_in.size(), TN_ERR_MODES, "output label not in A or B");
   for (auto& kv : ext_in) TN_REQUIRE(ext[kv.first] == kv.second, TN_ERR_EXTENT, "label extents differ");
   TN_REQUIRE(A->data && B->data && C->data, TN_ERR_ARG, "null data pointer");
+  TN_REQUIRE(A->dtype == B->dtype && B->dtype == C->dtype, TN_ERR_ARG, "tensors of different dtypes");
+  TN_REQUIRE((A->dtype == TN_C128) == (precision == TN_PREC_FP64), TN_ERR_ARG,
+             "complex128 tensors go with TN_PREC_FP64 and only they do");
   Arena arena;
   PairPlan pp;
   std::vector<int64_t> scratch;
@@ -283,7 +306,7 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
       if (o->rank == TN_RANK_FLOPS) {
         pairs = partition_search(pr, o->seed, o->trials, o->mem_budget_bytes);
       } else {
-        TN_REQUIRE(o->rank_precision >= TN_PREC_FP32 && o->rank_precision <= TN_PREC_F16X3, TN_ERR_ARG,
+        TN_REQUIRE(o->rank_precision >= TN_PREC_FP32 && o->rank_precision <= TN_PREC_FP64, TN_ERR_ARG,
                    "bad rank precision");
         auto cands = partition_candidates(pr, o->seed, o->trials, o->mem_budget_bytes, 16);
         int best = -1;
@@ -369,7 +392,7 @@ tn_status tn_amplitudes_workspace(const tn_network* n, const tn_path* p, int64_t
                                   int32_t precision, size_t* bytes) {
   return guarded([&] {
     TN_REQUIRE(n && p && bytes && n_bs >= 1, TN_ERR_ARG, "bad argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     *bytes = ws_layout(*plan, n_bs).total;
   });
@@ -383,7 +406,7 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
     TN_REQUIRE(n && p && bits && out && n_bs >= 1, TN_ERR_ARG, "bad argument");
     tn_exec_opts o{TN_PREC_FP32, 0, 0, -1, 0, 0, nullptr};
     if (opts) o = *opts;
-    TN_REQUIRE(o.precision >= TN_PREC_FP32 && o.precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(o.precision >= TN_PREC_FP32 && o.precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
     const int nq = n->net.n_qubits;
     TN_REQUIRE(int(p->open_q.size()) == nq, TN_ERR_ARG, "path belongs to another network");
     for (int64_t b = 0; b < n_bs; ++b)
@@ -406,7 +429,9 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
                "workspace too small: need " + std::to_string(L.total) + " bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws.ptr);
-    float2* full = upload_leaves(n);
+    const bool f64 = P.precision == TN_PREC_FP64;
+    float2* full = f64 ? nullptr : upload_leaves(n);
+    double2* full64 = f64 ? upload_leaves64(n) : nullptr;
     int64_t ctl[3] = {0, sbeg, scount};
     TN_HIP(hipMemcpyAsync(base + L.ctl, ctl, sizeof(ctl), hipMemcpyHostToDevice, s));
     TN_HIP(hipMemsetAsync(base + L.flag, 0, 4, s));
@@ -420,12 +445,21 @@ tn_status tn_amplitudes(const tn_network* n_, const tn_path* p_, const int8_t* b
                        nullptr, nullptr, nullptr, device_one()};
     const int64_t jobs = n_bs * scount;
     auto one_job = [&]() {
-      launch_gather_leaves(full, bufs[BUF_LEAF], reinterpret_cast<const LeafDesc*>(base + L.descs),
-                           int(P.leaves.size()), P.max_leaf_bits, reinterpret_cast<const int8_t*>(base + L.bits),
-                           nq, dctl, s);
+      const LeafDesc* descs = reinterpret_cast<const LeafDesc*>(base + L.descs);
+      const int8_t* dbits = reinterpret_cast<const int8_t*>(base + L.bits);
+      if (f64)
+        launch_gather_leaves(full64, reinterpret_cast<double2*>(bufs[BUF_LEAF]), descs, int(P.leaves.size()),
+                             P.max_leaf_bits, dbits, nq, dctl, s);
+      else
+        launch_gather_leaves(full, bufs[BUF_LEAF], descs, int(P.leaves.size()), P.max_leaf_bits, dbits, nq,
+                             dctl, s);
       run_ops(P.ops, bufs, s);
-      launch_accumulate(bufs[P.final_buf] + P.final_off, static_cast<double2*>(out), P.final_bits,
-                        P.final_pos, dctl, o.accumulate, s);
+      if (f64)
+        launch_accumulate(reinterpret_cast<const double2*>(bufs[P.final_buf] + P.final_off),
+                          static_cast<double2*>(out), P.final_bits, P.final_pos, dctl, o.accumulate, s);
+      else
+        launch_accumulate(bufs[P.final_buf] + P.final_off, static_cast<double2*>(out), P.final_bits,
+                          P.final_pos, dctl, o.accumulate, s);
     };
     const bool profile = o.op_seconds != nullptr;
     if (profile) {
@@ -542,7 +576,7 @@ tn_status tn_amplitudes_autotune(const tn_network* n_, const tn_path* p_, int32_
     auto* n = const_cast<tn_network*>(n_);
     auto* p = const_cast<tn_path*>(p_);
     TN_REQUIRE(n && p && reps >= 1, TN_ERR_ARG, "bad argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(n, p, precision);
     const WsLayout L = ws_layout(*plan, 1);
     const Workspace ws = get_ws();
@@ -560,7 +594,7 @@ tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p, int32_t
                                   tn_plan_info* info) {
   return guarded([&] {
     TN_REQUIRE(n && p && info, TN_ERR_ARG, "null argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     std::memset(info, 0, sizeof(*info));
     info->n_ops = int32_t(plan->ops.size());
@@ -578,7 +612,7 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
                                  int32_t* kind, double* flops, double* bytes, int64_t* shape) {
   return guarded([&] {
     TN_REQUIRE(n && p, TN_ERR_ARG, "null argument");
-    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_F16X3, TN_ERR_ARG, "bad precision");
+    TN_REQUIRE(precision >= TN_PREC_FP32 && precision <= TN_PREC_FP64, TN_ERR_ARG, "bad precision");
     auto plan = get_plan(const_cast<tn_network*>(n), const_cast<tn_path*>(p), precision);
     for (size_t k = 0; k < plan->ops.size(); ++k) {
       const PlanOp& op = plan->ops[k];
@@ -594,9 +628,9 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
         r[7] = 0;
         if (op.kind == OP_GEMM) {
           r[0] = op.gm.M; r[1] = op.gm.N; r[2] = op.gm.K; r[3] = op.gm.batch;
-          r[4] = gemm_tile_of(op.gm);
+          r[4] = op.f64 ? -1 : gemm_tile_of(op.gm);
           r[5] = op.gm.packed;
-          r[6] = gemm_dispatches(op.gm);
+          r[6] = op.f64 ? 1 : gemm_dispatches(op.gm);
         } else if (op.kind == OP_APPLY) {
           r[0] = int64_t(1) << (op.ap.a_bits - op.ap.nk);
           r[1] = int64_t(1) << op.ap.nn;

@@ -14,15 +14,18 @@
 struct tn_network {
   tn::Network net;
   std::mutex mu;
-  std::map<int, float2*> dev_full;  // per device: all leaves, complex64
+  std::map<int, float2*> dev_full;     // per device: all leaves, complex64
+  std::map<int, double2*> dev_full64;  // per device: all leaves, complex128 (FP64 plans)
   ~tn_network() {
-    for (auto& kv : dev_full) {
+    auto release = [](int dev, void* p) {
       int cur = 0;
-      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(kv.first) == hipSuccess) {
-        (void)hipFree(kv.second);
+      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(dev) == hipSuccess) {
+        (void)hipFree(p);
         (void)hipSetDevice(cur);
       }
-    }
+    };
+    for (auto& kv : dev_full) release(kv.first, kv.second);
+    for (auto& kv : dev_full64) release(kv.first, kv.second);
   }
 };
 

@@ -1830,8 +1830,9 @@ void launch_advance_job(int64_t* ctl, hipStream_t s) {
   TN_HIP(hipGetLastError());
 }
 
-__global__ __launch_bounds__(256) void gather_leaves_kernel(const float2* __restrict__ full,
-                                                            float2* __restrict__ arena,
+template <typename T>
+__global__ __launch_bounds__(256) void gather_leaves_kernel(const T* __restrict__ full,
+                                                            T* __restrict__ arena,
                                                             const LeafDesc* __restrict__ descs,
                                                             const int8_t* __restrict__ bits,
                                                             int n_qubits,
@@ -1855,13 +1856,25 @@ __global__ __launch_bounds__(256) void gather_leaves_kernel(const float2* __rest
   }
 }
 
+template <typename T>
+static void gather_leaves(const T* full, T* arena, const LeafDesc* descs, int n_leaves, int max_out,
+                          const int8_t* bits, int n_qubits, const int64_t* ctl, hipStream_t s) {
+  if (n_leaves == 0) return;
+  const int threads = std::min(256, std::max(64, 1 << max_out));
+  gather_leaves_kernel<T><<<dim3(n_leaves), dim3(threads), 0, s>>>(full, arena, descs, bits, n_qubits, ctl);
+  TN_HIP(hipGetLastError());
+}
+
 void launch_gather_leaves(const float2* full, float2* arena, const LeafDesc* descs, int n_leaves,
                           int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
                           hipStream_t s) {
-  if (n_leaves == 0) return;
-  const int threads = std::min(256, std::max(64, 1 << max_out));
-  gather_leaves_kernel<<<dim3(n_leaves), dim3(threads), 0, s>>>(full, arena, descs, bits, n_qubits, ctl);
-  TN_HIP(hipGetLastError());
+  gather_leaves(full, arena, descs, n_leaves, max_out, bits, n_qubits, ctl, s);
+}
+
+void launch_gather_leaves(const double2* full, double2* arena, const LeafDesc* descs, int n_leaves,
+                          int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
+                          hipStream_t s) {
+  gather_leaves(full, arena, descs, n_leaves, max_out, bits, n_qubits, ctl, s);
 }
 
 struct AccArgs {
@@ -1870,7 +1883,8 @@ struct AccArgs {
   int8_t pos[kMaxBits];
 };
 
-__global__ __launch_bounds__(256) void accumulate_kernel(const float2* __restrict__ R,
+template <typename T>
+__global__ __launch_bounds__(256) void accumulate_kernel(const T* __restrict__ R,
                                                          double2* __restrict__ out, AccArgs P,
                                                          const int64_t* __restrict__ ctl) {
   const int64_t job = ctl[0], scount = ctl[2];
@@ -1882,7 +1896,7 @@ __global__ __launch_bounds__(256) void accumulate_kernel(const float2* __restric
     int64_t src = 0;
     for (int j = 0; j < P.nbits; ++j)
       if ((i >> j) & 1) src |= int64_t(1) << P.pos[j];
-    const float2 v = R[src];
+    const T v = R[src];
     double2 r = make_double2(double(v.x), double(v.y));
     if (add) {
       r.x += o[i].x;
@@ -1892,8 +1906,9 @@ __global__ __launch_bounds__(256) void accumulate_kernel(const float2* __restric
   }
 }
 
-void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* pos_of_bit,
-                       const int64_t* ctl, int accumulate, hipStream_t s) {
+template <typename T>
+static void accumulate(const T* R, double2* out, int nbits, const int8_t* pos_of_bit, const int64_t* ctl,
+                       int accumulate, hipStream_t s) {
   AccArgs P;
   std::memset(&P, 0, sizeof(P));
   P.nbits = nbits;
@@ -1901,8 +1916,18 @@ void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* p
   for (int j = 0; j < nbits; ++j) P.pos[j] = pos_of_bit[j];
   const int64_t n = int64_t(1) << nbits;
   const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
-  accumulate_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(R, out, P, ctl);
+  accumulate_kernel<T><<<dim3(unsigned(blocks)), 256, 0, s>>>(R, out, P, ctl);
   TN_HIP(hipGetLastError());
+}
+
+void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* pos_of_bit,
+                       const int64_t* ctl, int acc, hipStream_t s) {
+  accumulate(R, out, nbits, pos_of_bit, ctl, acc, s);
+}
+
+void launch_accumulate(const double2* R, double2* out, int nbits, const int8_t* pos_of_bit,
+                       const int64_t* ctl, int acc, hipStream_t s) {
+  accumulate(R, out, nbits, pos_of_bit, ctl, acc, s);
 }
 
 __global__ void nonfinite_kernel(const double2* __restrict__ x, int64_t n, int* flag) {

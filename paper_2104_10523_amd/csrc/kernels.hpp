@@ -103,11 +103,16 @@ struct LeafDesc {
 void launch_gather_leaves(const float2* full, float2* arena, const LeafDesc* descs, int n_leaves,
                           int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
                           hipStream_t s);
+void launch_gather_leaves(const double2* full, double2* arena, const LeafDesc* descs, int n_leaves,
+                          int max_out, const int8_t* bits, int n_qubits, const int64_t* ctl,
+                          hipStream_t s);
 void launch_set_job(int64_t* ctl, int64_t job, hipStream_t s);
 void launch_advance_job(int64_t* ctl, hipStream_t s);
 
 // out[b][i] (complex128) (+)= R[gather(i)]; b = job / slice_count.
 void launch_accumulate(const float2* R, double2* out, int nbits, const int8_t* pos_of_bit,
+                       const int64_t* ctl, int accumulate_first, hipStream_t s);
+void launch_accumulate(const double2* R, double2* out, int nbits, const int8_t* pos_of_bit,
                        const int64_t* ctl, int accumulate_first, hipStream_t s);
 
 // Dot products (M = N = 1) with split-K; result written as complex64.
@@ -126,5 +131,14 @@ void launch_dot(const float2* A, const float2* B, float2* C, int64_t K, int64_t 
 
 // Sets *flag to 1 if any entry of x is non-finite.
 void launch_nonfinite(const double2* x, int64_t n, int* flag, hipStream_t s);
+
+// Complex128 (validation precision TN_PREC_FP64) counterparts, same
+// addressing as the complex64 launches (kernels64.hip).
+void launch_apply64(const double2* A, const double2* B, double2* C, const ApplySmallDesc& d, hipStream_t s);
+void launch_permute64(const double2* in, double2* out, const PermuteDesc& d, hipStream_t s);
+void launch_gemm64(const double2* A, const double2* B, double2* C, const GemmDesc& g, hipStream_t s);
+size_t dot64_workspace_bytes(int64_t K, int64_t outs);
+void launch_dot64(const double2* A, const double2* B, double2* C, int64_t K, int64_t batch, int64_t m, int64_t n,
+                  int transA, int transB, void* work, hipStream_t s);
 
 }  // namespace tn

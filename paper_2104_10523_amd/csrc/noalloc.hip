@@ -19,7 +19,9 @@ constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
 // pass these names to a kernel or a copy: they are host-side stand-ins; the
 // device addresses come from hipGetSymbolAddress below.
 static __device__ __align__(256) unsigned char scratch[tn::kNoAllocScratchBytes];
-static __device__ __align__(256) float scratch_one[2] = {1.0f, 0.0f};
+// 1 + 0i as complex64 at byte 0 and as complex128 at byte 16 (IEEE bits,
+// little-endian words)
+static __device__ __align__(256) unsigned int scratch_one[8] = {0x3f800000u, 0u, 0u, 0u, 0u, 0x3ff00000u, 0u, 0u};
 
 namespace tn {
 namespace {

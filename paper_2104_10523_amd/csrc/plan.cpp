@@ -48,6 +48,9 @@ void Arena::release(int64_t off) {
 
 namespace {
 
+// complex128 plans (TN_PREC_FP64): tensors take two float2 slots per entry
+thread_local int g_esz = 1;
+
 int pos_of(const std::vector<int>& layout, int label) {
   const auto it = std::find(layout.begin(), layout.end(), label);
   if (it == layout.end()) return -1;
@@ -99,7 +102,7 @@ TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
   } else {
     out.buf = BUF_WORK;
     const int64_t elems = int64_t(1) << op.pm.nb;
-    out.off = arena.alloc(np ? (elems * np + 1) / 2 : elems);
+    out.off = arena.alloc(np ? (elems * np + 1) / 2 : elems * g_esz);
     scratch->push_back(out.off);
   }
   if (f16) {
@@ -148,7 +151,7 @@ TRef emit_sum_out(const TRef& X, const std::vector<int>& dang, Arena& arena,
   TRef out;
   out.labels = filter(X.labels, std::set<int>(dang.begin(), dang.end()), false);
   out.buf = BUF_WORK;
-  out.off = arena.alloc(int64_t(1) << out.labels.size());
+  out.off = arena.alloc((int64_t(1) << out.labels.size()) * g_esz);
   scratch->push_back(out.off);
   op.a_buf = X.buf;
   op.a_off = X.off;
@@ -169,9 +172,10 @@ int resolve_precision(int precision, int64_t M, int64_t N, int64_t K) {
 
 }  // namespace
 
-TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v,
-                  const std::vector<int>* want, int want_buf, int64_t want_off, Arena& arena,
-                  int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch) {
+namespace {
+TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v,
+                       const std::vector<int>* want, int want_buf, int64_t want_off, Arena& arena,
+                       int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch) {
   const std::set<int> keep(keep_v.begin(), keep_v.end());
   TRef X = X0, Y = Y0;
   {
@@ -246,7 +250,7 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
       out.off = want_off;
     } else {
       out.buf = BUF_WORK;
-      out.off = arena.alloc(int64_t(1) << out.labels.size());
+      out.off = arena.alloc((int64_t(1) << out.labels.size()) * g_esz);
       if (want) scratch->push_back(out.off);
     }
     op.a_buf = big.buf;
@@ -325,7 +329,7 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   const bool dot_mn = skinny || (!(Mn == 1 && Nn == 1) && Mn * Nn <= 16 && Kn >= (int64_t(1) << 16) &&
                                  Bn * Mn * Nn <= 4096);
   const bool packable = Kn % 4 == 0 && !long_k && !dot_mn && !(Mn == 1 && Nn == 1);
-  if (long_k) prec = TN_PREC_FP32;
+  if (long_k && prec != TN_PREC_FP64) prec = TN_PREC_FP32;
   // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
   if (prec == TN_PREC_F16X3 && !packable) prec = TN_PREC_FP32;
   const bool packed = (prec == TN_PREC_BF16X3 || prec == TN_PREC_BF16X6 || prec == TN_PREC_F16X3) && packable;
@@ -383,7 +387,7 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     out.off = want_off;
   } else {
     out.buf = BUF_WORK;
-    out.off = arena.alloc(Bn * Mn * Nn);
+    out.off = arena.alloc(Bn * Mn * Nn * g_esz);
     if (want) scratch->push_back(out.off);
   }
   PlanOp op;
@@ -400,9 +404,13 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
     op.dot_m = Mn;
     op.dot_n = Nn;
     op.skinny = skinny ? 1 : 0;
-    op.dot_ta = transA;
-    op.dot_tb = transB;
-    op.work_elems = int64_t(((skinny ? skinny_workspace_bytes(Kn, Mn, Nn) : dot_workspace_bytes(Kn, Bn * Mn * Nn)) + 7) / 8);
+    // operand layouts: chosen freely on the skinny branch, else [b][m][k] x [b][n][k]
+    op.dot_ta = skinny ? transA : 0;
+    op.dot_tb = skinny ? transB : 1;
+    const size_t wbytes = prec == TN_PREC_FP64 ? dot64_workspace_bytes(Kn, Bn * Mn * Nn)
+                          : skinny             ? skinny_workspace_bytes(Kn, Mn, Nn)
+                                               : dot_workspace_bytes(Kn, Bn * Mn * Nn);
+    op.work_elems = int64_t((wbytes + 7) / 8);
     op.work_off = arena.alloc(op.work_elems);
     scratch->push_back(op.work_off);
   } else {
@@ -441,14 +449,66 @@ TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v
   return out;
 }
 
+}  // namespace
+
+TRef compile_pair(const TRef& X0, const TRef& Y0, const std::vector<int>& keep_v,
+                  const std::vector<int>* want, int want_buf, int64_t want_off, Arena& arena,
+                  int precision, std::vector<PlanOp>& ops, std::vector<int64_t>* scratch) {
+  const bool f64 = precision == TN_PREC_FP64;
+  const size_t first = ops.size();
+  const int saved = g_esz;
+  g_esz = f64 ? 2 : 1;
+  TRef r;
+  try {
+    r = compile_pair_impl(X0, Y0, keep_v, want, want_buf, want_off, arena, precision, ops, scratch);
+  } catch (...) {
+    g_esz = saved;
+    throw;
+  }
+  g_esz = saved;
+  if (f64)
+    for (size_t k = first; k < ops.size(); ++k) {
+      ops[k].f64 = 1;
+      ops[k].bytes *= 2.0;      // 16-byte entries
+    }
+  return r;
+}
+
 namespace {
 uint32_t* slot(float2* const bufs[6], int64_t off) {
   return off >= 0 ? reinterpret_cast<uint32_t*>(bufs[BUF_WORK] + off) : nullptr;
 }
 }  // namespace
 
+namespace {
+void run_op64(const PlanOp& op, float2* const bufs[6], hipStream_t s) {
+  auto d2 = [&](int buf, int64_t off) {
+    // the constant one buffer holds 1+0i as complex64 at byte 0 and as
+    // complex128 at byte 16
+    if (buf == BUF_ONE) return reinterpret_cast<double2*>(reinterpret_cast<char*>(bufs[BUF_ONE]) + 16);
+    return reinterpret_cast<double2*>(bufs[buf] + off);
+  };
+  const double2* a = d2(op.a_buf, op.a_off);
+  const double2* b = d2(op.b_buf, op.b_off);
+  double2* c = d2(op.c_buf, op.c_off);
+  void* w = op.work_off >= 0 ? static_cast<void*>(bufs[BUF_WORK] + op.work_off) : nullptr;
+  switch (op.kind) {
+    case OP_APPLY: launch_apply64(a, b, c, op.ap, s); break;
+    case OP_PERMUTE: launch_permute64(a, c, op.pm, s); break;
+    case OP_GEMM: launch_gemm64(a, b, c, op.gm, s); break;
+    case OP_DOT:
+      launch_dot64(a, b, c, op.dot_k, op.dot_batch, op.dot_m, op.dot_n, op.dot_ta, op.dot_tb, w, s);
+      break;
+  }
+}
+}  // namespace
+
 void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s) {
   for (const PlanOp& op : ops) {
+    if (op.f64) {
+      run_op64(op, bufs, s);
+      continue;
+    }
     const float2* a = bufs[op.a_buf] + op.a_off;
     const float2* b = bufs[op.b_buf] + op.b_off;
     float2* c = bufs[op.c_buf] + op.c_off;
@@ -494,7 +554,7 @@ void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hip
   std::map<TileKey, int> done;
   try {
     for (PlanOp& op : ops) {
-      if (op.kind != OP_GEMM) continue;
+      if (op.kind != OP_GEMM || op.f64) continue;
       auto it = done.find(key_of(op.gm));
       if (it != done.end()) {
         op.gm.tile = it->second;
@@ -607,7 +667,7 @@ AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, 
     P.max_leaf_bits = std::max(P.max_leaf_bits, d.out_bits);
     P.leaves.push_back(d);
     refs[i].buf = BUF_LEAF;
-    refs[i].off = d.dst_off;
+    refs[i].off = d.dst_off * (precision == TN_PREC_FP64 ? 2 : 1);   // float2 slots
     refs[i].labels = red;
   }
 
@@ -637,7 +697,12 @@ AmpPlan compile_amplitudes(const Network& net, const std::vector<std::pair<int, 
       const PlanOp& op = P.ops[k];
       P.flops_per_job += op.flops;
       P.bytes_per_job += op.bytes;
-      if (op.kind == OP_GEMM) {
+      if (op.f64) {
+        // complex128 throughout: unit roundoff 2^-53 per operation chain
+        if (op.kind == OP_GEMM) P.gemm_ops++;
+        const double K = op.kind == OP_GEMM ? double(op.gm.K) : 1.0;
+        err2 += std::ldexp(1.0, -106) * (1.0 + K);
+      } else if (op.kind == OP_GEMM) {
         P.gemm_ops++;
         const double u = op.gm.precision == TN_PREC_BF16X3   ? std::ldexp(1.0, -17)
                          : op.gm.precision == TN_PREC_F16X3 ? std::ldexp(1.0, -21)

@@ -36,6 +36,7 @@ struct PlanOp {
   GemmDesc gm;
   int64_t dot_k = 0, dot_batch = 0;
   int64_t dot_m = 1, dot_n = 1;   // DOT over all (m, n) row pairs of [b][m][k] x [b][n][k]
+  int f64 = 0;                     // complex128 operands (TN_PREC_FP64 plans)
   int skinny = 0;                  // DOT as the skinny long-K GEMM (batch 1), layouts below
   int dot_ta = 0, dot_tb = 1;      // skinny: transA / transB as for GEMMs
   double flops = 0, bytes = 0;

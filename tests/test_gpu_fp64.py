@@ -1,0 +1,132 @@
+"""The complex128 validation precision (TN_PREC_FP64) against the oracle.
+
+Every tensor of an FP64 plan is complex128 and every multiply-add FP64, so
+amplitudes must agree with the state-vector oracle (O1) and pairwise
+contractions with the einsum oracle (O2) to rounding level: 1e-12
+(floored relative) for amplitudes, 1e-13 (relative L2) for contractions.
+The circuits reach every FP64 kernel: bit-addressed apply, tiled and gather
+permutes, the block-tiled GEMM and the long-K dot products.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import statevector as sv
+from oracle.contract import contract_pair as oracle_pair
+from tests.helpers import floored_rel, l2_rel
+from tests.test_gpu_contract import CASES, make_case
+from workloads import cat_circuit, grid_random_circuit, random_bitstrings
+
+pytestmark = pytest.mark.gpu
+
+
+def _amps(n, ops, bits, algo="greedy", budget=0.0, **kw):
+    import torch
+    import paper_2104_10523_amd as tn
+    net = tn.tn_build_network(n, ops)
+    bits = np.asarray(bits, dtype=np.int8)
+    if bits.ndim == 1:
+        bits = bits[None]
+    path = tn.tn_find_path(net, algo, mem_budget_bytes=budget, open_mask=(bits[0] < 0).astype(np.int8), **kw)
+    big = torch.empty(tn.tn_amplitudes_workspace(net, path, len(bits), "fp64"), dtype=torch.uint8, device="cuda")
+    tn.tn_set_workspace(big)
+    out, rep = tn.tn_amplitudes(net, path, bits, precision="fp64")
+    return out.cpu().numpy(), rep, path, net
+
+
+def test_fp64_c1_all_amplitudes(gpu, workspace):
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(3, 4, 8, 1)
+    try:
+        got, rep, _, _ = _amps(n, ops, [-1] * n)
+    finally:
+        tn.tn_set_workspace(workspace)
+    ref = sv.simulate(n, ops).reshape(-1)
+    assert floored_rel(got[0], ref, 2.0 ** (-n / 2)) <= 1e-12
+    assert l2_rel(got[0], ref) <= 1e-12
+    assert rep.err_bound < 1e-13
+
+
+def test_fp64_random_fsim_circuit_large_gemms(gpu, workspace):
+    """The 4x5x14 fSim circuit whose greedy plan holds GEMMs up to
+    65536 x 1024 x 256 and permutes of 2^20+ entries (tiled kernel)."""
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(4, 5, 14, 2, two_qubit="fsim")
+    try:
+        got, rep, path, net = _amps(n, ops, [-1] * n)
+        kind, _, _, shape = tn.tn_amplitudes_plan_ops(net, path, "fp64")
+    finally:
+        tn.tn_set_workspace(workspace)
+    assert int(np.sum(kind == 2)) >= 20 and int(shape[kind == 2][:, 0].max()) >= 65536
+    ref = sv.simulate(n, ops).reshape(-1)
+    e1, e2 = floored_rel(got[0], ref, 2.0 ** (-n / 2)), l2_rel(got[0], ref)
+    print(f"fp64 4x5x14: floored {e1:.2e} l2 {e2:.2e}", flush=True)
+    assert e1 <= 1e-12 and e2 <= 1e-12
+
+
+def test_fp64_sliced_projected_and_marginal(gpu, workspace):
+    import paper_2104_10523_amd as tn
+    n, ops = grid_random_circuit(4, 5, 10, 3)
+    bits = random_bitstrings(6, n, 5)
+    psi = sv.simulate(n, ops)
+    try:
+        full, _, p0, _ = _amps(n, ops, bits)
+        sl, _, p1, _ = _amps(n, ops, bits, budget=8 * p0.cost.peak_elems / 16)
+        mbits = np.array(bits[0]).copy()
+        mbits[[3, 7, 11, 19]] = -1
+        marg, _, _, _ = _amps(n, ops, mbits, algo="partition", trials=4, seed=2)
+    finally:
+        tn.tn_set_workspace(workspace)
+    assert p1.cost.n_sliced >= 3
+    idx = [int("".join(map(str, b)), 2) for b in bits]
+    ref = psi.reshape(-1)[idx]
+    assert floored_rel(full[:, 0], ref, 2.0 ** (-n / 2)) <= 1e-12
+    assert floored_rel(sl[:, 0], ref, 2.0 ** (-n / 2)) <= 1e-12
+    assert floored_rel(marg[0], sv.slice_of(psi, mbits), 2.0 ** (-n / 2)) <= 1e-12
+
+
+def test_fp64_cat_marginal_slice(gpu, workspace):
+    """The paper's 60-qubit cat state slice (Sec. 4.4): raw amplitudes
+    1/sqrt(2) and 0 to rounding."""
+    import paper_2104_10523_amd as tn
+    n, ops = cat_circuit(60)
+    bits = [0] * n
+    bits[0] = bits[1] = -1
+    try:
+        got, _, _, _ = _amps(n, ops, bits)
+    finally:
+        tn.tn_set_workspace(workspace)
+    want = np.array([2 ** -0.5, 0, 0, 0])
+    assert np.abs(got[0] - want).max() <= 1e-15
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_fp64_contract_pair(gpu, workspace, name, kw):
+    """Complex128 tensors through tn_contract_pair at TN_PREC_FP64."""
+    import torch
+    import paper_2104_10523_amd as tn
+    A, la, B, lb, lc, shape_c = make_case(700 + len(name), **kw)
+    A = A.astype(np.complex128)
+    B = B.astype(np.complex128)
+    dA = torch.from_numpy(np.ascontiguousarray(A)).cuda()
+    dB = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    dC = torch.full(shape_c, complex(float("nan"), 0), dtype=torch.complex128, device="cuda")
+    tn.tn_contract_pair(dA, la, dB, lb, dC, lc, "fp64")
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    ref = oracle_pair(A, la, B, lb, lc)
+    assert np.all(np.isfinite(got))
+    assert l2_rel(got, ref) <= 1e-13, (name, l2_rel(got, ref))
+
+
+def test_fp64_dtype_rules(gpu, workspace):
+    import torch
+    import paper_2104_10523_amd as tn
+    a64 = torch.zeros((2, 2), dtype=torch.complex64, device="cuda")
+    a128 = torch.zeros((2, 2), dtype=torch.complex128, device="cuda")
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_contract_pair(a64, [1, 2], a64, [2, 3], a64, [1, 3], "fp64")
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_contract_pair(a128, [1, 2], a128, [2, 3], a128, [1, 3], "fp32")
+    with pytest.raises(tn.TnError, match="ARG"):
+        tn.tn_contract_pair(a128, [1, 2], a64, [2, 3], a128, [1, 3], "fp64")
