@@ -165,9 +165,26 @@ TRef emit_sum_out(const TRef& X, const std::vector<int>& dang, Arena& arena,
   return out;
 }
 
-int resolve_precision(int precision, int64_t M, int64_t N, int64_t K) {
-  if (precision != TN_PREC_AUTO) return precision;
-  return (K >= 64 && M >= 1024 && N >= 64) ? TN_PREC_F16X3 : TN_PREC_FP32;
+// AUTO: among the precisions whose a-priori error for this GEMM stays
+// within kAutoErr (u sqrt(1 + log2 K): scaled split-FP16x3 and FP32 always,
+// split-BF16x3 never), the one of least modelled time: max(flops / F,
+// GEMM bytes / B) plus the operand passes it needs -- for FP32 a permute
+// (16 bytes per entry) of an operand whose labels are not grouped for the
+// GEMM, for the split form the max-abs pass and the packing permute of both
+// operands (8 + 16 bytes per entry).  F and B as in the time ranking of
+// paths (350e12 split, 120e12 FP32, 4.0e12 B/s).
+constexpr double kAutoErr = 2e-6;
+int auto_precision(int64_t Bn, int64_t M, int64_t N, int64_t K, bool permA, bool permB, bool packable) {
+  constexpr double kSplit = 350e12, kFp32 = 120e12, kHbm = 4.0e12;
+  const double b = double(Bn), fl = 8.0 * b * M * N * K;
+  const double ab = b * M * K, bb = b * K * N, cb = b * M * N;
+  const double gemm_bytes = 8.0 * (ab + bb + cb);
+  const double t32 = std::max(fl / kFp32, gemm_bytes / kHbm) + 16.0 * ((permA ? ab : 0) + (permB ? bb : 0)) / kHbm;
+  if (!packable) return TN_PREC_FP32;
+  const double e16 = std::ldexp(1.0, -21) * std::sqrt(1.0 + std::log2(double(K)));
+  if (e16 > kAutoErr) return TN_PREC_FP32;
+  const double t16 = std::max(fl / kSplit, gemm_bytes / kHbm) + 24.0 * (ab + bb) / kHbm;
+  return t16 < t32 ? TN_PREC_F16X3 : TN_PREC_FP32;
 }
 
 }  // namespace
@@ -317,7 +334,6 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
   auto lowest = [](const TRef& T) { return T.labels.empty() ? -1 : T.labels.back(); };
   int transA = 0, transB = 0;
   TRef Ap = A, Bp = B;
-  int prec = resolve_precision(precision, Mn, Nn, Kn);
   // packed planes are addressed with 32-bit panel offsets: a 256-row panel
   // of one plane (4 bytes per entry) must stay below 2 GiB, so K <= 2^20;
   // longer contractions run on the FP32 kernel at every precision
@@ -329,6 +345,14 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
   const bool dot_mn = skinny || (!(Mn == 1 && Nn == 1) && Mn * Nn <= 16 && Kn >= (int64_t(1) << 16) &&
                                  Bn * Mn * Nn <= 4096);
   const bool packable = Kn % 4 == 0 && !long_k && !dot_mn && !(Mn == 1 && Nn == 1);
+  int prec = precision;
+  if (prec == TN_PREC_AUTO) {
+    // would the FP32 GEMM have to permute an operand first?
+    const auto ga0 = cat({b_o, m_o, k_o}), ga1 = cat({b_o, k_o, m_o});
+    const auto gb0 = cat({b_o, k_o, n_o}), gb1 = cat({b_o, n_o, k_o});
+    const bool permA = !(A.labels == ga0 || A.labels == ga1), permB = !(B.labels == gb0 || B.labels == gb1);
+    prec = auto_precision(Bn, Mn, Nn, Kn, permA, permB, packable);
+  }
   if (long_k && prec != TN_PREC_FP64) prec = TN_PREC_FP32;
   // split-FP16 exists only on packed planes; elsewhere such GEMMs run FP32
   if (prec == TN_PREC_F16X3 && !packable) prec = TN_PREC_FP32;

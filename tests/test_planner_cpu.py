@@ -223,19 +223,20 @@ def test_identity_coupled_7x7_has_benchmark_path():
     """The full-size GPU parity case (fSim(0, 0) couplers) has the network
     structure of the benchmark's 7x7 grid circuit (same tensors, labels and
     extents), so every path search plans it alike: here the recursive-
-    bisection search at 64 trials with the benchmark's 160 GiB budget (the
-    full-size GPU test repeats this at the benchmark's 1024 trials)."""
+    bisection search at 64 trials with the benchmark's 160 GiB budget and
+    time ranking (the full-size GPU test repeats this at the benchmark's 1024
+    trials)."""
     n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim")
     _, ops0 = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim", fsim_params=(0.0, 0.0))
     a, b = tn.tn_build_network(n, ops), tn.tn_build_network(n, ops0)
     assert a.info().n_tensors == b.info().n_tensors
     for i in range(a.info().n_tensors):
         assert a.tensor(i)[1] == b.tensor(i)[1]
-    opts = dict(trials=64, seed=1, mem_budget_bytes=160.0 * 2 ** 30)
+    opts = dict(trials=64, seed=1, mem_budget_bytes=160.0 * 2 ** 30, rank="time")
     p = tn.tn_find_path(a, "partition", **opts)
     p0 = tn.tn_find_path(b, "partition", **opts)
     assert p.pairs == p0.pairs and p.sliced == p0.sliced
-    assert p.cost.n_sliced == p0.cost.n_sliced and p.cost.n_sliced >= 5
+    assert p.cost.n_sliced == p0.cost.n_sliced and p.cost.n_sliced >= 4
 
 
 # ---- recursive-bisection path search -------------------------------------
