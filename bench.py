@@ -102,7 +102,7 @@ def parse():
     ap.add_argument("--cycles", type=int, default=14)
     ap.add_argument("--autotune", type=int, default=1,
                     help="run the GEMM tile autotuner before the warmup (its trial launches appear in kernel traces)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "learned", "expval", "dm"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "pmps", "learned", "expval", "dm"],
                     help="c2 (default) is the benchmark line; the others measure the remaining rows")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
@@ -349,6 +349,54 @@ def bench_traj(a):
             "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "trajectories/s", "cores": 1, "kind": "oracle",
                              "sample": "oracle trajectory (state vector, complex128): one trajectory of the "
                                        "depth-10 circuit, scaled to the ensemble's mean depth 20"}}
+
+
+def bench_pmps(a):
+    """Locally-purified MPS (Sec. 3.4): 24-site noisy chain, 8 cycles of
+    fSim(pi/2, pi/6) on alternating bonds, depolarising 1e-3 / 1e-2 and
+    damping 5e-3 after every gate, d_max 32, k_max 8."""
+    import paper_2104_10523_amd as tn
+    from oracle.gates import gate_matrix, is_channel, kraus_ops
+    from oracle.pmps import run_circuit as pmps_oracle
+    from workloads import chain_random_circuit, noisy_ops
+    n, ops = chain_random_circuit(24, 8, 9)
+    ops = noisy_ops(ops, 1e-3, 1e-2, 5e-3)
+    d_max, k_max = 32, 8
+
+    def run():
+        m = tn.tn_pmps_create(n, d_max, k_max)
+        db = dk = 0.0
+        for op in ops:
+            q = op.qubits
+            if is_channel(op.name):
+                b, k = m.apply_channel(q[0], kraus_ops(op.name, op.params))
+                db, dk = db + b, dk + k
+            elif len(q) == 1:
+                m.apply_gate1(q[0], gate_matrix(op.name, op.params))
+            else:
+                db += m.apply_gate(q[0], gate_matrix(op.name, op.params))
+        return m, db, dk
+    run()                                   # warm (graph captures per shape)
+    t0 = time.perf_counter()
+    m, db, dk = run()
+    T = time.perf_counter() - t0
+    z = m.expect_z()
+    n_ops = sum(1 for op in ops if len(op.qubits) == 2 or is_channel(op.name))
+    t1 = time.perf_counter()
+    ref, rdb, rdk = pmps_oracle(n, ops, d_max=d_max, k_max=k_max)
+    t_cpu = time.perf_counter() - t1
+    zerr = float(np.abs(z - ref.expect_z()).max())
+    return {"metric": "locally-purified MPS: two-qubit gates + channels per second, 24-site noisy chain",
+            "value": n_ops / T, "unit": "ops/s", "dtype": "c64 sites, fp64 SVD/QR",
+            "config": {"workload": "24-site chain, 8 cycles fSim(pi/2,pi/6), depolarising 1e-3/1e-2 + damping 5e-3, "
+                                   "d_max 32, k_max 8", "seconds": T, "ops": n_ops,
+                       "discarded_bond": db, "discarded_kraus": dk, "oracle_discarded_bond": rdb,
+                       "oracle_discarded_kraus": rdk, "z_max_abs_diff_vs_oracle": zerr,
+                       "dims": m.dims()},
+            "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                         "traffic": None, "note": "per op: one FP64 Jacobi SVD of <= 1024 x 512 and QR moves"},
+            "cpu_baseline": {"value": n_ops / t_cpu, "unit": "ops/s", "cores": os.cpu_count(), "kind": "oracle",
+                             "sample": "PMPS oracle (numpy complex128 + LAPACK SVD/QR), the same circuit"}}
 
 
 def bench_mps(a):
@@ -680,7 +728,8 @@ def roofline_entry(kernel, flops, bytes_, seconds, precision):
             "algorithmic_bytes_per_launch": bytes_}
 
 
-ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "learned": bench_learned,
+ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "pmps": bench_pmps,
+        "learned": bench_learned,
         "expval": bench_expval, "dm": bench_dm}
 
 

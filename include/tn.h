@@ -540,6 +540,62 @@ tn_status tn_mps_amplitudes(tn_mps* m, const int8_t* bits, int64_t n_bs,
                             double* out, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Locally-purified MPS (Sec. 3.4, the locally-purified MPS figure and the */
+/* Kraus-contraction figure)                                               */
+/* ---------------------------------------------------------------------- */
+
+/* rho = Tr_K |X><X|: X is an MPS whose site tensors T[l, s, k, r] carry a
+ * Kraus leg k (dimension K_i <= k_max) beside the physical leg s and the
+ * virtual bonds (<= d_max); the Kraus leg is traced between X and its
+ * conjugate.  Sites are complex64 in library-owned device memory; SVDs and
+ * QRs run in FP64 (one-sided Jacobi, Householder), the merged pair on the
+ * complex MFMA GEMM. */
+typedef struct tn_pmps tn_pmps;
+
+/* |0..0><0..0| on n_sites qubits (every K = 1).  d_max 1..256, k_max
+ * 1..64, and the factorisation workspace (16 d_max^2 (2 k_max)^2 complex128
+ * for a merged pair under a 16-operator channel) at most 16 GiB.
+ * Errors: TN_ERR_ARG, TN_ERR_UNSUPPORTED, TN_ERR_NOMEM, TN_ERR_DEVICE. */
+tn_status tn_pmps_create(int32_t n_sites, int32_t d_max, int32_t k_max,
+                         void* stream, tn_pmps** out);
+tn_status tn_pmps_destroy(tn_pmps* p);
+/* One-qubit gate (2x2 complex128 row-major, host) on the physical leg. */
+tn_status tn_pmps_apply_gate1(tn_pmps* p, int32_t site, const double* gate,
+                              void* stream);
+/* Two-qubit gate (4x4 complex128, host; `site` the more significant bit)
+ * on (site, site+1), as tn_mps_apply_gate: the centre moves onto the pair,
+ * the merged pair is split by an SVD of the (l, s, k) x (s, k, r) matrix,
+ * at most d_max values with s / s_max > cutoff kept and renormalised; only
+ * the virtual bond changes.  *discarded (may be NULL): dropped weight.
+ * Synchronises.  Errors: TN_ERR_SITE, TN_ERR_ARG, TN_ERR_UNSUPPORTED,
+ * TN_ERR_DEVICE. */
+tn_status tn_pmps_apply_gate(tn_pmps* p, int32_t site, const double* gate,
+                             double cutoff, double* discarded, void* stream);
+/* Channel of n_kraus (1..16) operators on n_qubits (1 or 2) qubits starting
+ * at `site` (host, complex128 row-major, 2x2 or 4x4 each, sum A^dagger A =
+ * 1): each operator is contracted with the physical leg(s), its index
+ * joining the (first) site's Kraus leg, which is then compressed at the
+ * orthogonality centre by an SVD along it (T <- U S; at most k_max values
+ * with s / s_max > cutoff, renormalised).  A two-qubit channel acts on the
+ * merged pair, split as a gate with S on the first site.  *discarded_bond /
+ * *discarded_kraus (may be NULL): dropped weights.  Synchronises.
+ * Errors: TN_ERR_SITE, TN_ERR_ARG, TN_ERR_UNSUPPORTED, TN_ERR_DEVICE. */
+tn_status tn_pmps_apply_channel(tn_pmps* p, int32_t site, int32_t n_qubits,
+                                const double* kraus, int32_t n_kraus,
+                                double cutoff, double* discarded_bond,
+                                double* discarded_kraus, void* stream);
+/* Bond dimensions (n_sites - 1) and Kraus dimensions (n_sites); either may
+ * be NULL.  Host only. */
+tn_status tn_pmps_dims(const tn_pmps* p, int32_t* bond_dims, int32_t* kraus_dims);
+/* <Z_i> = Tr(rho Z_i) for every site (host, n_sites doubles).  Moves the
+ * centre; synchronises. */
+tn_status tn_pmps_expect_z(tn_pmps* p, double* out, void* stream);
+/* Site tensor as complex128 (l, 2, K, r) row-major into host `data` (may
+ * be NULL to query), its four dimensions into dims.  Synchronises. */
+tn_status tn_pmps_get_site(tn_pmps* p, int32_t site, double* data, int32_t* dims,
+                           void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Stochastic Kraus trajectories (Sec. 3.3, Eq. 3, sampled)               */
 /* ---------------------------------------------------------------------- */
 

@@ -16,7 +16,7 @@ import numpy as np
 from ._native import (GATE_IDS, PATH_ALGO, PAULI, PREC, TnCircuit, TnExecOpts, TnNetworkInfo, TnOp,
                       TnPathCost, TnPathOpts, TnPlanInfo, TnReport, TnTensor, TnError, check, lib)
 
-__all__ = ["Network", "Path", "Mps", "TnError", "tn_build_network", "tn_find_path",
+__all__ = ["Network", "Path", "Mps", "Pmps", "TnError", "tn_pmps_create", "tn_build_network", "tn_find_path",
            "tn_path_from_pairs", "tn_contract_pair", "tn_amplitudes", "tn_set_workspace",
            "tn_amplitudes_workspace", "tn_build_expectation_network", "tn_build_density_network",
            "tn_pauli_expectation", "tn_sample_amplitudes",
@@ -389,6 +389,75 @@ def tn_mps_apply_gate(mps: Mps, site: int, U, chi_max: int, cutoff: float = 1e-1
                                   int(chi_max), float(cutoff), C.byref(disc),
                                   C.c_void_p(_stream_ptr(stream))))
     return disc.value
+
+
+class Pmps:
+    """Locally-purified MPS handle (tn_pmps_*)."""
+
+    def __init__(self, handle: int, n: int):
+        self.h = C.c_void_p(handle)
+        self.n = n
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().tn_pmps_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    @staticmethod
+    def _mat(U):
+        u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128)).view(np.float64)
+        return u, u.ctypes.data_as(C.POINTER(C.c_double))
+
+    def apply_gate1(self, site: int, U, stream=None):
+        u, pu = self._mat(U)
+        check(lib().tn_pmps_apply_gate1(self.h, int(site), pu, C.c_void_p(_stream_ptr(stream))))
+
+    def apply_gate(self, site: int, U, cutoff: float = 1e-12, stream=None) -> float:
+        u, pu = self._mat(U)
+        d = C.c_double()
+        check(lib().tn_pmps_apply_gate(self.h, int(site), pu, float(cutoff), C.byref(d),
+                                       C.c_void_p(_stream_ptr(stream))))
+        return d.value
+
+    def apply_channel(self, site: int, kraus, cutoff: float = 1e-12, stream=None):
+        """kraus: list of 2x2 or 4x4 matrices; returns (discarded bond, discarded Kraus)."""
+        ks = [np.asarray(k, dtype=np.complex128) for k in kraus]
+        nq = 1 if ks[0].shape == (2, 2) else 2
+        u, pu = self._mat(np.stack(ks))
+        db, dk = C.c_double(), C.c_double()
+        check(lib().tn_pmps_apply_channel(self.h, int(site), nq, pu, len(ks), float(cutoff), C.byref(db),
+                                          C.byref(dk), C.c_void_p(_stream_ptr(stream))))
+        return db.value, dk.value
+
+    def dims(self):
+        b = (C.c_int32 * max(self.n - 1, 1))()
+        k = (C.c_int32 * self.n)()
+        check(lib().tn_pmps_dims(self.h, b, k))
+        return list(b)[:self.n - 1], list(k)
+
+    def expect_z(self, stream=None) -> np.ndarray:
+        out = np.zeros(self.n)
+        check(lib().tn_pmps_expect_z(self.h, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                     C.c_void_p(_stream_ptr(stream))))
+        return out
+
+    def site(self, i: int, stream=None) -> np.ndarray:
+        dims = (C.c_int32 * 4)()
+        check(lib().tn_pmps_get_site(self.h, int(i), None, dims, C.c_void_p(_stream_ptr(stream))))
+        shape = tuple(dims)
+        out = np.zeros(2 * int(np.prod(shape)))
+        check(lib().tn_pmps_get_site(self.h, int(i), out.ctypes.data_as(C.POINTER(C.c_double)), dims,
+                                     C.c_void_p(_stream_ptr(stream))))
+        return out.view(np.complex128).reshape(shape)
+
+
+def tn_pmps_create(n_sites: int, d_max: int, k_max: int, stream=None) -> Pmps:
+    h = C.c_void_p()
+    check(lib().tn_pmps_create(int(n_sites), int(d_max), int(k_max), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
+    return Pmps(h.value, n_sites)
 
 
 def tn_run_trajectories(circuits, traj_per_circ: int, uniforms, stream=None):

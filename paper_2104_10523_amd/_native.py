@@ -111,6 +111,14 @@ SIGNATURES = {
     "tn_mps_destroy": (I32, [P]),
     "tn_mps_apply_gate1": (I32, [P, I32, PD, P]),
     "tn_mps_apply_gate": (I32, [P, I32, PD, I32, D, PD, P]),
+    "tn_pmps_create": (I32, [I32, I32, I32, P, C.POINTER(C.c_void_p)]),
+    "tn_pmps_destroy": (I32, [P]),
+    "tn_pmps_apply_gate1": (I32, [P, I32, PD, P]),
+    "tn_pmps_apply_gate": (I32, [P, I32, PD, C.c_double, PD, P]),
+    "tn_pmps_apply_channel": (I32, [P, I32, I32, PD, I32, C.c_double, PD, PD, P]),
+    "tn_pmps_dims": (I32, [P, PI32, PI32]),
+    "tn_pmps_expect_z": (I32, [P, PD, P]),
+    "tn_pmps_get_site": (I32, [P, I32, PD, PI32, P]),
     "tn_mps_bond_dims": (I32, [P, PI32]),
     "tn_mps_bond_spectrum": (I32, [P, I32, PD, I32, PI32]),
     "tn_mps_expect_z": (I32, [P, PD, P]),
