@@ -403,8 +403,9 @@ tn_status tn_amplitudes_plan_info(const tn_network* n, const tn_path* p,
  * algorithmic flops and bytes, and `shape`, 8 int64 per op: m, n, k, batch,
  * block-tile id, packed flag, GEMM kernel launches (K-chunked accumulation:
  * ceil(k / 4096) unless split-K is used), 0 — for GEMMs; other kinds give
- * 1, 1, 1, 1, -1, 0, 1, 0 except APPLY: rows, 2^#N, 2^#K and 1 for the
- * LDS-tiled kernel (apply_tile_kernel) or 0 (apply_small_kernel) in the first four,
+ * 1, 1, 1, 1, -1, 0, 1, 0 except APPLY: rows, 2^#N, 2^#K and the kernel
+ * (0 apply_small_kernel, 1 the LDS-tiled apply_tile_kernel, 2 the matrix-core
+ * apply16_mfma_kernel for 2^#N = 16) in the first four,
  * DOT: m, n, k, batch, and in the sixth 1 for the skinny long-K kernel
  * (batch 1, both operands read once) or 0 for one dot per (m, n), PERMUTE: output entries, planes
  * (0 = complex64, 2 or 3 split planes), fp16 flag and the kernel (0 device

@@ -635,7 +635,7 @@ tn_status tn_amplitudes_plan_ops(const tn_network* n, const tn_path* p, int32_t 
           r[0] = int64_t(1) << (op.ap.a_bits - op.ap.nk);
           r[1] = int64_t(1) << op.ap.nn;
           r[2] = int64_t(1) << op.ap.nk;
-          r[3] = apply_tiled_ok(op.ap, nullptr, nullptr) ? 1 : 0;
+          r[3] = apply_variant(op.ap, nullptr, nullptr);
         } else if (op.kind == OP_DOT) {
           r[0] = op.dot_m; r[1] = op.dot_n; r[2] = op.dot_k; r[3] = op.dot_batch;
           r[5] = op.skinny;

@@ -620,6 +620,97 @@ __global__ __launch_bounds__(256) void apply_tile_kernel(const float2* __restric
   }
 }
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// NN = 16 on the FP32 matrix cores.  A wave takes 2 x 32 rows at a time:
+// every K value is one v_mfma_f32_32x32x2f32 per 32 rows in the real 2 x 2
+// block form of the complex product (the MFMA's two k slots carry re a and
+// im a; its 32 columns are the 16 outputs' re and im parts, B entered as
+// [[re b, im b], [-im b, re b]]), so a row costs KK MFMA issues instead of
+// 64 KK VALU FMAs.  Lane l loads only its own float of row l % 32's entry
+// (re for l < 32, im above), so a load instruction covers 32 rows' entries
+// once; accumulator register r holds row 8 (r / 4) + 4 (l / 32) + r % 4, so
+// each store instruction writes two contiguous 128-byte row segments.  A's
+// K values are loaded CH at a time ahead of their MFMAs; the two 32-row
+// groups keep two independent accumulator chains.  Needs n_rows a multiple
+// of 64.
+template <int KK>
+__global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restrict__ A,
+                                                           const float2* __restrict__ B,
+                                                           float2* __restrict__ C, ApplyArgs P) {
+  constexpr int CH = KK < 8 ? KK : 8;
+  __shared__ float2 sB[KK * 16];
+  __shared__ int64_t s_koff[KK];
+  const int t = threadIdx.x;
+  for (int idx = t; idx < KK * 16; idx += 256) {
+    const int k = idx / 16, n = idx % 16;
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if (P.bk[i] >= 0 && ((k >> i) & 1)) off |= int64_t(1) << P.bk[i];
+    for (int i = 0; i < 4; ++i)
+      if ((n >> i) & 1) off |= int64_t(1) << P.bn[i];
+    float2 v = make_float2(0.f, 0.f);
+    for (int e = 0; e < (1 << P.n_b_extra); ++e) {
+      int64_t o2 = off;
+      for (int i = 0; i < P.n_b_extra; ++i)
+        if ((e >> i) & 1) o2 |= int64_t(1) << P.b_extra[i];
+      const float2 b = B[o2];
+      v.x += b.x;
+      v.y += b.y;
+    }
+    sB[idx] = v;
+  }
+  if (t < KK) {
+    int64_t off = 0;
+    for (int i = 0; i < P.nk; ++i)
+      if ((t >> i) & 1) off |= int64_t(1) << P.kpos[i];
+    s_koff[t] = off;
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int bn = li >> 1, bt = li & 1;
+  const bool pick_re = lh == bt;
+  const float sgn = (lh == 1 && bt == 0) ? -1.f : 1.f;
+  const float* Af = reinterpret_cast<const float*>(A) + lh;
+  float* Cf = reinterpret_cast<float*>(C);
+  auto expand = [&](int64_t m) {
+    for (int i = 0; i < P.nk; ++i) {
+      const int p = P.kpos[i];
+      m = ((m >> p) << (p + 1)) | (m & ((int64_t(1) << p) - 1));
+    }
+    return m;
+  };
+  const int64_t groups = P.n_rows >> 6;
+  for (int64_t g = int64_t(blockIdx.x) * 4 + wave; g < groups; g += int64_t(gridDim.x) * 4) {
+    const int64_t b0 = 2 * expand(g * 64 + li), b1 = 2 * expand(g * 64 + 32 + li);
+    floatx16 acc0 = {}, acc1 = {};
+#pragma unroll 1
+    for (int k0 = 0; k0 < KK; k0 += CH) {
+      float a0[CH], a1[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int64_t o = 2 * s_koff[k0 + j];
+        a0[j] = Af[b0 + o];
+        a1[j] = Af[b1 + o];
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const float2 b = sB[(k0 + j) * 16 + bn];
+        const float bv = sgn * (pick_re ? b.x : b.y);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], bv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], bv, acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = g * 64 + 8 * (r >> 2) + 4 * lh + (r & 3);
+      Cf[(row * 16 + bn) * 2 + bt] = acc0[r];
+      Cf[((row + 32) * 16 + bn) * 2 + bt] = acc1[r];
+    }
+  }
+}
+
 // The LDS-tiled apply: lowest A bit is a K bit, every K bit below 8 + nk
 // (a block's 256 rows are one run of A), KK <= 16, full blocks, and 16-byte
 // aligned A and C (the plan's buffers are).
@@ -630,6 +721,24 @@ bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C) {
   if (A && (reinterpret_cast<uintptr_t>(A) & 15)) return false;
   if (C && (reinterpret_cast<uintptr_t>(C) & 15)) return false;
   return true;
+}
+
+namespace {
+bool apply_mfma_ok(const ApplySmallDesc& d) { return d.nn == 4 && d.a_bits - d.nk >= 6; }
+}  // namespace
+
+int apply_variant(const ApplySmallDesc& d, const void* A, const void* C) {
+  if (d.variant == 2 && apply_mfma_ok(d)) return 2;
+  const bool tiled = apply_tiled_ok(d, A, C);
+  if (d.variant == 0) return tiled ? 1 : 0;
+  if (tiled) return 1;
+  return apply_mfma_ok(d) ? 2 : 0;
+}
+
+std::vector<int> apply_variant_candidates(const ApplySmallDesc& d) {
+  std::vector<int> v{0};
+  if (apply_mfma_ok(d)) v.push_back(2);
+  return v;
 }
 
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
@@ -648,9 +757,25 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
     P.bn[i] = d.bn[i];
   }
   for (int i = 0; i < 12; ++i) P.b_extra[i] = d.b_extra[i];
+  const int variant = apply_variant(d, A, C);
+  if (variant == 2) {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
+    const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
+    switch (1 << d.nk) {
+      case 1: apply16_mfma_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 2: apply16_mfma_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 4: apply16_mfma_kernel<4><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 8: apply16_mfma_kernel<8><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 16: apply16_mfma_kernel<16><<<g, b, 0, s>>>(A, B, C, P); break;
+      case 32: apply16_mfma_kernel<32><<<g, b, 0, s>>>(A, B, C, P); break;
+      default: apply16_mfma_kernel<64><<<g, b, 0, s>>>(A, B, C, P); break;
+    }
+    TN_HIP(hipGetLastError());
+    return;
+  }
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
   const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
-  if (apply_tiled_ok(d, A, C)) {
+  if (variant == 1) {
     switch (1 << d.nn) {
       case 1: apply_tile_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
       case 2: apply_tile_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;
@@ -673,7 +798,6 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 
 // -------------------------------------------------------------- MFMA GEMM
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));

@@ -49,12 +49,19 @@ struct ApplySmallDesc {
   int8_t bn[8];            // N bit i of B
   int8_t b_extra[12];      // B bits summed out (dangling in B), -1 padded
   int n_b_extra = 0;
+  int variant = -1;        // kernel (see apply_variant); -1: the default rule
 };
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
                         hipStream_t s);
 // Whether launch_apply_small runs apply_tile_kernel (A and C may be NULL:
 // then alignment is assumed, as for the plan's buffers).
 bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C);
+// Kernel launch_apply_small picks: 0 one thread per row, 1 LDS-tiled, 2 matrix cores (NN = 16).
+// d.variant = 0 or 2 asks for that kernel where it applies (the autotuner's
+// choice); -1 takes the default: 1 where it applies, else 2 where it applies, else 0.
+int apply_variant(const ApplySmallDesc& d, const void* A, const void* C);
+// Kernels the autotuner may time for an apply (at least one).
+std::vector<int> apply_variant_candidates(const ApplySmallDesc& d);
 
 // Complex GEMM C[b][m][n] = sum_k A[b](m,k) * B[b](k,n), contiguous operands.
 // transA = 0: A[b][m][k]; 1: A[b][k][m].  transB = 0: B[b][k][n]; 1: B[b][n][k].

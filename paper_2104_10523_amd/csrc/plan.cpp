@@ -136,6 +136,7 @@ TRef emit_sum_out(const TRef& X, const std::vector<int>& dang, Arena& arena,
   op.kind = OP_APPLY;
   std::memset(&op.ap, 0, sizeof(op.ap));
   std::memset(op.ap.b_extra, -1, sizeof(op.ap.b_extra));
+  op.ap.variant = -1;
   op.ap.a_bits = int(X.labels.size());
   std::vector<int> kp;
   for (int l : dang) kp.push_back(pos_of(X.labels, l));
@@ -260,6 +261,7 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
     op.ap.n_b_extra = int(dsmall.size());
     for (size_t i = 0; i < dsmall.size(); ++i) op.ap.b_extra[i] = int8_t(pos_of(small.labels, dsmall[i]));
     op.ap.nb_b = int(small.labels.size());
+    op.ap.variant = tuned_apply(op.ap);
     TRef out;
     out.labels = cat({Mbig, Norder});
     if (want && direct) {
@@ -571,13 +573,74 @@ void remember_tile(const GemmDesc& g, int tile) {
   g_tiles[key_of(g)] = tile;
 }
 
+namespace {
+// an apply's identity for the cache: its descriptor without the variant
+std::vector<int> apply_key(const ApplySmallDesc& d) {
+  std::vector<int> k{d.a_bits, d.nk, d.nn, d.nb_b, d.n_b_extra};
+  for (int i = 0; i < 8; ++i) k.insert(k.end(), {d.kpos[i], d.bk[i], d.bn[i]});
+  for (int i = 0; i < 12; ++i) k.push_back(d.b_extra[i]);
+  return k;
+}
+std::map<std::vector<int>, int> g_applies;
+}  // namespace
+
+int tuned_apply(const ApplySmallDesc& d) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_applies.find(apply_key(d));
+  return it == g_applies.end() ? -1 : it->second;
+}
+
+// Times the apply kernels that fit op (on its first 2^24 or so rows: every
+// address stays inside the real operands) and keeps the fastest.
+void autotune_apply(PlanOp& op, float2* const bufs[6], int reps, hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+  const std::vector<int> cands = apply_variant_candidates(op.ap);
+  if (cands.size() < 2) return;
+  const float2* a = bufs[op.a_buf] + op.a_off;
+  const float2* b = bufs[op.b_buf] + op.b_off;
+  float2* c = bufs[op.c_buf] + op.c_off;
+  ApplySmallDesc d = op.ap;
+  const int kmax = d.nk > 0 ? d.kpos[d.nk - 1] + 1 : 0;
+  d.a_bits = std::max({kmax, d.nk + 6, std::min(d.a_bits, d.nk + 24)});
+  float best_ms = 0;
+  int best = -1;
+  for (int v : cands) {
+    d.variant = v;
+    launch_apply_small(a, b, c, d, s);  // warm
+    TN_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch_apply_small(a, b, c, d, s);
+    TN_HIP(hipEventRecord(e1, s));
+    TN_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    TN_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (best < 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  op.ap.variant = best;
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_applies[apply_key(op.ap)] = best;
+}
+
 void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hipStream_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TN_HIP(hipEventCreate(&e0));
   TN_HIP(hipEventCreate(&e1));
   std::map<TileKey, int> done;
+  std::map<std::vector<int>, int> done_apply;
   try {
     for (PlanOp& op : ops) {
+      if (op.kind == OP_APPLY && !op.f64) {
+        const auto key = apply_key(op.ap);
+        auto it = done_apply.find(key);
+        if (it != done_apply.end()) {
+          op.ap.variant = it->second;
+        } else {
+          autotune_apply(op, bufs, reps, e0, e1, s);
+          done_apply[key] = op.ap.variant;
+        }
+        continue;
+      }
       if (op.kind != OP_GEMM || op.f64) continue;
       auto it = done.find(key_of(op.gm));
       if (it != done.end()) {

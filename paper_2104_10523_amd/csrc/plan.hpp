@@ -65,11 +65,14 @@ TRef compile_pair(const TRef& X, const TRef& Y, const std::vector<int>& keep,
 
 void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t s);
 
-// Autotune cache: fastest tile id per GEMM shape (process-wide).
+// Autotune cache: fastest tile id per GEMM shape and fastest kernel per
+// apply descriptor (process-wide; -1 when not tuned).
+int tuned_apply(const ApplySmallDesc& d);
 int tuned_tile(const GemmDesc& g);
 void remember_tile(const GemmDesc& g, int tile);
-// Times every candidate tile of every GEMM op on the given buffers and
-// stores the fastest in the op (and the cache).  Synchronises `s`.
+// Times every candidate tile of every GEMM op, and every candidate kernel
+// of every apply op, on the given buffers and stores the fastest in the op
+// (and the cache).  Synchronises `s`.
 void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hipStream_t s);
 
 struct AmpPlan {

@@ -66,6 +66,10 @@ CASES = [
     ("apply_k2_n2", dict(nm=16, nk=2, nn=2)),
     ("apply_k4_n4", dict(nm=12, nk=4, nn=4)),
     ("apply_k6_n0", dict(nm=10, nk=6, nn=0)),
+    # 16 outputs per row: the matrix-core apply (32-row groups, KK = 2 .. 64)
+    ("apply_k1_n4", dict(nm=16, nk=1, nn=4)),
+    ("apply_k3_n4_many_groups", dict(nm=20, nk=3, nn=4)),
+    ("apply_k6_n4", dict(nm=5, nk=6, nn=4)),
     ("gemm_square", dict(nm=9, nk=7, nn=8)),
     ("gemm_ragged_small_mn", dict(nm=5, nk=6, nn=5)),
     ("gemm_n16", dict(nm=11, nk=7, nn=4 + 1)),
