@@ -104,6 +104,11 @@ def parse():
                     help="run the GEMM tile autotuner before the warmup (its trial launches appear in kernel traces)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c3", "traj", "mps", "pmps", "learned", "expval", "dm"],
                     help="c2 (default) is the benchmark line; the others measure the remaining rows")
+    ap.add_argument("--learned-train", type=int, default=5000, help="learned row: training circuits")
+    ap.add_argument("--learned-test", type=int, default=200, help="learned row: held-out circuits")
+    ap.add_argument("--learned-epochs", type=int, default=6)
+    ap.add_argument("--learned-batch", type=int, default=64)
+    ap.add_argument("--learned-lr", type=float, default=1e-3)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
     return ap.parse_args()
@@ -456,38 +461,144 @@ def bench_mps(a):
                                        f"gates in {t_cpu:.1f} s (BLAS/LAPACK threads: {threads})"}}
 
 
+def _learned_corpus_teachers(m, ids, trials, states_per_circuit):
+    """Teacher paths (best of `trials` randomised-greedy paths) of corpus
+    circuits `ids`, sampled at about `states_per_circuit` states each into the
+    model's training set; returns the number of states added."""
+    import paper_2104_10523_amd as tn
+    from workloads import path_search_circuit
+    added = 0
+    for i in ids:
+        n, ops = path_search_circuit(i)
+        net = tn.tn_build_network(n, ops)
+        teacher = tn.tn_find_path(net, "random_greedy", trials=trials, seed=i, temperature=0.5)
+        steps = len(teacher.pairs)
+        stride = max(1, steps // states_per_circuit)
+        m.add_teacher(net, teacher.pairs, stride=stride)
+        added += len(range(0, steps - 1, stride))   # states with more than two live tensors
+    return added
+
+
+def _geomean_ratio(a, b):
+    return float(2.0 ** np.mean(np.log2(np.asarray(a)) - np.log2(np.asarray(b))))
+
+
 def bench_learned(a):
-    """Scorer training by imitation and the learned path on held-out grids."""
+    """Learned contraction-order proposer at the path-search corpus scale:
+    a.learned_train training circuits (30-60 qubits, 8-16 CZ cycles), each
+    labelled by the best of 32 randomised-greedy paths and sampled at ~16
+    states; a.learned_test held-out circuits searched by greedy, the learned
+    scorer (greedy fallback), the same scorer untrained, the 32-trial teacher
+    and randomised greedy given the learned search's wall time.  End-to-end
+    time of one amplitude (search + plan + contraction, auto precision) on
+    held-out circuits whose learned and equal-time paths both stay within 2^40
+    flops."""
+    import torch
     import paper_2104_10523_amd as tn
     from oracle import gnn
-    from workloads import grid_random_circuit, scorer_init
+    from workloads import path_search_circuit, random_bitstrings, scorer_init
     H, L = 128, 4
+    theta0 = scorer_init(gnn.param_shapes(H, L), 11)
     m = tn.Model(H, L)
-    m.set_params(scorer_init(gnn.param_shapes(H, L), 11))
-    shapes = [(4, 5), (4, 6), (5, 5), (5, 6), (6, 6)]
-    for i in range(60):
-        r, c = shapes[i % len(shapes)]
-        n, ops = grid_random_circuit(r, c, 8 + i % 9, 100000 + i)
-        net = tn.tn_build_network(n, ops)
-        teacher = tn.tn_find_path(net, "random_greedy", trials=32, seed=i, temperature=0.5)
-        m.add_teacher(net, teacher.pairs, stride=2)
+    m.set_params(theta0)
+    m0 = tn.Model(H, L)
+    m0.set_params(theta0)
     t0 = time.perf_counter()
-    first, last = m.train(epochs=8, batch=16, lr=2e-3, seed=3)
+    n_states = 0
+    for c0 in range(0, a.learned_train, 500):
+        n_states += _learned_corpus_teachers(m, range(c0, min(a.learned_train, c0 + 500)), 32, 16)
+        print(f"# learned: {min(a.learned_train, c0 + 500)} teacher paths, {n_states} states, "
+              f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    t_label = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    first, last = m.train(epochs=a.learned_epochs, batch=a.learned_batch, lr=a.learned_lr, seed=3)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    gains = []
-    for i in range(20):
-        r, c = shapes[i % len(shapes)]
-        n, ops = grid_random_circuit(r, c, 8 + i % 9, 200000 + i)
+    steps = a.learned_epochs * -(-n_states // a.learned_batch)
+    print(f"# learned: trained {steps} steps in {t_train:.1f} s, loss {first:.3f} -> {last:.3f}",
+          file=sys.stderr, flush=True)
+
+    def timed_path(fn):
+        t = time.perf_counter()
+        p = fn()
+        return p, time.perf_counter() - t
+
+    rows = []
+    for i in range(5000, 5000 + a.learned_test):
+        n, ops = path_search_circuit(i)
         net = tn.tn_build_network(n, ops)
-        g = tn.tn_find_path(net, "greedy")
-        lp = tn.tn_find_path_learned(net, m)
-        gains.append(math.log2(g.cost.flops_per_slice / lp.cost.flops_per_slice))
-    return {"metric": "learned path: mean log2 flop gain over greedy on held-out grids", "value": float(np.mean(gains)),
-            "unit": "log2", "dtype": "fp32 training",
-            "config": {"workload": "60 training / 20 held-out grid circuits (20-36 qubits, depth 8-16)",
-                       "train_seconds": t_train, "loss_first": first, "loss_last": last,
-                       "win_rate": float(np.mean([x > 0 for x in gains]))},
-            "roofline": None, "cpu_baseline": None}
+        g, tg = timed_path(lambda: tn.tn_find_path(net, "greedy"))
+        lp, tl = timed_path(lambda: tn.tn_find_path_learned(net, m))
+        l0 = tn.tn_find_path_learned(net, m0)
+        r32, tr = timed_path(lambda: tn.tn_find_path(net, "random_greedy", trials=32, seed=i, temperature=0.5))
+        eq = max(1, int(round(32 * tl / tr)))
+        req, te = timed_path(lambda: tn.tn_find_path(net, "random_greedy", trials=eq, seed=i, temperature=0.5))
+        rows.append(dict(i=i, n=n, greedy=g.cost.flops_per_slice, learned=lp.cost.flops_per_slice,
+                         untrained=l0.cost.flops_per_slice, teacher=r32.cost.flops_per_slice,
+                         equal_time=req.cost.flops_per_slice, chosen=lp.cost.algo_used == 2,
+                         t_greedy=tg, t_learned=tl, t_teacher=tr, t_equal=te, eq_trials=eq,
+                         pairs_learned=lp.pairs, pairs_equal=req.pairs))
+        if len(rows) % 50 == 0:
+            print(f"# learned: {len(rows)} held-out circuits searched", file=sys.stderr, flush=True)
+    col = {k: np.array([r[k] for r in rows]) for k in rows[0] if not k.startswith("pairs")}
+
+    # end-to-end amplitude time: search + plan + contraction of one amplitude
+    ws = torch.empty(64 << 30, dtype=torch.uint8, device="cuda")
+    tn.tn_set_workspace(ws)
+    e2e = []
+    for r in rows:
+        if max(r["learned"], r["equal_time"]) > 2.0 ** 40:
+            continue
+        n, ops = path_search_circuit(r["i"])
+        net = tn.tn_build_network(n, ops)
+        bits = random_bitstrings(1, n, r["i"])
+        rec = {"i": r["i"], "n": n}
+        for name, pairs, ts in (("learned", r["pairs_learned"], r["t_learned"]),
+                                ("equal_time", r["pairs_equal"], r["t_equal"])):
+            t = time.perf_counter()
+            p = tn.tn_path_from_pairs(net, pairs, mem_budget_bytes=16.0 * 2 ** 30)
+            if tn.tn_amplitudes_workspace(net, p, 1, "auto") > ws.numel():
+                rec = None
+                break
+            out, rep = tn.tn_amplitudes(net, p, bits, precision="auto")
+            rec[name] = ts + time.perf_counter() - t
+            rec[name + "_amp"] = complex(out.cpu().numpy()[0, 0])
+        if rec is not None:
+            e2e.append(rec)
+    del ws
+    torch.cuda.empty_cache()
+    amp_diff = max((abs(x["learned_amp"] - x["equal_time_amp"]) / max(abs(x["equal_time_amp"]), 2.0 ** (-x["n"] / 2))
+                    for x in e2e), default=None)
+    gains = np.log2(col["greedy"] / col["learned"])
+    res = {
+        "metric": "learned path: mean log2 flop gain over greedy on held-out circuits",
+        "value": float(np.mean(gains)), "unit": "log2", "higher_is_better": True, "dtype": "fp32 training",
+        "config": {"workload": f"path-search corpus: {a.learned_train} training / {a.learned_test} held-out "
+                               f"circuits, 30-60 qubits, 8-16 CZ cycles",
+                   "scorer": f"H={H}, L={L}, {m.n_params} parameters", "states": n_states,
+                   "teacher_seconds": t_label, "train_seconds": t_train, "train_steps": steps,
+                   "train_steps_per_s": steps / t_train, "epochs": a.learned_epochs, "batch": a.learned_batch,
+                   "loss_first": first, "loss_last": last},
+        "held_out": {
+            "learned_chosen_fraction": float(np.mean(col["chosen"])),
+            "geomean_flops_learned_over_greedy": _geomean_ratio(col["learned"], col["greedy"]),
+            "geomean_flops_untrained_over_greedy": _geomean_ratio(col["untrained"], col["greedy"]),
+            "geomean_flops_learned_over_teacher32": _geomean_ratio(col["learned"], col["teacher"]),
+            "geomean_flops_learned_over_equal_time": _geomean_ratio(col["learned"], col["equal_time"]),
+            "learned_beats_equal_time_fraction": float(np.mean(col["learned"] < col["equal_time"])),
+            "median_search_seconds": {k: float(np.median(col["t_" + k]))
+                                      for k in ("greedy", "learned", "teacher", "equal")},
+            "median_equal_time_trials": float(np.median(col["eq_trials"])),
+            "log2_gain_over_greedy_quartiles": [float(x) for x in np.percentile(gains, [25, 50, 75])]},
+        "end_to_end": {
+            "circuits": len(e2e),
+            "median_seconds_learned": float(np.median([x["learned"] for x in e2e])) if e2e else None,
+            "median_seconds_equal_time": float(np.median([x["equal_time"] for x in e2e])) if e2e else None,
+            "total_seconds_learned": float(sum(x["learned"] for x in e2e)),
+            "total_seconds_equal_time": float(sum(x["equal_time"] for x in e2e)),
+            "max_floored_amplitude_difference": amp_diff},
+        "roofline": None, "cpu_baseline": None}
+    return res
 
 
 def bench_expval(a):
@@ -687,6 +798,8 @@ def op_kernel_name(precision, k, sh):
     if k == 2:
         return kernel_name(precision, int(sh[4]), int(sh[5]))
     if k == 0:
+        if int(sh[3]) == 2:
+            return f"apply16_mfma_kernel<{int(sh[2])}>"
         return f"{'apply_tile_kernel' if sh[3] else 'apply_small_kernel'}<{int(sh[1])}>"
     if k == 3:
         return f"skinny_partial_kernel<{int(sh[0])}, {int(sh[1])}>" if sh[5] else "dot_partial_kernel"

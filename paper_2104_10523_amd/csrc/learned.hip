@@ -26,35 +26,27 @@ struct StateFeat {
   std::vector<int> ptr, idx; // CSR line-graph neighbours, ascending
 };
 
-// Features of every candidate of a state (see include/tn.h for the list).
-StateFeat featurize(const PathState& st, int n_leaves) {
+// Features of every candidate of a state (see include/tn.h for the list),
+// from the candidate sizes the CandidateSet keeps current.
+StateFeat featurize(const PathState& st, const CandidateSet& cs, int n_leaves) {
   StateFeat f;
-  f.cand = st.candidates();
-  const int nc = int(f.cand.size());
-  const auto& ext = st.pr.ext;
+  const auto& cl = cs.list();
+  const int nc = int(cl.size());
+  f.cand.resize(nc);
   std::vector<int> deg(st.sets.size(), 0);
-  for (auto [i, j] : f.cand) {
-    deg[i]++;
-    deg[j]++;
-  }
   struct Row {
     double a, b, c, u, sig;
-    int shared;
   };
   std::vector<Row> rows(nc);
   double smin = INFINITY, umin = INFINITY;
   for (int k = 0; k < nc; ++k) {
-    const auto [i, j] = f.cand[k];
-    const auto &A = st.sets[i], &B = st.sets[j];
-    const auto C = st.result(i, j);
-    const double sa = size_of_labels(A, ext), sb = size_of_labels(B, ext), sc = size_of_labels(C, ext);
-    const double su = size_of_labels(union_of(A, B), ext);
-    const double d = sc - sa - sb;
+    const Cand& q = cl[k];
+    f.cand[k] = {q.i, q.j};
+    deg[q.i]++;
+    deg[q.j]++;
+    const double d = q.sc - q.sa - q.sb;
     const double sig = std::copysign(std::log2(1.0 + std::fabs(d)), d);
-    int shared = 0;
-    for (int l : A)
-      if (std::binary_search(B.begin(), B.end(), l)) ++shared;
-    rows[k] = {std::log2(sa), std::log2(sb), std::log2(sc), std::log2(su), sig, shared};
+    rows[k] = {std::log2(q.sa), std::log2(q.sb), std::log2(q.sc), std::log2(q.su), sig};
     smin = std::min(smin, sig);
     umin = std::min(umin, rows[k].u);
   }
@@ -77,7 +69,7 @@ StateFeat featurize(const PathState& st, int n_leaves) {
     x[11] = (r.u - umin) / 8;
     x[12] = double(deg[i]) / 16;
     x[13] = double(deg[j]) / 16;
-    x[14] = r.shared == 0 ? 1.0 : 0.0;
+    x[14] = cl[k].shared == 0 ? 1.0 : 0.0;
     x[15] = 1.0;
   }
   std::vector<std::vector<int>> by_t(st.sets.size());
@@ -97,44 +89,70 @@ StateFeat featurize(const PathState& st, int n_leaves) {
 
 // ------------------------------------------------------------------ kernels
 
+using floatx16 = __attribute__((__vector_size__(16 * sizeof(float)))) float;
+
 // C[M,N] = op(A) op(B) (+ C) (+ bias[n]) (relu); op(A)[m][k] = transA ?
 // A[k*lda+m] : A[m*lda+k]; op(B)[k][n] = transB ? B[n*ldb+k] : B[k*ldb+n].
-__global__ __launch_bounds__(256) void sgemm_kernel(const float* __restrict__ A, const float* __restrict__ B,
-                                                    float* __restrict__ C, int M, int N, int K, int lda, int ldb,
-                                                    int ldc, int transA, int transB, int accumulate,
-                                                    const float* __restrict__ bias, int relu) {
-  __shared__ float As[16][65], Bs[16][65];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+// FP32 matrix cores: a 64 x 64 tile per block of four waves, each wave one
+// 32 x 32 accumulator of v_mfma_f32_32x32x2f32 (lane l feeds A row l % 32
+// and B column l % 32 at k offset l / 32; accumulator register r holds row
+// 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32).  K is staged through
+// LDS 16 at a time.  With gridDim.z > 1 block z covers k in [z kchunk,
+// (z + 1) kchunk) and adds its tile into C atomically (no bias or relu then;
+// C holds zero or the term to accumulate).
+__global__ __launch_bounds__(256) void sgemm_mfma_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                                                         float* __restrict__ C, int M, int N, int K, int lda, int ldb,
+                                                         int ldc, int transA, int transB, int accumulate,
+                                                         const float* __restrict__ bias, int relu, int kchunk) {
+  __shared__ float As[64][17];   // [m][k]: a wave's 32 rows fall on distinct banks
+  __shared__ float Bs[16][65];   // [k][n]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 31, lh = lane >> 5;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  floatx16 acc = {};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int kk = e / 64, mm = e % 64;
-      const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? (transA ? A[int64_t(k) * lda + m] : A[int64_t(m) * lda + k]) : 0.f;
-      const int n = n0 + mm;
-      Bs[kk][mm] = (n < N && k < K) ? (transB ? B[int64_t(n) * ldb + k] : B[int64_t(k) * ldb + n]) : 0.f;
+      // the index fastest in memory runs fastest over threads
+      int mm = transA ? (e & 63) : (e >> 4), kk = transA ? (e >> 6) : (e & 15);
+      int m = m0 + mm, k = k0 + kk;
+      As[mm][kk] = (m < M && k < ke) ? (transA ? A[int64_t(k) * lda + m] : A[int64_t(m) * lda + k]) : 0.f;
+      const int nn = transB ? (e >> 4) : (e & 63);
+      kk = transB ? (e & 15) : (e >> 6);
+      const int n = n0 + nn;
+      k = k0 + kk;
+      Bs[kk][nn] = (n < N && k < ke) ? (transB ? B[int64_t(n) * ldb + k] : B[int64_t(k) * ldb + n]) : 0.f;
     }
     __syncthreads();
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-      for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
-    }
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[wm + li][kk + lh], Bs[kk + lh][wn + li], acc, 0, 0, 0);
     __syncthreads();
   }
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-      if (m >= M || n >= N) continue;
-      float v = acc[i][j];
-      if (accumulate) v += C[int64_t(m) * ldc + n];
+  const int n = n0 + wn + li;
+  if (n >= N) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm + 8 * (r >> 2) + 4 * lh + (r & 3);
+    if (m >= M) continue;
+    float* c = C + int64_t(m) * ldc + n;
+    if (gridDim.z > 1) {
+      atomicAdd(c, acc[r]);
+    } else {
+      float v = acc[r];
+      if (accumulate) v += *c;
       if (bias) v += bias[n];
       if (relu) v = fmaxf(v, 0.f);
-      C[int64_t(m) * ldc + n] = v;
+      *c = v;
     }
+  }
+}
+
+__global__ void zero_rows_kernel(float* __restrict__ C, int M, int N, int ldc) {
+  const int64_t n = int64_t(M) * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    C[(e / N) * ldc + e % N] = 0.f;
 }
 
 // forward (transpose = 0): out[i] = mean_{j in nbr(i)} h[j];
@@ -165,11 +183,14 @@ __global__ void mask_kernel(float* __restrict__ g, const float* __restrict__ h, 
     if (!(h[e] > 0.f)) g[e] = 0.f;
 }
 
-__global__ void colsum_kernel(const float* __restrict__ G, float* __restrict__ out, int N, int H) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < H; c += gridDim.x * blockDim.x) {
+// out[c] += sum_i G[i][c]: block b sums rows [b R, (b + 1) R) per column
+// and adds the partial atomically (out zeroed first).
+__global__ void colsum_kernel(const float* __restrict__ G, float* __restrict__ out, int N, int H, int R) {
+  const int i0 = blockIdx.x * R, i1 = min(N, i0 + R);
+  for (int c = threadIdx.x; c < H; c += blockDim.x) {
     float s = 0.f;
-    for (int i = 0; i < N; ++i) s += G[int64_t(i) * H + c];
-    out[c] = s;
+    for (int i = i0; i < i1; ++i) s += G[int64_t(i) * H + c];
+    atomicAdd(&out[c], s);
   }
 }
 
@@ -284,9 +305,30 @@ namespace {
 
 void gemm(const float* A, const float* B, float* C, int M, int N, int K, int lda, int ldb, int ldc, int tA, int tB,
           int acc, const float* bias, int relu, hipStream_t s) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
-  sgemm_kernel<<<grid, 256, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, tA, tB, acc, bias, relu);
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int ksplit = 1, kchunk = std::max(K, 1);
+  // long-K products with few output tiles (weight gradients: K = nodes)
+  // split K over blocks so that the chip fills
+  if (!bias && !relu && tiles < 256 && K > 2048) {
+    ksplit = std::min((K + 1023) / 1024, std::max(1, 512 / tiles));
+    kchunk = ((K + ksplit - 1) / ksplit + 15) / 16 * 16;
+    ksplit = (K + kchunk - 1) / kchunk;
+  }
+  if (ksplit > 1 && !acc) {
+    zero_rows_kernel<<<blocks_for(int64_t(M) * N), 256, 0, s>>>(C, M, N, ldc);
+  }
+  dim3 grid((N + 63) / 64, (M + 63) / 64, ksplit);
+  sgemm_mfma_kernel<<<grid, 256, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, tA, tB, acc, bias, relu, kchunk);
   TN_HIP(hipGetLastError());
+}
+
+// out[0..H) = column sums of G[N][H]
+void colsum(const float* G, float* out, int N, int H, hipStream_t s) {
+  zero_rows_kernel<<<1, 256, 0, s>>>(out, 1, H, H);
+  if (N <= 0) return;
+  const int nb = std::max(1, std::min((N + 63) / 64, 1024));
+  const int R = (N + nb - 1) / nb;
+  colsum_kernel<<<(N + R - 1) / R, std::min(256, std::max(64, (H + 63) / 64 * 64)), 0, s>>>(G, out, N, H, R);
 }
 
 // Forward over `nodes` nodes already uploaded (X, ptr, idx); scores into m->s.
@@ -312,11 +354,11 @@ void backward(tn_model* m, int nodes, hipStream_t st) {
   float* G = m->G;
   // head
   gemm(m->hh(), m->ds, G + m->off_wo(), H, 1, nodes, H, 1, 1, 1, 0, 0, nullptr, 0, st);
-  colsum_kernel<<<1, 64, 0, st>>>(m->ds, G + m->off_bo(), nodes, 1);
+  colsum(m->ds, G + m->off_bo(), nodes, 1, st);
   gemm(m->ds, P + m->off_wo(), m->t1(), nodes, H, 1, 1, H, H, 0, 0, 0, nullptr, 0, st);   // dhh
   mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t1(), m->hh(), int64_t(nodes) * H);
   gemm(m->hbuf(m->L), m->t1(), G + m->off_Wh(), H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
-  colsum_kernel<<<blocks_for(H), 256, 0, st>>>(m->t1(), G + m->off_bh(), nodes, H);
+  colsum(m->t1(), G + m->off_bh(), nodes, H, st);
   gemm(m->t1(), P + m->off_Wh(), m->t2(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);   // dh_L
   for (int l = m->L - 1; l >= 0; --l) {
     const int64_t o = m->off_layer(l);
@@ -324,7 +366,7 @@ void backward(tn_model* m, int nodes, hipStream_t st) {
     mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t2(), m->hbuf(l + 1), int64_t(nodes) * H);
     gemm(m->hbuf(l), m->t2(), G + o, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
     gemm(m->mbuf(l), m->t2(), G + o + int64_t(H) * H, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
-    colsum_kernel<<<blocks_for(H), 256, 0, st>>>(m->t2(), G + o + 2 * int64_t(H) * H, nodes, H);
+    colsum(m->t2(), G + o + 2 * int64_t(H) * H, nodes, H, st);
     // dh_l = dz Ws^T + agg^T(dz Wn^T): t1 = dz Wn^T, then mbuf(l) <- agg^T(t1)
     gemm(m->t2(), P + o + int64_t(H) * H, m->t1(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);
     agg_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t1(), m->ptr, m->idx, m->mbuf(l), nodes, H, 1);
@@ -333,7 +375,7 @@ void backward(tn_model* m, int nodes, hipStream_t st) {
   }
   mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t2(), m->hbuf(0), int64_t(nodes) * H);
   gemm(m->X, m->t2(), G + m->off_W0(), kF, H, nodes, kF, H, H, 1, 0, 0, nullptr, 0, st);
-  colsum_kernel<<<blocks_for(H), 256, 0, st>>>(m->t2(), G + m->off_b0(), nodes, H);
+  colsum(m->t2(), G + m->off_b0(), nodes, H, st);
   TN_HIP(hipGetLastError());
 }
 
@@ -389,9 +431,10 @@ std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* mc, 
   std::vector<std::pair<int, int>> path;
   try {
     PathState state(pr, {});
+    CandidateSet cs(state);
     const int n_leaves = int(pr.leaves.size());
     while (state.n_alive > 1) {
-      const StateFeat f = featurize(state, n_leaves);
+      const StateFeat f = featurize(state, cs, n_leaves);
       const int nc = int(f.cand.size());
       tn_model::Sample smp = make_sample(f, 0);
       int nodes = 0;
@@ -404,7 +447,7 @@ std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* mc, 
       for (int k = 1; k < nc; ++k)
         if (sc[k] > sc[best]) best = k;
       path.push_back(f.cand[best]);
-      state.merge(f.cand[best].first, f.cand[best].second);
+      cs.merge(state, f.cand[best].first, f.cand[best].second);
     }
   } catch (...) {
     (void)hipStreamDestroy(st);
@@ -491,7 +534,7 @@ tn_status tn_model_state_features(const tn_network* n, const int8_t* open_mask, 
       st.merge(i, j);
     }
     TN_REQUIRE(st.n_alive > 1, TN_ERR_STATE, "no candidates left after the prefix");
-    const StateFeat f = featurize(st, int(pr.leaves.size()));
+    const StateFeat f = featurize(st, CandidateSet(st), int(pr.leaves.size()));
     const int nc = int(f.cand.size());
     if (n_cands) *n_cands = nc;
     if (n_nbr) *n_nbr = int(f.idx.size());
@@ -549,10 +592,11 @@ tn_status tn_model_add_teacher(tn_model* m, const tn_network* n, const int8_t* o
       for (int q = 0; q < n->net.n_qubits; ++q) open_q[q] = open_mask[q] ? 1 : 0;
     const PathProblem pr = make_problem(n->net, open_q);
     PathState st(pr, {});
+    CandidateSet cs(st);
     for (int t = 0; t < n_steps; ++t) {
       const std::pair<int, int> step{pairs[2 * t], pairs[2 * t + 1]};
       if (t % stride == 0 && st.n_alive > 2) {
-        const StateFeat f = featurize(st, int(pr.leaves.size()));
+        const StateFeat f = featurize(st, cs, int(pr.leaves.size()));
         const auto it = std::find(f.cand.begin(), f.cand.end(), step);
         TN_REQUIRE(it != f.cand.end(), TN_ERR_ARG, "teacher step is not a candidate");
         m->data.push_back(make_sample(f, int(it - f.cand.begin())));
@@ -560,7 +604,7 @@ tn_status tn_model_add_teacher(tn_model* m, const tn_network* n, const int8_t* o
       TN_REQUIRE(step.first >= 0 && step.second >= 0 && step.first < int(st.sets.size()) &&
                      step.second < int(st.sets.size()) && st.alive[step.first] && st.alive[step.second],
                  TN_ERR_ARG, "teacher path uses a consumed or unknown tensor");
-      st.merge(step.first, step.second);
+      cs.merge(st, step.first, step.second);
     }
   });
 }

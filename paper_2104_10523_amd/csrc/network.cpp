@@ -208,49 +208,121 @@ PathProblem make_problem(const Network& net, const std::vector<char>& open_q) {
   return pr;
 }
 
+CandidateSet::CandidateSet(const PathState& st) : by_label_(st.pr.ext.size()) {
+  for (size_t i = 0; i < st.sets.size(); ++i)
+    if (st.alive[i])
+      for (int l : st.sets[i]) by_label_[l].push_back(int(i));
+  std::vector<std::pair<int, int>> pairs;
+  for (const auto& ids : by_label_)
+    for (size_t x = 0; x < ids.size(); ++x)
+      for (size_t y = x + 1; y < ids.size(); ++y) pairs.push_back({ids[x], ids[y]});
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  for (auto [i, j] : pairs) c_.push_back(make(st, i, j));
+  if (c_.empty() && st.n_alive > 1) all_pairs(st);
+}
+
+Cand CandidateSet::make(const PathState& st, int i, int j) const {
+  const Set &a = st.sets[i], &b = st.sets[j];
+  const auto& ext = st.pr.ext;
+  int shared = 0;
+  for (int l : a)
+    if (std::binary_search(b.begin(), b.end(), l)) ++shared;
+  return {i, j, size_of(a, ext), size_of(b, ext), size_of(st.result(i, j), ext), size_of(set_union(a, b), ext),
+          shared};
+}
+
+void CandidateSet::all_pairs(const PathState& st) {
+  all_pairs_ = true;
+  c_.clear();
+  std::vector<int> ids;
+  for (size_t i = 0; i < st.sets.size(); ++i)
+    if (st.alive[i]) ids.push_back(int(i));
+  for (size_t x = 0; x < ids.size(); ++x)
+    for (size_t y = x + 1; y < ids.size(); ++y) c_.push_back(make(st, ids[x], ids[y]));
+}
+
+int CandidateSet::merge(PathState& st, int i, int j) {
+  for (int t : {i, j})
+    for (int l : st.sets[t]) {
+      auto& v = by_label_[l];
+      v.erase(std::lower_bound(v.begin(), v.end(), t));
+    }
+  const int k = st.merge(i, j);
+  for (int l : st.sets[k]) by_label_[l].push_back(k);
+  // partners of k, ascending
+  std::vector<int> xs;
+  if (all_pairs_) {
+    for (int x = 0; x < k; ++x)
+      if (st.alive[x]) xs.push_back(x);
+  } else {
+    for (int l : st.sets[k])
+      for (int x : by_label_[l])
+        if (x != k) xs.push_back(x);
+    std::sort(xs.begin(), xs.end());
+    xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+  }
+  // (x, k) sorts after every (x, y < k) and before every (x' > x, .)
+  std::vector<Cand> next;
+  next.reserve(c_.size() + xs.size());
+  size_t q = 0;
+  for (const Cand& e : c_) {
+    if (e.i == i || e.j == i || e.i == j || e.j == j) continue;
+    while (q < xs.size() && xs[q] < e.i) next.push_back(make(st, xs[q++], k));
+    next.push_back(e);
+  }
+  while (q < xs.size()) next.push_back(make(st, xs[q++], k));
+  c_.swap(next);
+  if (c_.empty() && !all_pairs_ && st.n_alive > 1) all_pairs(st);
+  return k;
+}
+
 std::vector<std::pair<int, int>> greedy_path(const PathProblem& pr, uint64_t* rng,
                                              double temperature) {
   State st(pr, {});
+  CandidateSet cs(st);
   std::vector<std::pair<int, int>> path;
+  std::vector<double> sig, w;
   while (st.n_alive > 1) {
-    auto cands = st.candidates();
-    std::vector<double> d(cands.size()), fl(cands.size());
-    for (size_t k = 0; k < cands.size(); ++k) {
-      const auto [i, j] = cands[k];
-      const Set c = st.result(i, j);
-      d[k] = size_of(c, pr.ext) - size_of(st.sets[i], pr.ext) - size_of(st.sets[j], pr.ext);
-      fl[k] = 8.0 * size_of(set_union(st.sets[i], st.sets[j]), pr.ext);
-    }
+    const auto& cands = cs.list();
+    const size_t nc = cands.size();
+    auto d_of = [&](size_t k) { return cands[k].sc - cands[k].sa - cands[k].sb; };
     size_t pick = 0;
     if (rng == nullptr) {
-      for (size_t k = 1; k < cands.size(); ++k) {
-        if (d[k] < d[pick] || (d[k] == d[pick] && (fl[k] < fl[pick] ||
-            (fl[k] == fl[pick] && cands[k] < cands[pick]))))
+      double dp = d_of(0), fp = 8.0 * cands[0].su;
+      for (size_t k = 1; k < nc; ++k) {
+        const double dk = d_of(k), fk = 8.0 * cands[k].su;
+        if (dk < dp || (dk == dp && fk < fp)) {   // ties keep the lower pair (ascending order)
           pick = k;
+          dp = dk;
+          fp = fk;
+        }
       }
     } else {
-      std::vector<double> sig(cands.size());
+      sig.resize(nc);
+      w.resize(nc);
       double smin = std::numeric_limits<double>::infinity();
-      for (size_t k = 0; k < cands.size(); ++k) {
-        sig[k] = std::copysign(std::log2(1.0 + std::fabs(d[k])), d[k]);
+      for (size_t k = 0; k < nc; ++k) {
+        const double d = d_of(k);
+        sig[k] = std::copysign(std::log2(1.0 + std::fabs(d)), d);
         smin = std::min(smin, sig[k]);
       }
-      std::vector<double> w(cands.size());
       double tot = 0.0;
-      for (size_t k = 0; k < cands.size(); ++k) {
+      for (size_t k = 0; k < nc; ++k) {
         w[k] = std::exp(-(sig[k] - smin) / temperature);
         tot += w[k];
       }
       const double u = splitmix64_uniform(rng) * tot;
       double acc = 0.0;
-      pick = cands.size() - 1;
-      for (size_t k = 0; k < cands.size(); ++k) {
+      pick = nc - 1;
+      for (size_t k = 0; k < nc; ++k) {
         acc += w[k];
         if (acc >= u) { pick = k; break; }
       }
     }
-    st.merge(cands[pick].first, cands[pick].second);
-    path.push_back(cands[pick]);
+    const std::pair<int, int> step{cands[pick].i, cands[pick].j};
+    cs.merge(st, step.first, step.second);
+    path.push_back(step);
   }
   return path;
 }

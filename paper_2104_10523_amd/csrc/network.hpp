@@ -62,6 +62,34 @@ struct PathState {
   std::vector<std::pair<int, int>> candidates() const;
 };
 
+// One candidate pair (i < j) with the sizes the path searches rank it by:
+// |A|, |B|, |C| (the result), |A u B| (flops / 8) and the shared label count.
+struct Cand {
+  int i, j;
+  double sa, sb, sc, su;
+  int shared;
+};
+
+// The candidate pairs of a PathState kept current across merges, in the
+// order and with the values PathState::candidates() + result() give.  A
+// merge (i, j) -> k changes the result of no pair that avoids i, j and k: a
+// label whose count drops is still held by k, so every other pair keeps it.
+// Hence only pairs with i or j are dropped and pairs (x, k) added.
+class CandidateSet {
+ public:
+  explicit CandidateSet(const PathState& st);
+  // st.merge(i, j) plus the candidate update; returns the new SSA id.
+  int merge(PathState& st, int i, int j);
+  const std::vector<Cand>& list() const { return c_; }
+
+ private:
+  Cand make(const PathState& st, int i, int j) const;
+  void all_pairs(const PathState& st);
+  std::vector<std::vector<int>> by_label_;   // live tensors per label, ascending
+  std::vector<Cand> c_;
+  bool all_pairs_ = false;                   // no live pair shares a label
+};
+
 double size_of_labels(const std::vector<int>& s, const std::vector<double>& ext);
 std::vector<int> union_of(const std::vector<int>& a, const std::vector<int>& b);
 // Path problem of a network: projected output labels removed, open ones kept.

@@ -9,6 +9,7 @@ implemented separately by the oracle and by the native library.
 from .circuits import (  # noqa: F401
     Op,
     grid_random_circuit,
+    path_search_circuit,
     chain_random_circuit,
     cat_circuit,
     ghz_circuit,

@@ -97,6 +97,19 @@ def grid_random_circuit(rows: int, cols: int, cycles: int, seed: int,
     return n, ops
 
 
+def path_search_circuit(i: int) -> Tuple[int, List[Op]]:
+    """Circuit i of the path-search corpus: n in [30, 60] qubits on the first
+    n sites of a floor(sqrt(n)) x ceil(n / floor(sqrt(n))) grid, 8-16
+    cycles of the CZ grid family, all drawn from seed 100000 + i
+    (training set: i < 5000; held-out set: i >= 5000)."""
+    rng = np.random.default_rng(100000 + i)
+    n = int(rng.integers(30, 61))
+    cycles = int(rng.integers(8, 17))
+    rows = int(math.isqrt(n))
+    cols = -(-n // rows)
+    return grid_random_circuit(rows, cols, cycles, 100000 + i, n_qubits=n)
+
+
 def chain_random_circuit(n: int, cycles: int, seed: int,
                          fsim_params: Tuple[float, float] = (math.pi / 2, math.pi / 6)
                          ) -> Tuple[int, List[Op]]:
