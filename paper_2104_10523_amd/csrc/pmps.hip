@@ -200,6 +200,171 @@ constexpr int kMaxKraus = 16;
 
 using namespace tn;
 
+namespace {
+
+// ------------------------------------------------ rank-revealing pre-pass
+//
+// Pivoted Householder QR of W (mm x nn, column-major, mm >= nn, in place),
+// stopped at the numerical rank r: step j takes the column with the largest
+// remaining norm (rows j..) as pivot, and stops once that norm is below
+// 1e-13 of the largest column norm (the level of the factorisation's own
+// rounding).  After step j the column's rows > j hold the reflector, rd[j] =
+// R[j][j], and rows j of the later columns hold R[j][c]; perm[j] is the
+// input column now at j.  ctl[0] = r once found, ctl[1] = 1 then (later
+// steps do nothing).
+
+__global__ __launch_bounds__(256) void qrp_init_kernel(const double2* __restrict__ W, int mm, double* pn, int* perm,
+                                                       int* ctl) {
+  __shared__ double red[8];
+  const double2* w = W + int64_t(blockIdx.x) * mm;
+  double a = 0;
+  for (int i = threadIdx.x; i < mm; i += blockDim.x) a += w[i].x * w[i].x + w[i].y * w[i].y;
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    pn[blockIdx.x] = a;
+    perm[blockIdx.x] = blockIdx.x;
+    if (blockIdx.x == 0) ctl[0] = ctl[1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void qrp_pivot_kernel(double2* __restrict__ W, int mm, int nn, int j, double* pn,
+                                                        int* perm, int* ctl, double* thr2) {
+  if (ctl[1]) return;   // rank already found (uniform)
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int bc = nn;
+  for (int c = j + t; c < nn; c += 256)
+    if (pn[c] > best) {   // ascending c: ties keep the lowest index
+      best = pn[c];
+      bc = c;
+    }
+  bv[t] = best;
+  bi[t] = bc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o && (bv[t + o] > bv[t] || (bv[t + o] == bv[t] && bi[t + o] < bi[t]))) {
+      bv[t] = bv[t + o];
+      bi[t] = bi[t + o];
+    }
+    __syncthreads();
+  }
+  const int p = bi[0];
+  const double v = bv[0];
+  if (j == 0 && t == 0) *thr2 = 1e-26 * v;          // (1e-13 of the largest column norm)^2
+  const double lim = j == 0 ? 1e-26 * v : *thr2;
+  if (!(v > lim)) {                                   // numerical rank reached (uniform)
+    if (t == 0) {
+      ctl[0] = j;
+      ctl[1] = 1;
+    }
+    return;
+  }
+  if (p != j) {
+    for (int i = t; i < mm; i += 256) {
+      const double2 a = W[int64_t(j) * mm + i];
+      W[int64_t(j) * mm + i] = W[int64_t(p) * mm + i];
+      W[int64_t(p) * mm + i] = a;
+    }
+    if (t == 0) {
+      const double x = pn[j];
+      pn[j] = pn[p];
+      pn[p] = x;
+      const int q = perm[j];
+      perm[j] = perm[p];
+      perm[p] = q;
+    }
+  }
+}
+
+// Reflector of column j (rows j..): v = x - beta e_j, beta = -e^{i arg x_j} |x|,
+// rd[j] = beta, tau[j] = 2 / |v|^2.
+__global__ __launch_bounds__(256) void qrp_reflect_kernel(double2* __restrict__ W, int mm, int j, double2* rd,
+                                                          double2* tau, const int* ctl) {
+  if (ctl[1]) return;
+  __shared__ double red[8];
+  double2* x = W + int64_t(j) * mm;
+  double ss = 0;
+  for (int i = j + threadIdx.x; i < mm; i += blockDim.x) ss += x[i].x * x[i].x + x[i].y * x[i].y;
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) {
+    const double2 alpha = x[j];
+    const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+    const double nrm = sqrt(ss);
+    const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
+    const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+    const double2 v0 = make_double2(alpha.x - beta.x, alpha.y - beta.y);
+    const double vn2 = ss - an * an + v0.x * v0.x + v0.y * v0.y;
+    x[j] = v0;
+    rd[j] = beta;
+    tau[j] = make_double2(vn2 > 0 ? 2.0 / vn2 : 0.0, 0.0);
+  }
+}
+
+// Applies reflector j to columns j+1 .. nn-1 (one wave per column, rows j..)
+// and leaves each column's remaining norm (rows j+1..) in pn.
+__global__ __launch_bounds__(256) void qrp_apply_kernel(double2* __restrict__ W, int mm, int nn, int j,
+                                                        const double2* __restrict__ tau, double* pn, const int* ctl) {
+  if (ctl[1]) return;
+  const int c = j + 1 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= nn) return;
+  const double t2 = tau[j].x;
+  const double2* v = W + int64_t(j) * mm;
+  double2* y = W + int64_t(c) * mm;
+  double dr = 0, di = 0;
+  for (int i = j + lane; i < mm; i += 64) {
+    const double2 a = v[i], b = y[i];
+    dr += a.x * b.x + a.y * b.y;
+    di += a.x * b.y - a.y * b.x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dr += __shfl_xor(dr, o);
+    di += __shfl_xor(di, o);
+  }
+  const double2 f = make_double2(t2 * dr, t2 * di);
+  double rest = 0;
+  for (int i = j + lane; i < mm; i += 64) {
+    const double2 fv = cmul(v[i], f);
+    double2 b = y[i];
+    b.x -= fv.x;
+    b.y -= fv.y;
+    y[i] = b;
+    if (i > j) rest += b.x * b.x + b.y * b.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) rest += __shfl_xor(rest, o);
+  if (lane == 0) pn[c] = rest;
+}
+
+// X = R_r^dagger (nn x r, column-major): X[c, k] = conj(R[k][c]), zero below R's diagonal.
+__global__ void qrp_form_x_kernel(const double2* __restrict__ W, int mm, int nn, int r, const double2* __restrict__ rd,
+                                  double2* __restrict__ X) {
+  const int64_t n = int64_t(nn) * r;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(e / nn), c = int(e % nn);
+    double2 v = make_double2(0, 0);
+    if (c > k) v = W[int64_t(c) * mm + k];
+    else if (c == k) v = rd[k];
+    X[e] = make_double2(v.x, -v.y);
+  }
+}
+
+// Right singular vectors: V[perm[c], k] = X[c, k] / S[k] (nn x r, column-major).
+__global__ void qrp_right_kernel(const double2* __restrict__ X, const double* __restrict__ S,
+                                 const int* __restrict__ perm, int nn, int r, double2* __restrict__ V) {
+  const int64_t n = int64_t(nn) * r;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    const int k = int(e / nn), c = int(e % nn);
+    const double sk = S[k];
+    const double2 x = X[e];
+    V[int64_t(k) * nn + perm[c]] = sk > 0 ? make_double2(x.x / sk, x.y / sk) : make_double2(0, 0);
+  }
+}
+
+}  // namespace
+
 struct tn_pmps {
   int n = 0, dmax = 0, kmax = 0, center = 0;
   std::vector<int> chi;             // bond i between sites i and i+1
@@ -210,12 +375,19 @@ struct tn_pmps {
   float2* wide = nullptr;           // a first site whose Kraus leg a two-qubit channel has widened
   double2 *W = nullptr, *V = nullptr, *X = nullptr, *Q = nullptr, *R = nullptr, *tau = nullptr, *G = nullptr;
   double* S = nullptr;
+  // rank-revealing pre-pass of the SVD: copy of the input, R^dagger, pivots,
+  // partial column norms, R's diagonal, reflector scales, control words
+  double2 *Wo = nullptr, *XR = nullptr, *rd = nullptr, *qtau = nullptr;
+  double* pn = nullptr;
+  int *perm = nullptr, *ctl = nullptr;
+  double* qthr = nullptr;
   double* zbuf = nullptr;
   int* flag = nullptr;
   int* order = nullptr;
   void* gemm_work = nullptr;
   size_t gemm_work_bytes = 0, w_elems = 0, v_elems = 0, s_elems = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> sweeps;
+  std::map<std::pair<int, int>, hipGraphExec_t> sweeps_xr;   // Jacobi sweeps on XR
   std::map<std::pair<int, int>, hipGraphExec_t> qrs;
   hipStream_t gstream = nullptr;
 
@@ -225,10 +397,12 @@ struct tn_pmps {
 
   ~tn_pmps() {
     for (auto& kv : sweeps) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : sweeps_xr) (void)hipGraphExecDestroy(kv.second);
     for (auto& kv : qrs) (void)hipGraphExecDestroy(kv.second);
     for (float2* p : site) (void)hipFree(p);
     for (void* p : {(void*)theta, (void*)tmp, (void*)wide, (void*)W, (void*)V, (void*)X, (void*)Q, (void*)R, (void*)tau,
-                    (void*)G, (void*)S, (void*)zbuf, (void*)flag, (void*)order, gemm_work})
+                    (void*)G, (void*)S, (void*)zbuf, (void*)flag, (void*)order, gemm_work, (void*)Wo, (void*)XR,
+                    (void*)rd, (void*)qtau, (void*)pn, (void*)perm, (void*)ctl, (void*)qthr})
       if (p) (void)hipFree(p);
     if (gstream) (void)hipStreamDestroy(gstream);
   }
@@ -302,18 +476,15 @@ void pmps_move_center(tn_pmps* m, int target, hipStream_t s) {
   while (m->center > target) pmps_move_left(m, m->center, s);
 }
 
-// One-sided Jacobi on W (mm x nn) with V = I: sweeps (each captured once per
-// shape) until no pair rotates (at most 60), then column norms into S.
-// Returns the norms on the host.  Runs on the library stream after `s`.
-std::vector<double> pmps_svd(tn_pmps* m, int mm, int nn, hipStream_t s) {
-  TN_REQUIRE(size_t(mm) * nn <= m->w_elems && size_t(nn) * nn <= m->v_elems && size_t(nn) <= m->s_elems,
-             TN_ERR_UNSUPPORTED, "PMPS factorisation larger than its buffers");
-  ensure_gstream(m);
-  eye_kernel<<<grid_n(int64_t(nn) * nn), 256, 0, s>>>(m->V, nn, m->flag);
-  TN_HIP(hipGetLastError());
+// One-sided Jacobi sweeps on A (mm x nn) and V (nn x nn, set to I by the
+// caller), the sweep captured once per shape into `graphs`, until no pair
+// rotates (at most 60).  On the library stream.
+void jacobi_until_converged(tn_pmps* m, double2* A, double2* V, int mm, int nn,
+                            std::map<std::pair<int, int>, hipGraphExec_t>& graphs) {
+  if (nn < 2) return;
   const auto key = std::make_pair(mm, nn);
-  auto it = m->sweeps.find(key);
-  if (it == m->sweeps.end()) {
+  auto it = graphs.find(key);
+  if (it == graphs.end()) {
     const int npad = nn + (nn & 1);
     const double tol = 2.3e-16 * double(std::max(mm, 8));
     hipGraph_t g = nullptr;
@@ -321,30 +492,95 @@ std::vector<double> pmps_svd(tn_pmps* m, int mm, int nn, hipStream_t s) {
     TN_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
     flag_reset_kernel<<<1, 1, 0, m->gstream>>>(m->flag);
     for (int r = 0; r < npad - 1; ++r)
-      jacobi_round_kernel<<<npad / 2, 256, 0, m->gstream>>>(m->W, m->V, mm, nn, npad, r, tol, m->flag);
+      jacobi_round_kernel<<<npad / 2, 256, 0, m->gstream>>>(A, V, mm, nn, npad, r, tol, m->flag);
     const hipError_t e = hipStreamEndCapture(m->gstream, &g);
     TN_REQUIRE(e == hipSuccess, TN_ERR_DEVICE, "graph capture of the Jacobi sweep failed");
     TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     (void)hipGraphDestroy(g);
-    it = m->sweeps.emplace(key, ge).first;
+    it = graphs.emplace(key, ge).first;
   }
+  int sweeps = 0, flag = 1;
+  while (flag && sweeps < 60) {
+    TN_HIP(hipGraphLaunch(it->second, m->gstream));
+    TN_HIP(hipMemcpyAsync(&flag, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->gstream));
+    TN_HIP(hipStreamSynchronize(m->gstream));
+    ++sweeps;
+  }
+}
+
+// SVD of W (mm x nn, column-major): on return W (mm x r) holds
+// U S, V (nn x r) the right singular vectors (W_in = U S V^dagger), and the
+// r singular values come back on the host (and in m->S).  Narrow or wide
+// matrices (nn <= 32 or nn > mm): one-sided Jacobi on W itself (r = nn).
+// Tall ones with more columns first
+// reveal their numerical rank by a pivoted QR, W P = Q R, then run the
+// one-sided Jacobi on X = R_r^dagger (nn x r, rows of R past the rank
+// dropped): the columns of X are close to orthogonal, so few sweeps do
+// (the preconditioning of Drmac and Veselic), and a sweep has r - 1 rounds
+// instead of nn - 1.  With X V' = U' S: V = P U' and U S = W_in V.
+// Runs on the library stream after `s`.
+std::vector<double> pmps_svd(tn_pmps* m, int mm, int nn, hipStream_t s) {
+  TN_REQUIRE(size_t(mm) * nn <= m->w_elems && size_t(nn) * nn <= m->v_elems && size_t(nn) <= m->s_elems,
+             TN_ERR_UNSUPPORTED, "PMPS factorisation larger than its buffers");
+  ensure_gstream(m);
   hipEvent_t ev = nullptr;
   TN_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   TN_HIP(hipEventRecord(ev, s));
   TN_HIP(hipStreamWaitEvent(m->gstream, ev, 0));
-  int sweeps = 0, flag = 1;
-  if (nn > 1)
-    while (flag && sweeps < 60) {
-      TN_HIP(hipGraphLaunch(it->second, m->gstream));
-      TN_HIP(hipMemcpyAsync(&flag, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->gstream));
-      TN_HIP(hipStreamSynchronize(m->gstream));
-      ++sweeps;
-    }
-  colnorm_kernel<<<nn, 256, 0, m->gstream>>>(m->W, mm, m->S);
-  std::vector<double> S(nn);
-  TN_HIP(hipMemcpyAsync(S.data(), m->S, nn * sizeof(double), hipMemcpyDeviceToHost, m->gstream));
-  TN_HIP(hipStreamSynchronize(m->gstream));
   (void)hipEventDestroy(ev);
+  hipStream_t g = m->gstream;
+  int r = nn;
+  bool pre = nn > 32 && mm >= nn;
+  if (pre) {
+    TN_HIP(hipMemcpyAsync(m->Wo, m->W, size_t(mm) * nn * sizeof(double2), hipMemcpyDeviceToDevice, g));
+    qrp_init_kernel<<<nn, 256, 0, g>>>(m->W, mm, m->pn, m->perm, m->ctl);
+    TN_HIP(hipGetLastError());
+    for (int j0 = 0; j0 < nn; j0 += 16) {
+      for (int j = j0; j < std::min(nn, j0 + 16); ++j) {
+        qrp_pivot_kernel<<<1, 256, 0, g>>>(m->W, mm, nn, j, m->pn, m->perm, m->ctl, m->qthr);
+        qrp_reflect_kernel<<<1, 256, 0, g>>>(m->W, mm, j, m->rd, m->qtau, m->ctl);
+        if (j + 1 < nn)
+          qrp_apply_kernel<<<(nn - j - 1 + 3) / 4, 256, 0, g>>>(m->W, mm, nn, j, m->qtau, m->pn, m->ctl);
+      }
+      TN_HIP(hipGetLastError());
+      int c[2] = {0, 0};
+      TN_HIP(hipMemcpyAsync(c, m->ctl, sizeof(c), hipMemcpyDeviceToHost, g));
+      TN_HIP(hipStreamSynchronize(g));
+      if (c[1]) {
+        r = c[0];
+        break;
+      }
+    }
+    if (r == 0) {   // a zero matrix: the plain path on the saved input
+      TN_HIP(hipMemcpyAsync(m->W, m->Wo, size_t(mm) * nn * sizeof(double2), hipMemcpyDeviceToDevice, g));
+      pre = false;
+      r = nn;
+    }
+  }
+  std::vector<double> S(r);
+  if (!pre) {
+    eye_kernel<<<grid_n(int64_t(nn) * nn), 256, 0, g>>>(m->V, nn, m->flag);
+    TN_HIP(hipGetLastError());
+    jacobi_until_converged(m, m->W, m->V, mm, nn, m->sweeps);
+    colnorm_kernel<<<nn, 256, 0, g>>>(m->W, mm, m->S);
+  } else {
+    qrp_form_x_kernel<<<grid_n(int64_t(nn) * r), 256, 0, g>>>(m->W, mm, nn, r, m->rd, m->XR);
+    eye_kernel<<<grid_n(int64_t(r) * r), 256, 0, g>>>(m->V, r, m->flag);
+    TN_HIP(hipGetLastError());
+    jacobi_until_converged(m, m->XR, m->V, nn, r, m->sweeps_xr);
+    colnorm_kernel<<<r, 256, 0, g>>>(m->XR, nn, m->S);
+    qrp_right_kernel<<<grid_n(int64_t(nn) * r), 256, 0, g>>>(m->XR, m->S, m->perm, nn, r, m->V);
+    TN_HIP(hipGetLastError());
+    // U S = W_in V: row-major (r x nn) times (nn x mm) -> (r x mm), i.e. column-major mm x r
+    GemmDesc gd;
+    gd.M = r;
+    gd.N = mm;
+    gd.K = nn;
+    launch_gemm64(m->V, m->Wo, m->W, gd, g);
+  }
+  TN_HIP(hipGetLastError());
+  TN_HIP(hipMemcpyAsync(S.data(), m->S, r * sizeof(double), hipMemcpyDeviceToHost, g));
+  TN_HIP(hipStreamSynchronize(g));
   return S;
 }
 
@@ -497,6 +733,14 @@ tn_status tn_pmps_create(int32_t n_sites, int32_t d_max, int32_t k_max, void* st
     TN_HIP(hipMalloc(&m->zbuf, size_t(n_sites) * sizeof(double)));
     TN_HIP(hipMalloc(&m->flag, 256));
     TN_HIP(hipMalloc(&m->order, m->s_elems * sizeof(int)));
+    TN_HIP(hipMalloc(&m->Wo, m->w_elems * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->XR, m->v_elems * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->rd, m->s_elems * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->qtau, m->s_elems * sizeof(double2)));
+    TN_HIP(hipMalloc(&m->pn, m->s_elems * sizeof(double)));
+    TN_HIP(hipMalloc(&m->perm, m->s_elems * sizeof(int)));
+    TN_HIP(hipMalloc(&m->ctl, 256));
+    TN_HIP(hipMalloc(&m->qthr, 256));
     m->gemm_work_bytes = size_t(64) << 20;
     TN_HIP(hipMalloc(&m->gemm_work, m->gemm_work_bytes));
     *out = m.release();
