@@ -405,7 +405,7 @@ def bench_pmps(a):
                        "oracle_discarded_kraus": rdk, "z_max_abs_diff_vs_oracle": zerr,
                        "dims": m.dims()},
             "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
-                         "traffic": None, "note": "per op: one FP64 Jacobi SVD of <= 1024 x 512 and QR moves"},
+                         "traffic": None, "note": "per op: a pivoted QR to the numerical rank (<= 128) and an FP64 Jacobi SVD of R^dagger, plus QR moves"},
             "cpu_baseline": {"value": n_ops / t_cpu, "unit": "ops/s", "cores": os.cpu_count(), "kind": "oracle",
                              "sample": "PMPS oracle (numpy complex128 + LAPACK SVD/QR), the same circuit"}}
 
