@@ -12,6 +12,10 @@ A label may appear at most once per tensor.
 accumulates C[out] += A[a] * B[b] (pure Python, for <= ~2^16 index points).
 ``contract_pair`` is the same definition handed to ``numpy.einsum``, a
 library routine; a test pins the two against each other on small cases.
+``contract_pair_mm`` writes the same sum as one batched matrix product
+(operands transposed to [batch, free, summed] and [batch, summed, free],
+then ``numpy.matmul``), for the large contractions of full-size references;
+a test pins it against ``contract_pair`` on every label kind.
 
 Parity pins: loop nest == einsum (tests); whole-network contraction ==
 state vector (O1); path invariance; slicing invariance.
@@ -63,6 +67,37 @@ def contract_pair(A, la, B, lb, lc) -> np.ndarray:
     return np.einsum(spec, np.asarray(A, dtype=np.complex128), np.asarray(B, dtype=np.complex128))
 
 
+def contract_pair_mm(A, la, B, lb, lc) -> np.ndarray:
+    """contract_pair as one batched matrix product (library matmul)."""
+    _check(la, lb, lc)
+    A = np.asarray(A, dtype=np.complex128)
+    B = np.asarray(B, dtype=np.complex128)
+    la, lb, lc = list(la), list(lb), list(lc)
+    # labels in one input only and not in C: summed out of that input first
+    for T, ls, other in ((0, la, lb), (1, lb, la)):
+        drop = [l for l in ls if l not in other and l not in lc]
+        if drop:
+            axes = tuple(ls.index(l) for l in drop)
+            if T == 0:
+                A = A.sum(axis=axes)
+                la = [l for l in la if l not in drop]
+            else:
+                B = B.sum(axis=axes)
+                lb = [l for l in lb if l not in drop]
+    batch = [l for l in la if l in lb and l in lc]
+    summed = [l for l in la if l in lb and l not in lc]
+    fa = [l for l in la if l not in lb]
+    fb = [l for l in lb if l not in la]
+    ext = {l: A.shape[i] for i, l in enumerate(la)}
+    ext.update({l: B.shape[i] for i, l in enumerate(lb)})
+    size = lambda ls: int(np.prod([ext[l] for l in ls], dtype=np.int64))
+    At = np.transpose(A, [la.index(l) for l in batch + fa + summed]).reshape(size(batch), size(fa), size(summed))
+    Bt = np.transpose(B, [lb.index(l) for l in batch + summed + fb]).reshape(size(batch), size(summed), size(fb))
+    C = np.matmul(At, Bt).reshape([ext[l] for l in batch + fa + fb])
+    order = batch + fa + fb
+    return np.transpose(C, [order.index(l) for l in lc]) if lc else C.reshape(())
+
+
 def contract_entries(A, la, B, lb, lc, index_list) -> np.ndarray:
     """Selected entries C[idx] of contract_pair(A, la, B, lb, lc), each
     computed on its own: fix the output labels, then sum the product over
@@ -93,28 +128,29 @@ def result_labels(la, lb, others: List[Sequence[int]], keep: Sequence[int]) -> L
 
 
 def contract_path(tensors: List[np.ndarray], labels: List[List[int]], path,
-                  open_labels: Sequence[int]) -> np.ndarray:
+                  open_labels: Sequence[int], pair=None) -> np.ndarray:
     """Contract a network along an SSA path (pairs of tensor ids; the result of
     step t gets id len(tensors) + t).  Returns the tensor over
     ``open_labels`` in that order (a scalar array if there are none).
 
     Components left unconnected at the end are multiplied as outer products in
-    id order.
+    id order.  ``pair``: the pairwise contraction (default contract_pair).
     """
+    pair = pair or contract_pair
     live = {i: (np.asarray(T, dtype=np.complex128), list(ls)) for i, (T, ls) in enumerate(zip(tensors, labels))}
     nid = len(tensors)
     for (i, j) in path:
         A, la = live.pop(i)
         B, lb = live.pop(j)
         lc = result_labels(la, lb, [ls for _, ls in live.values()], open_labels)
-        live[nid] = (contract_pair(A, la, B, lb, lc), lc)
+        live[nid] = (pair(A, la, B, lb, lc), lc)
         nid += 1
     while len(live) > 1:
         ids = sorted(live)
         A, la = live.pop(ids[0])
         B, lb = live.pop(ids[1])
         lc = result_labels(la, lb, [ls for _, ls in live.values()], open_labels)
-        live[nid] = (contract_pair(A, la, B, lb, lc), lc)
+        live[nid] = (pair(A, la, B, lb, lc), lc)
         nid += 1
     (T, ls), = live.values()
     # sum out anything not open (cannot happen for circuit networks)

@@ -155,3 +155,52 @@ def test_rqc_7x7_14_random_circuit_against_fp64(gpu, workspace, identity_coupled
         err = np.abs(np.array(res[prec]) - ref) / np.maximum(np.abs(ref), floor)
         print(f"  {prec}: floored errors {err} (|ref|/floor {np.abs(ref) / floor})", flush=True)
         assert err.max() <= 1e-5, (prec, err)
+
+
+def test_rqc_7x7_14_random_circuit_slices_against_oracle(gpu, workspace):
+    """The benchmark's random circuit itself against the oracle: three
+    (bit-string, slice) jobs of a full 49-qubit plan whose kernels include
+    the direct-to-LDS split GEMM and the matrix-core apply, compared with
+    the complex128 values that tests/golden/make_c2_slices.py computed with
+    the oracle alone (same path and sliced labels: the library's planner
+    reproduces the oracle's bit for bit, checked here by the pairs' hash).
+    Floored relative error <= 1e-5 at auto and FP32 (1e-10 at FP64), the floor being
+    the RMS value of one slice, 2^-(n + n_sliced)/2."""
+    import hashlib
+    import json
+    from pathlib import Path
+    import torch
+    import paper_2104_10523_amd as tn
+    ref = json.loads((Path(__file__).parent / "golden" / "c2_slices.json").read_text())
+    n, ops = grid_random_circuit(7, 7, 14, 2, two_qubit="fsim")
+    net = tn.tn_build_network(n, ops)
+    pf = ref["path"]
+    lib = tn.tn_find_path(net, pf["algorithm"], trials=pf["trials"], seed=pf["seed"],
+                          mem_budget_bytes=pf["mem_budget_bytes"])
+    sha = hashlib.sha256(json.dumps([list(map(int, p)) for p in lib.pairs]).encode()).hexdigest()
+    assert sha == pf["pairs_sha256"]
+    path = tn.tn_path_from_pairs(net, lib.pairs, mem_budget_bytes=ref["slice_budget_bytes"])
+    assert list(path.sliced) == ref["sliced"]
+    kind, _, _, shape = tn.tn_amplitudes_plan_ops(net, path, "auto")
+    assert int(np.sum((kind == 2) & (shape[:, 4] == 5))) >= 1      # direct-to-LDS split GEMM
+    assert int(np.sum((kind == 0) & (shape[:, 3] == 2))) >= 1      # matrix-core apply
+    floor = 2.0 ** (-(n + len(ref["sliced"])) / 2)
+    try:
+        for prec in ("auto", "fp32", "fp64"):
+            big = torch.empty(tn.tn_amplitudes_workspace(net, path, 1, prec), dtype=torch.uint8, device=gpu)
+            tn.tn_set_workspace(big)
+            for job in ref["jobs"]:
+                bits = np.array([job["bits"]], dtype=np.int8)
+                print(f"{prec}: bit-string {job['bitstring_index']} slice {job['slice']}", flush=True)
+                out, rep = tn.tn_amplitudes(net, path, bits, precision=prec, slice_begin=job["slice"], slice_count=1)
+                got = complex(out.cpu().numpy()[0, 0])
+                want = complex(*job["value"])
+                err = abs(got - want) / max(abs(want), floor)
+                print(f"  got {got:.6e} oracle {want:.6e} |ref|/floor {abs(want) / floor:.2f} err {err:.2e}", flush=True)
+                assert rep.nonfinite == 0
+                assert err <= (1e-10 if prec == "fp64" else 1e-5), (prec, job["slice"], err)
+            tn.tn_set_workspace(workspace)
+            del big
+            torch.cuda.empty_cache()
+    finally:
+        tn.tn_set_workspace(workspace)

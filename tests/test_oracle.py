@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from oracle import gates, statevector as sv
-from oracle.contract import contract_pair, contract_pair_loops, contract_path
+from oracle.contract import contract_pair, contract_pair_loops, contract_pair_mm, contract_path
 from oracle.network import build_network, fix_outputs, fix_labels
 from oracle.paths import (greedy_path, path_stats, random_greedy_path, slice_path, SplitMix64)
 from workloads import (grid_random_circuit, cat_circuit, ghz_circuit, bell_circuit, qft_circuit,
@@ -143,6 +143,38 @@ def test_loops_match_einsum(seed):
     got = contract_pair_loops(A, la, B, lb, lc)
     ref = contract_pair(A, la, B, lb, lc)
     assert np.abs(got - ref).max() <= 1e-12 * max(1, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_matmul_pair_matches_loops(seed):
+    """The batched-matmul contraction against the loop nest, over random
+    label mixes: batch, summed, free and summed-out labels, scalar outputs."""
+    rng = np.random.default_rng(100 + seed)
+    labels = list(range(8))
+    la = list(rng.choice(labels, size=rng.integers(0, 6), replace=False))
+    lb = list(rng.choice(labels, size=rng.integers(0, 6), replace=False))
+    pool = list(dict.fromkeys(la + lb))
+    lc = [l for l in pool if rng.random() < 0.5]
+    rng.shuffle(lc)
+    ext = {l: int(rng.integers(1, 4)) for l in labels}
+    A = random_complex([ext[l] for l in la], seed + 30)
+    B = random_complex([ext[l] for l in lb], seed + 40)
+    got = contract_pair_mm(A, la, B, lb, lc)
+    ref = contract_pair_loops(A, la, B, lb, lc)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 1e-12 * max(1, np.abs(ref).max())
+
+
+def test_matmul_path_equals_state_vector():
+    """Whole-network contraction with the matmul pair equals O1."""
+    n, ops = grid_random_circuit(3, 3, 6, 46)
+    net = build_network(n, ops)
+    bits = [-1] * n
+    ts, ls, open_l = fix_outputs(net, bits)
+    ext = {l: 2 for t in ls for l in t}
+    got = contract_path(ts, ls, greedy_path(ls, ext, open_l), open_l, pair=contract_pair_mm).reshape(-1)
+    ref = sv.simulate(n, ops).reshape(-1)
+    assert np.abs(got - ref).max() <= 1e-12
 
 
 def _net_amplitudes(n, ops, bits, path=None):
