@@ -214,12 +214,128 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double2* __restrict
   }
 }
 
+// Panel step of the blocked Householder QR: for j = j0 .. j1-1 in order,
+// the reflector of column j (as hh_reflect_kernel) and its application to
+// the panel's later columns (recording R[j][c]), in one workgroup.
+__global__ __launch_bounds__(256) void hh_panel_kernel(double2* __restrict__ X, int m, int n, int j0, int j1,
+                                                       double2* __restrict__ R, double2* __restrict__ tau) {
+  __shared__ double red[8];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = j0; j < j1; ++j) {
+    double2* x = X + int64_t(j) * m;
+    double ss = 0;
+    for (int i = j + threadIdx.x; i < m; i += blockDim.x) ss += x[i].x * x[i].x + x[i].y * x[i].y;
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+      const double2 alpha = x[j];
+      const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
+      const double nrm = sqrt(ss);
+      const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
+      const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+      const double2 v0 = make_double2(alpha.x - beta.x, alpha.y - beta.y);
+      const double vn2 = ss - an * an + v0.x * v0.x + v0.y * v0.y;
+      x[j] = v0;
+      R[int64_t(j) * n + j] = beta;
+      tau[j] = make_double2(vn2 > 0 ? 2.0 / vn2 : 0.0, 0.0);
+    }
+    __syncthreads();   // v_j and tau_j written
+    const double t2 = tau[j].x;
+    for (int c = j + 1 + wave; c < j1; c += int(blockDim.x >> 6)) {
+      double2* y = X + int64_t(c) * m;
+      double dr = 0, di = 0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 a = x[i], b = y[i];
+        dr += a.x * b.x + a.y * b.y;
+        di += a.x * b.y - a.y * b.x;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        dr += __shfl_xor(dr, o);
+        di += __shfl_xor(di, o);
+      }
+      const double2 f = make_double2(t2 * dr, t2 * di);
+      for (int i = j + lane; i < m; i += 64) {
+        const double2 fv = cmul(x[i], f);
+        double2 b = y[i];
+        b.x -= fv.x;
+        b.y -= fv.y;
+        y[i] = b;
+        if (i == j) R[int64_t(j) * n + c] = b;
+      }
+    }
+    __syncthreads();   // the panel's columns updated before the next reflector
+  }
+}
+
+// Reflectors j0 .. j1-1 (in V, as left by hh_panel_kernel) applied to
+// columns c0 .. c1-1 of Y, one wave per column: in order (reverse = 0,
+// recording R[j][c] when R is given) or in reverse order (reverse = 1, for
+// accumulating Q).
+__global__ __launch_bounds__(256) void hh_apply_block_kernel(const double2* __restrict__ V, int m, int j0, int j1,
+                                                             int reverse, const double2* __restrict__ tau,
+                                                             double2* __restrict__ Y, int c0, int c1,
+                                                             double2* __restrict__ R, int n) {
+  const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= c1) return;
+  double2* y = Y + int64_t(c) * m;
+  for (int t = 0; t < j1 - j0; ++t) {
+    const int j = reverse ? j1 - 1 - t : j0 + t;
+    const double t2 = tau[j].x;
+    const double2* v = V + int64_t(j) * m;
+    double dr = 0, di = 0;
+    for (int i = j + lane; i < m; i += 64) {
+      const double2 a = v[i], b = y[i];
+      dr += a.x * b.x + a.y * b.y;
+      di += a.x * b.y - a.y * b.x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dr += __shfl_xor(dr, o);
+      di += __shfl_xor(di, o);
+    }
+    const double2 f = make_double2(t2 * dr, t2 * di);
+    for (int i = j + lane; i < m; i += 64) {
+      const double2 fv = cmul(v[i], f);
+      double2 b = y[i];
+      b.x -= fv.x;
+      b.y -= fv.y;
+      y[i] = b;
+      if (R && i == j) R[int64_t(j) * n + c] = b;
+    }
+  }
+}
+
 // Q (m x k, column-major) = [I; 0], before the reflectors are applied.
 __global__ void q_init_kernel(double2* __restrict__ Q, int m, int k) {
   const int64_t n = int64_t(m) * k;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     Q[i] = make_double2((i % m) == (i / m) ? 1.0 : 0.0, 0.0);
 }
+
+// Columns per panel of the blocked QR.
+constexpr int kQrPanel = 8;
+
+// Records the blocked Householder QR of X (rows x cols, column-major, in
+// place) on s: R (k x cols row-major, k = min(rows, cols)) and Q (rows x k,
+// column-major) = H_0 ... H_{k-1} [I; 0].  3 k / kQrPanel launches.
+inline void record_blocked_qr(double2* X, double2* R, double2* Q, double2* tau, int rows, int cols, hipStream_t s,
+                              int grid_cap) {
+  const int k = rows < cols ? rows : cols;
+  auto grid = [&](int64_t n) { return int(n / 256 + 1 < grid_cap ? n / 256 + 1 : grid_cap); };
+  zero_kernel<<<grid(int64_t(k) * cols), 256, 0, s>>>(R, int64_t(k) * cols);
+  for (int j0 = 0; j0 < k; j0 += kQrPanel) {
+    const int j1 = j0 + kQrPanel < k ? j0 + kQrPanel : k;
+    hh_panel_kernel<<<1, 256, 0, s>>>(X, rows, cols, j0, j1, R, tau);
+    if (j1 < cols)
+      hh_apply_block_kernel<<<(cols - j1 + 3) / 4, 256, 0, s>>>(X, rows, j0, j1, 0, tau, X, j1, cols, R, cols);
+  }
+  q_init_kernel<<<grid(int64_t(rows) * k), 256, 0, s>>>(Q, rows, k);
+  for (int j1 = k; j1 > 0; j1 -= kQrPanel) {
+    const int j0 = j1 - kQrPanel > 0 ? j1 - kQrPanel : 0;
+    hh_apply_block_kernel<<<(k - j0 + 3) / 4, 256, 0, s>>>(X, rows, j0, j1, 1, tau, Q, j0, k, nullptr, 0);
+  }
+}
+
 
 
 // Write Q (m x k, column-major) back as the site: !adj: A[(l,s), k] = Q;

@@ -231,21 +231,11 @@ void run_qr(tn_mps* m, int rows, int cols, hipStream_t s) {
   const auto key = std::make_pair(rows, cols);
   auto it = m->qrs.find(key);
   if (it == m->qrs.end()) {
-    const int k = std::min(rows, cols);
     if (!m->gstream) TN_HIP(hipStreamCreateWithFlags(&m->gstream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     TN_HIP(hipStreamBeginCapture(m->gstream, hipStreamCaptureModeThreadLocal));
-    zero_kernel<<<grid_for(int64_t(k) * cols), 256, 0, m->gstream>>>(m->R, int64_t(k) * cols);
-    for (int j = 0; j < k; ++j) {
-      hh_reflect_kernel<<<1, 256, 0, m->gstream>>>(m->X, rows, cols, j, m->R, m->tau);
-      if (j + 1 < cols)
-        hh_apply_kernel<<<(cols - j - 1 + 3) / 4, 256, 0, m->gstream>>>(m->X, rows, j, m->tau, m->X, j + 1, cols,
-                                                                        m->R, cols);
-    }
-    q_init_kernel<<<grid_for(int64_t(rows) * k), 256, 0, m->gstream>>>(m->Q, rows, k);
-    for (int j = k - 1; j >= 0; --j)
-      hh_apply_kernel<<<(k - j + 3) / 4, 256, 0, m->gstream>>>(m->X, rows, j, m->tau, m->Q, j, k, nullptr, 0);
+    record_blocked_qr(m->X, m->R, m->Q, m->tau, rows, cols, m->gstream, 4096);
     const hipError_t e = hipStreamEndCapture(m->gstream, &g);
     TN_REQUIRE(e == hipSuccess, TN_ERR_DEVICE, "graph capture of the QR failed");
     TN_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
