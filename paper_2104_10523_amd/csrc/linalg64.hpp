@@ -155,68 +155,12 @@ __global__ void zero_kernel(double2* __restrict__ p, int64_t n) {
     p[i] = make_double2(0, 0);
 }
 
-// Householder step j of the QR of X (m x n, column-major, in place): the
-// reflector of column j, v = x - beta e_j with beta = -e^{i arg x_j} ||x||,
-// stored over the column; R[j, j] = beta (R: k x n row-major); tau[j] =
-// 2 / ||v||^2.
-__global__ __launch_bounds__(256) void hh_reflect_kernel(double2* __restrict__ X, int m, int n, int j,
-                                                         double2* __restrict__ R, double2* __restrict__ tau) {
-  __shared__ double red[8];
-  double2* x = X + int64_t(j) * m;
-  double ss = 0;
-  for (int i = j + threadIdx.x; i < m; i += blockDim.x) ss += x[i].x * x[i].x + x[i].y * x[i].y;
-  ss = block_sum(ss, red);
-  if (threadIdx.x == 0) {
-    const double2 alpha = x[j];
-    const double an = sqrt(alpha.x * alpha.x + alpha.y * alpha.y);
-    const double nrm = sqrt(ss);
-    const double2 ph = an > 0 ? make_double2(alpha.x / an, alpha.y / an) : make_double2(1, 0);
-    const double2 beta = make_double2(-ph.x * nrm, -ph.y * nrm);
-    const double2 v0 = make_double2(alpha.x - beta.x, alpha.y - beta.y);
-    // |v|^2 = |x|^2 - |alpha|^2 + |alpha - beta|^2
-    const double vn2 = ss - an * an + v0.x * v0.x + v0.y * v0.y;
-    x[j] = v0;
-    R[int64_t(j) * n + j] = beta;
-    tau[j] = make_double2(vn2 > 0 ? 2.0 / vn2 : 0.0, 0.0);
-  }
-}
-
-// Applies I - tau_j v_j v_j^dagger (v_j: rows j.. of column j of V, m rows,
-// column-major) to columns c0 .. c1-1 of Y (m rows, column-major), one wave
-// per column; with R, also records row j of the result (R[j, c]).
-__global__ __launch_bounds__(256) void hh_apply_kernel(const double2* __restrict__ V, int m, int j,
-                                                       const double2* __restrict__ tau, double2* __restrict__ Y,
-                                                       int c0, int c1, double2* __restrict__ R, int n) {
-  const int c = c0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (c >= c1) return;
-  const double t2 = tau[j].x;
-  const double2* v = V + int64_t(j) * m;
-  double2* y = Y + int64_t(c) * m;
-  double dr = 0, di = 0;  // v^dagger y
-  for (int i = j + lane; i < m; i += 64) {
-    const double2 a = v[i], b = y[i];
-    dr += a.x * b.x + a.y * b.y;
-    di += a.x * b.y - a.y * b.x;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    dr += __shfl_xor(dr, o);
-    di += __shfl_xor(di, o);
-  }
-  const double2 f = make_double2(t2 * dr, t2 * di);
-  for (int i = j + lane; i < m; i += 64) {
-    const double2 fv = cmul(v[i], f);
-    double2 b = y[i];
-    b.x -= fv.x;
-    b.y -= fv.y;
-    y[i] = b;
-    if (R && i == j) R[int64_t(j) * n + c] = b;
-  }
-}
-
-// Panel step of the blocked Householder QR: for j = j0 .. j1-1 in order,
-// the reflector of column j (as hh_reflect_kernel) and its application to
-// the panel's later columns (recording R[j][c]), in one workgroup.
+// Panel step of the blocked Householder QR of X (m x n, column-major, in
+// place): for j = j0 .. j1-1 in order, the reflector of column j, v = x -
+// beta e_j with beta = -e^{i arg x_j} |x| (rows j..), stored over the
+// column, R[j][j] = beta (R: k x n row-major), tau[j] = 2 / |v|^2; then its
+// application to the panel's later columns (recording R[j][c]); one
+// workgroup.
 __global__ __launch_bounds__(256) void hh_panel_kernel(double2* __restrict__ X, int m, int n, int j0, int j1,
                                                        double2* __restrict__ R, double2* __restrict__ tau) {
   __shared__ double red[8];
