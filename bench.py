@@ -109,6 +109,7 @@ def parse():
     ap.add_argument("--learned-epochs", type=int, default=6)
     ap.add_argument("--learned-batch", type=int, default=64)
     ap.add_argument("--learned-lr", type=float, default=1e-3)
+    ap.add_argument("--learned-rescore", type=int, default=8, help="merges per scoring of the second learned search")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a counter calibration kernel)")
     return ap.parse_args()
@@ -499,7 +500,8 @@ def bench_learned(a):
     a.learned_train training circuits (30-60 qubits, 8-16 CZ cycles), each
     labelled by the best of 32 randomised-greedy paths and sampled at ~16
     states; a.learned_test held-out circuits searched by greedy, the learned
-    scorer (greedy fallback), the same scorer untrained, the 32-trial teacher
+    scorer (greedy fallback) re-scoring after every merge and after every
+    a.learned_rescore merges, the same scorer untrained, the 32-trial teacher
     and randomised greedy given the learned search's wall time.  End-to-end
     time of one amplitude (search + plan + contraction, auto precision) on
     held-out circuits whose learned and equal-time paths both stay within 2^40
@@ -541,11 +543,13 @@ def bench_learned(a):
         g, tg = timed_path(lambda: tn.tn_find_path(net, "greedy"))
         lp, tl = timed_path(lambda: tn.tn_find_path_learned(net, m))
         l0 = tn.tn_find_path_learned(net, m0)
+        lr, tlr = timed_path(lambda: tn.tn_find_path_learned(net, m, rescore_every=a.learned_rescore))
         r32, tr = timed_path(lambda: tn.tn_find_path(net, "random_greedy", trials=32, seed=i, temperature=0.5))
         eq = max(1, int(round(32 * tl / tr)))
         req, te = timed_path(lambda: tn.tn_find_path(net, "random_greedy", trials=eq, seed=i, temperature=0.5))
         rows.append(dict(i=i, n=n, greedy=g.cost.flops_per_slice, learned=lp.cost.flops_per_slice,
                          untrained=l0.cost.flops_per_slice, teacher=r32.cost.flops_per_slice,
+                         learned_r=lr.cost.flops_per_slice, t_learned_r=tlr,
                          equal_time=req.cost.flops_per_slice, chosen=lp.cost.algo_used == 2,
                          t_greedy=tg, t_learned=tl, t_teacher=tr, t_equal=te, eq_trials=eq,
                          pairs_learned=lp.pairs, pairs_equal=req.pairs))
@@ -598,7 +602,10 @@ def bench_learned(a):
             "geomean_flops_learned_over_equal_time": _geomean_ratio(col["learned"], col["equal_time"]),
             "learned_beats_equal_time_fraction": float(np.mean(col["learned"] < col["equal_time"])),
             "median_search_seconds": {k: float(np.median(col["t_" + k]))
-                                      for k in ("greedy", "learned", "teacher", "equal")},
+                                      for k in ("greedy", "learned", "learned_r", "teacher", "equal")},
+            "rescore_every": a.learned_rescore,
+            "geomean_flops_learned_r_over_greedy": _geomean_ratio(col["learned_r"], col["greedy"]),
+            "geomean_flops_learned_r_over_learned": _geomean_ratio(col["learned_r"], col["learned"]),
             "median_equal_time_trials": float(np.median(col["eq_trials"])),
             "log2_gain_over_greedy_quartiles": [float(x) for x in np.percentile(gains, [25, 50, 75])]},
         "end_to_end": {

@@ -150,6 +150,10 @@ typedef struct {
                               /* or TN_RANK_TIME (see tn_find_path)         */
   int32_t rank_precision;     /* TN_RANK_TIME: TN_PREC_* of the modelled    */
                               /* amplitude plan                             */
+  int32_t rescore_every;      /* TN_PATH_LEARNED: merges per scoring (<= 1: */
+                              /* re-score after every merge); each scoring  */
+                              /* takes its best-scored pairs that share no  */
+                              /* tensor, best first                         */
 } tn_path_opts;
 
 enum { TN_RANK_FLOPS = 0, TN_RANK_TIME = 1 };

@@ -564,9 +564,14 @@ def tn_model_state_features(net: Network, pairs, n_prefix: int, open_mask=None):
     return [tuple(cand[2 * k:2 * k + 2]) for k in range(nc.value)], X, nbrs
 
 
-def tn_find_path_learned(net: Network, model: Model, mem_budget_bytes: float = 0.0, open_mask=None) -> Path:
+def tn_find_path_learned(net: Network, model: Model, mem_budget_bytes: float = 0.0, open_mask=None,
+                         rescore_every: int = 1) -> Path:
+    """Scores the candidate pairs, takes up to rescore_every of the best
+    that share no tensor, and scores again; greedy replaces the result when
+    greedy is cheaper."""
     o, _keep = _path_opts(net.n_qubits, "learned", 0, 0, 1.0, mem_budget_bytes, open_mask)
     o.model = model.h
+    o.rescore_every = int(rescore_every)
     h = C.c_void_p()
     cost = TnPathCost()
     check(lib().tn_find_path(net.h, C.byref(o), C.byref(h), C.byref(cost)))

@@ -43,7 +43,8 @@ class TnPathOpts(C.Structure):
     _fields_ = [("algo", C.c_int32), ("trials", C.c_int32), ("seed", C.c_uint64),
                 ("temperature", C.c_double), ("mem_budget_bytes", C.c_double),
                 ("open_mask", C.POINTER(C.c_int8)), ("model", C.c_void_p),
-                ("rank", C.c_int32), ("rank_precision", C.c_int32)]
+                ("rank", C.c_int32), ("rank_precision", C.c_int32),
+                ("rescore_every", C.c_int32)]
 
 
 class TnPathCost(C.Structure):

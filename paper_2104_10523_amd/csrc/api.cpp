@@ -332,7 +332,7 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
     } else {
       TN_REQUIRE(o->model != nullptr, TN_ERR_STATE, "learned path needs a model");
       int used = TN_PATH_GREEDY;
-      pairs = learned_path_with_fallback(o->model, pr, &used);
+      pairs = learned_path_with_fallback(o->model, pr, o->rescore_every, &used);
       *out = finish_path(n->net, o, std::move(pairs), used, cost);
       return;
     }

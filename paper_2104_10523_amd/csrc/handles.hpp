@@ -41,6 +41,7 @@ struct tn_path {
 
 namespace tn {
 // Learned path with greedy fallback (defined with the scorer).
+// rescore_every: merges taken per scoring (<= 1: one).
 std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* m, const PathProblem& pr,
-                                                            int* algo_used);
+                                                            int rescore_every, int* algo_used);
 }  // namespace tn

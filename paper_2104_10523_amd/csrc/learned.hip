@@ -98,8 +98,9 @@ using floatx16 = __attribute__((__vector_size__(16 * sizeof(float)))) float;
 // and B column l % 32 at k offset l / 32; accumulator register r holds row
 // 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32).  K is staged through
 // LDS 16 at a time.  With gridDim.z > 1 block z covers k in [z kchunk,
-// (z + 1) kchunk) and adds its tile into C atomically (no bias or relu then;
-// C holds zero or the term to accumulate).
+// (z + 1) kchunk) and stores its partial tile at C + z M ldc (no bias or
+// relu then); splitk_reduce_kernel sums the partials in a fixed order, so
+// results do not depend on block scheduling.
 __global__ __launch_bounds__(256) void sgemm_mfma_kernel(const float* __restrict__ A, const float* __restrict__ B,
                                                          float* __restrict__ C, int M, int N, int K, int lda, int ldb,
                                                          int ldc, int transA, int transB, int accumulate,
@@ -136,9 +137,9 @@ __global__ __launch_bounds__(256) void sgemm_mfma_kernel(const float* __restrict
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + wm + 8 * (r >> 2) + 4 * lh + (r & 3);
     if (m >= M) continue;
-    float* c = C + int64_t(m) * ldc + n;
+    float* c = C + (int64_t(blockIdx.z) * M + m) * ldc + n;
     if (gridDim.z > 1) {
-      atomicAdd(c, acc[r]);
+      *c = acc[r];
     } else {
       float v = acc[r];
       if (accumulate) v += *c;
@@ -146,6 +147,19 @@ __global__ __launch_bounds__(256) void sgemm_mfma_kernel(const float* __restrict
       if (relu) v = fmaxf(v, 0.f);
       *c = v;
     }
+  }
+}
+
+// C[m][n] = (accumulate ? C[m][n] : 0) + sum over z = 0 .. Z-1, in order, of
+// part[z][m][n] (part dense, M x N per z).
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, int Z, int M, int N, float* __restrict__ C,
+                                     int ldc, int accumulate) {
+  const int64_t n = int64_t(M) * N;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < Z; ++z) s += part[int64_t(z) * n + e];
+    float* c = C + (e / N) * ldc + e % N;
+    *c = accumulate ? *c + s : s;
   }
 }
 
@@ -183,14 +197,13 @@ __global__ void mask_kernel(float* __restrict__ g, const float* __restrict__ h, 
     if (!(h[e] > 0.f)) g[e] = 0.f;
 }
 
-// out[c] += sum_i G[i][c]: block b sums rows [b R, (b + 1) R) per column
-// and adds the partial atomically (out zeroed first).
-__global__ void colsum_kernel(const float* __restrict__ G, float* __restrict__ out, int N, int H, int R) {
+// part[b][c] = sum_i G[i][c] over the rows [b R, (b + 1) R) of block b.
+__global__ void colsum_kernel(const float* __restrict__ G, float* __restrict__ part, int N, int H, int R) {
   const int i0 = blockIdx.x * R, i1 = min(N, i0 + R);
   for (int c = threadIdx.x; c < H; c += blockDim.x) {
     float s = 0.f;
     for (int i = i0; i < i1; ++i) s += G[int64_t(i) * H + c];
-    atomicAdd(&out[c], s);
+    part[int64_t(blockIdx.x) * H + c] = s;
   }
 }
 
@@ -235,6 +248,7 @@ struct tn_model {
   int64_t np = 0;
   int dev = 0;
   float *P = nullptr, *G = nullptr, *Mo = nullptr, *Vo = nullptr;
+  float* part = nullptr;   // split-K and column-sum partials (kPartFloats)
   int64_t adam_t = 0;
   // activations (grown on demand)
   int cap_nodes = 0, cap_nbr = 0, cap_seg = 0;
@@ -295,7 +309,7 @@ struct tn_model {
   }
 
   ~tn_model() {
-    for (void* p : {(void*)P, (void*)G, (void*)Mo, (void*)Vo, (void*)X, (void*)work, (void*)s, (void*)ds,
+    for (void* p : {(void*)P, (void*)G, (void*)Mo, (void*)Vo, (void*)part, (void*)X, (void*)work, (void*)s, (void*)ds,
                     (void*)loss, (void*)ptr, (void*)idx, (void*)seg, (void*)lab})
       if (p) (void)hipFree(p);
   }
@@ -303,8 +317,12 @@ struct tn_model {
 
 namespace {
 
-void gemm(const float* A, const float* B, float* C, int M, int N, int K, int lda, int ldb, int ldc, int tA, int tB,
-          int acc, const float* bias, int relu, hipStream_t s) {
+// Split-K partials and column-sum partials: ksplit <= 512 / tiles bounds a
+// GEMM's partials by 512 tiles of 64 x 64; column sums take <= 1024 x 256.
+constexpr int64_t kPartFloats = int64_t(512) * 64 * 64;
+
+void gemm(float* part, const float* A, const float* B, float* C, int M, int N, int K, int lda, int ldb, int ldc,
+          int tA, int tB, int acc, const float* bias, int relu, hipStream_t s) {
   const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
   int ksplit = 1, kchunk = std::max(K, 1);
   // long-K products with few output tiles (weight gradients: K = nodes)
@@ -314,37 +332,46 @@ void gemm(const float* A, const float* B, float* C, int M, int N, int K, int lda
     kchunk = ((K + ksplit - 1) / ksplit + 15) / 16 * 16;
     ksplit = (K + kchunk - 1) / kchunk;
   }
-  if (ksplit > 1 && !acc) {
-    zero_rows_kernel<<<blocks_for(int64_t(M) * N), 256, 0, s>>>(C, M, N, ldc);
-  }
   dim3 grid((N + 63) / 64, (M + 63) / 64, ksplit);
-  sgemm_mfma_kernel<<<grid, 256, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, tA, tB, acc, bias, relu, kchunk);
+  if (ksplit > 1) {
+    TN_REQUIRE(int64_t(M) * N * ksplit <= kPartFloats, TN_ERR_ARG, "split-K partials exceed their buffer");
+    sgemm_mfma_kernel<<<grid, 256, 0, s>>>(A, B, part, M, N, K, lda, ldb, N, tA, tB, 0, nullptr, 0, kchunk);
+    TN_HIP(hipGetLastError());
+    splitk_reduce_kernel<<<blocks_for(int64_t(M) * N), 256, 0, s>>>(part, ksplit, M, N, C, ldc, acc);
+  } else {
+    sgemm_mfma_kernel<<<grid, 256, 0, s>>>(A, B, C, M, N, K, lda, ldb, ldc, tA, tB, acc, bias, relu, kchunk);
+  }
   TN_HIP(hipGetLastError());
 }
 
 // out[0..H) = column sums of G[N][H]
-void colsum(const float* G, float* out, int N, int H, hipStream_t s) {
-  zero_rows_kernel<<<1, 256, 0, s>>>(out, 1, H, H);
-  if (N <= 0) return;
+void colsum(float* part, const float* G, float* out, int N, int H, hipStream_t s) {
+  if (N <= 0) {
+    zero_rows_kernel<<<1, 256, 0, s>>>(out, 1, H, H);
+    return;
+  }
   const int nb = std::max(1, std::min((N + 63) / 64, 1024));
   const int R = (N + nb - 1) / nb;
-  colsum_kernel<<<(N + R - 1) / R, std::min(256, std::max(64, (H + 63) / 64 * 64)), 0, s>>>(G, out, N, H, R);
+  const int blocks = (N + R - 1) / R;
+  TN_REQUIRE(int64_t(blocks) * H <= kPartFloats, TN_ERR_ARG, "column-sum partials exceed their buffer");
+  colsum_kernel<<<blocks, std::min(256, std::max(64, (H + 63) / 64 * 64)), 0, s>>>(G, part, N, H, R);
+  splitk_reduce_kernel<<<blocks_for(H), 256, 0, s>>>(part, blocks, 1, H, out, H, 0);
 }
 
 // Forward over `nodes` nodes already uploaded (X, ptr, idx); scores into m->s.
 void forward(tn_model* m, int nodes, hipStream_t st) {
   const int H = m->H;
   const float* P = m->P;
-  gemm(m->X, P + m->off_W0(), m->hbuf(0), nodes, H, kF, kF, H, H, 0, 0, 0, P + m->off_b0(), 1, st);
+  gemm(m->part, m->X, P + m->off_W0(), m->hbuf(0), nodes, H, kF, kF, H, H, 0, 0, 0, P + m->off_b0(), 1, st);
   for (int l = 0; l < m->L; ++l) {
     const int64_t o = m->off_layer(l);
     agg_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->hbuf(l), m->ptr, m->idx, m->mbuf(l), nodes, H, 0);
-    gemm(m->hbuf(l), P + o, m->hbuf(l + 1), nodes, H, H, H, H, H, 0, 0, 0, nullptr, 0, st);
-    gemm(m->mbuf(l), P + o + int64_t(H) * H, m->hbuf(l + 1), nodes, H, H, H, H, H, 0, 0, 1,
+    gemm(m->part, m->hbuf(l), P + o, m->hbuf(l + 1), nodes, H, H, H, H, H, 0, 0, 0, nullptr, 0, st);
+    gemm(m->part, m->mbuf(l), P + o + int64_t(H) * H, m->hbuf(l + 1), nodes, H, H, H, H, H, 0, 0, 1,
          P + o + 2 * int64_t(H) * H, 1, st);
   }
-  gemm(m->hbuf(m->L), P + m->off_Wh(), m->hh(), nodes, H, H, H, H, H, 0, 0, 0, P + m->off_bh(), 1, st);
-  gemm(m->hh(), P + m->off_wo(), m->s, nodes, 1, H, H, 1, 1, 0, 0, 0, P + m->off_bo(), 0, st);
+  gemm(m->part, m->hbuf(m->L), P + m->off_Wh(), m->hh(), nodes, H, H, H, H, H, 0, 0, 0, P + m->off_bh(), 1, st);
+  gemm(m->part, m->hh(), P + m->off_wo(), m->s, nodes, 1, H, H, 1, 1, 0, 0, 0, P + m->off_bo(), 0, st);
 }
 
 // Backward from m->ds; gradients into m->G (overwritten).
@@ -353,29 +380,29 @@ void backward(tn_model* m, int nodes, hipStream_t st) {
   const float* P = m->P;
   float* G = m->G;
   // head
-  gemm(m->hh(), m->ds, G + m->off_wo(), H, 1, nodes, H, 1, 1, 1, 0, 0, nullptr, 0, st);
-  colsum(m->ds, G + m->off_bo(), nodes, 1, st);
-  gemm(m->ds, P + m->off_wo(), m->t1(), nodes, H, 1, 1, H, H, 0, 0, 0, nullptr, 0, st);   // dhh
+  gemm(m->part, m->hh(), m->ds, G + m->off_wo(), H, 1, nodes, H, 1, 1, 1, 0, 0, nullptr, 0, st);
+  colsum(m->part, m->ds, G + m->off_bo(), nodes, 1, st);
+  gemm(m->part, m->ds, P + m->off_wo(), m->t1(), nodes, H, 1, 1, H, H, 0, 0, 0, nullptr, 0, st);   // dhh
   mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t1(), m->hh(), int64_t(nodes) * H);
-  gemm(m->hbuf(m->L), m->t1(), G + m->off_Wh(), H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
-  colsum(m->t1(), G + m->off_bh(), nodes, H, st);
-  gemm(m->t1(), P + m->off_Wh(), m->t2(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);   // dh_L
+  gemm(m->part, m->hbuf(m->L), m->t1(), G + m->off_Wh(), H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
+  colsum(m->part, m->t1(), G + m->off_bh(), nodes, H, st);
+  gemm(m->part, m->t1(), P + m->off_Wh(), m->t2(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);   // dh_L
   for (int l = m->L - 1; l >= 0; --l) {
     const int64_t o = m->off_layer(l);
     // dz = dh_{l+1} masked, kept in t2
     mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t2(), m->hbuf(l + 1), int64_t(nodes) * H);
-    gemm(m->hbuf(l), m->t2(), G + o, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
-    gemm(m->mbuf(l), m->t2(), G + o + int64_t(H) * H, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
-    colsum(m->t2(), G + o + 2 * int64_t(H) * H, nodes, H, st);
+    gemm(m->part, m->hbuf(l), m->t2(), G + o, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
+    gemm(m->part, m->mbuf(l), m->t2(), G + o + int64_t(H) * H, H, H, nodes, H, H, H, 1, 0, 0, nullptr, 0, st);
+    colsum(m->part, m->t2(), G + o + 2 * int64_t(H) * H, nodes, H, st);
     // dh_l = dz Ws^T + agg^T(dz Wn^T): t1 = dz Wn^T, then mbuf(l) <- agg^T(t1)
-    gemm(m->t2(), P + o + int64_t(H) * H, m->t1(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);
+    gemm(m->part, m->t2(), P + o + int64_t(H) * H, m->t1(), nodes, H, H, H, H, H, 0, 1, 0, nullptr, 0, st);
     agg_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t1(), m->ptr, m->idx, m->mbuf(l), nodes, H, 1);
-    gemm(m->t2(), P + o, m->mbuf(l), nodes, H, H, H, H, H, 0, 1, 1, nullptr, 0, st);
+    gemm(m->part, m->t2(), P + o, m->mbuf(l), nodes, H, H, H, H, H, 0, 1, 1, nullptr, 0, st);
     TN_HIP(hipMemcpyAsync(m->t2(), m->mbuf(l), size_t(nodes) * H * sizeof(float), hipMemcpyDeviceToDevice, st));
   }
   mask_kernel<<<blocks_for(int64_t(nodes) * H), 256, 0, st>>>(m->t2(), m->hbuf(0), int64_t(nodes) * H);
-  gemm(m->X, m->t2(), G + m->off_W0(), kF, H, nodes, kF, H, H, 1, 0, 0, nullptr, 0, st);
-  colsum(m->t2(), G + m->off_b0(), nodes, H, st);
+  gemm(m->part, m->X, m->t2(), G + m->off_W0(), kF, H, nodes, kF, H, H, 1, 0, 0, nullptr, 0, st);
+  colsum(m->part, m->t2(), G + m->off_b0(), nodes, H, st);
   TN_HIP(hipGetLastError());
 }
 
@@ -424,7 +451,8 @@ tn_model::Sample make_sample(const StateFeat& f, int label) {
 namespace tn {
 
 std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* mc, const PathProblem& pr,
-                                                            int* algo_used) {
+                                                            int rescore_every, int* algo_used) {
+  const int r = std::max(1, rescore_every);
   tn_model* m = const_cast<tn_model*>(mc);
   hipStream_t st = nullptr;
   TN_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -443,11 +471,23 @@ std::vector<std::pair<int, int>> learned_path_with_fallback(const tn_model* mc, 
       std::vector<float> sc(nc);
       TN_HIP(hipMemcpyAsync(sc.data(), m->s, nc * sizeof(float), hipMemcpyDeviceToHost, st));
       TN_HIP(hipStreamSynchronize(st));
-      int best = 0;
-      for (int k = 1; k < nc; ++k)
-        if (sc[k] > sc[best]) best = k;
-      path.push_back(f.cand[best]);
-      cs.merge(state, f.cand[best].first, f.cand[best].second);
+      // Up to r merges per scoring, best score first, no tensor in two of
+      // them: a merge changes no other candidate whose tensors it avoids.
+      std::vector<int> order(nc);
+      for (int k = 0; k < nc; ++k) order[k] = k;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sc[a] > sc[b]; });
+      std::vector<int> used;
+      for (int k : order) {
+        if (int(used.size()) >= 2 * r) break;
+        const auto pq = f.cand[k];
+        if (std::find(used.begin(), used.end(), pq.first) != used.end() ||
+            std::find(used.begin(), used.end(), pq.second) != used.end())
+          continue;
+        used.push_back(pq.first);
+        used.push_back(pq.second);
+        path.push_back(pq);
+        cs.merge(state, pq.first, pq.second);
+      }
     }
   } catch (...) {
     (void)hipStreamDestroy(st);
@@ -481,6 +521,7 @@ tn_status tn_model_create(int32_t hidden, int32_t layers, tn_model** out) {
       TN_HIP(hipMalloc(p, size_t(m->np) * sizeof(float)));
       TN_HIP(hipMemset(*p, 0, size_t(m->np) * sizeof(float)));
     }
+    TN_HIP(hipMalloc(&m->part, size_t(kPartFloats) * sizeof(float)));
     *out = m.release();
   });
 }
