@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -309,24 +310,38 @@ tn_status tn_find_path(const tn_network* n, const tn_path_opts* o, tn_path** out
         TN_REQUIRE(o->rank_precision >= TN_PREC_FP32 && o->rank_precision <= TN_PREC_FP64, TN_ERR_ARG,
                    "bad rank precision");
         auto cands = partition_candidates(pr, o->seed, o->trials, o->mem_budget_bytes, 16);
-        int best = -1;
-        double best_t = 0;
-        for (size_t c = 0; c < cands.size(); ++c) {
-          std::vector<int> sl;
+        // modelled seconds of all slices of each candidate (infinite when
+        // the budget rejects it), candidates evaluated on host threads
+        std::vector<double> tc(cands.size(), std::numeric_limits<double>::infinity());
+        auto modelled = [&](const std::vector<std::pair<int, int>>& p) {
+          const std::vector<int> sl = slice_path(pr, p, o->mem_budget_bytes);
+          const PathStats ps = path_stats(pr, p, sl);
+          return ps.n_slices * modelled_job_seconds(compile_amplitudes(n->net, p, sl, open_q, o->rank_precision));
+        };
+        run_parallel(int(cands.size()), [&](int c) {
           try {
-            sl = slice_path(pr, cands[c], o->mem_budget_bytes);
+            tc[c] = modelled(cands[c]);
           } catch (const Error& e) {
             if (e.code != TN_ERR_BUDGET) throw;
-            continue;
+            return;
           }
-          const PathStats ps = path_stats(pr, cands[c], sl);
-          const AmpPlan plan = compile_amplitudes(n->net, cands[c], sl, open_q, o->rank_precision);
-          const double t = ps.n_slices * modelled_job_seconds(plan);
-          if (best < 0 || t < best_t) {
-            best = int(c);
-            best_t = t;
+          // the same tree reconfigured for modelled step time at its slice
+          // sizes (then re-sliced), kept when the whole plan models faster
+          auto alt = reconfigure_for_time(pr, cands[c], slice_path(pr, cands[c], o->mem_budget_bytes));
+          if (alt == cands[c]) return;
+          try {
+            const double t2 = modelled(alt);
+            if (t2 < tc[c]) {
+              cands[c] = std::move(alt);
+              tc[c] = t2;
+            }
+          } catch (const Error& e) {
+            if (e.code != TN_ERR_BUDGET) throw;
           }
-        }
+        });
+        int best = -1;
+        for (size_t c = 0; c < cands.size(); ++c)
+          if (tc[c] < std::numeric_limits<double>::infinity() && (best < 0 || tc[c] < tc[best])) best = int(c);
         pairs = std::move(cands[best < 0 ? 0 : best]);
       }
     } else {

@@ -143,7 +143,9 @@ void launch_nonfinite(const double2* x, int64_t n, int* flag, hipStream_t s);
 // addressing as the complex64 launches (kernels64.hip).
 void launch_apply64(const double2* A, const double2* B, double2* C, const ApplySmallDesc& d, hipStream_t s);
 void launch_permute64(const double2* in, double2* out, const PermuteDesc& d, hipStream_t s);
-void launch_gemm64(const double2* A, const double2* B, double2* C, const GemmDesc& g, hipStream_t s);
+// work: split-K partials (gemm64_workspace_bytes(g) bytes); NULL = no split.
+size_t gemm64_workspace_bytes(const GemmDesc& g);
+void launch_gemm64(const double2* A, const double2* B, double2* C, const GemmDesc& g, void* work, hipStream_t s);
 size_t dot64_workspace_bytes(int64_t K, int64_t outs);
 void launch_dot64(const double2* A, const double2* B, double2* C, int64_t K, int64_t batch, int64_t m, int64_t n,
                   int transA, int transB, void* work, hipStream_t s);

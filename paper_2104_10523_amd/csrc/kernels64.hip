@@ -187,10 +187,13 @@ __global__ __launch_bounds__(256) void permute64_tiled_kernel(const double2* __r
 struct Gemm64Args {
   int64_t M, N, K;
   int transA, transB;
+  int64_t kchunk;   // K range of one blockIdx.y (K when not split)
 };
 
 // C[b][m][n] = sum_k A(m, k) B(k, n); transA = 0: A[b][m][k], 1: A[b][k][m];
-// transB = 0: B[b][k][n], 1: B[b][n][k].
+// transB = 0: B[b][k][n], 1: B[b][n][k].  Block y sums k in [y kchunk,
+// (y + 1) kchunk) and writes C + y batch M N (split-K partials when
+// gridDim.y > 1, summed by gemm64_reduce_kernel).
 __global__ __launch_bounds__(256) void gemm64_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
                                                      double2* __restrict__ C, Gemm64Args P) {
   __shared__ double2 As[8][64 + 1];
@@ -200,27 +203,28 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const double2* __restrict__
   const int64_t b = blockIdx.z;
   const double2* Ab = A + b * P.M * P.K;
   const double2* Bb = B + b * P.K * P.N;
-  double2* Cb = C + b * P.M * P.N;
+  double2* Cb = C + (int64_t(blockIdx.y) * gridDim.z + b) * P.M * P.N;
+  const int64_t kb = int64_t(blockIdx.y) * P.kchunk, ke = min(P.K, kb + P.kchunk);
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   double2 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
-  for (int64_t k0 = 0; k0 < P.K; k0 += 8) {
+  for (int64_t k0 = kb; k0 < ke; k0 += 8) {
     for (int e = t; e < 512; e += 256) {
       // A tile: 64 rows x 8 k; B tile: 8 k x 64 columns
       int kk, mm;
       if (P.transA) { kk = e >> 6; mm = e & 63; } else { mm = e >> 3; kk = e & 7; }
       const int64_t gm = m0 + mm, gk = k0 + kk;
       double2 v = make_double2(0.0, 0.0);
-      if (gm < P.M && gk < P.K) v = P.transA ? Ab[gk * P.M + gm] : Ab[gm * P.K + gk];
+      if (gm < P.M && gk < ke) v = P.transA ? Ab[gk * P.M + gm] : Ab[gm * P.K + gk];
       As[kk][mm] = v;
       int kb, nn;
       if (P.transB) { nn = e >> 3; kb = e & 7; } else { kb = e >> 6; nn = e & 63; }
       const int64_t gn = n0 + nn, gkb = k0 + kb;
       double2 w = make_double2(0.0, 0.0);
-      if (gn < P.N && gkb < P.K) w = P.transB ? Bb[gn * P.K + gkb] : Bb[gkb * P.N + gn];
+      if (gn < P.N && gkb < ke) w = P.transB ? Bb[gn * P.K + gkb] : Bb[gkb * P.N + gn];
       Bs[kb][nn] = w;
     }
     __syncthreads();
@@ -245,6 +249,19 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const double2* __restrict__
       const int64_t gm = m0 + ty + 16 * i, gn = n0 + tx + 16 * j;
       if (gm < P.M && gn < P.N) Cb[gm * P.N + gn] = acc[i][j];
     }
+}
+
+// C[e] = sum over y = 0 .. Z-1, in order, of part[y][e], e < n.
+__global__ void gemm64_reduce_kernel(const double2* __restrict__ part, int Z, int64_t n, double2* __restrict__ C) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int y = 0; y < Z; ++y) {
+      const double2 v = part[int64_t(y) * n + e];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    C[e] = acc;
+  }
 }
 
 // ------------------------------------------------------ long-K, few outputs
@@ -381,13 +398,35 @@ void launch_permute64(const double2* in, double2* out, const PermuteDesc& d, hip
   TN_HIP(hipGetLastError());
 }
 
-void launch_gemm64(const double2* A, const double2* B, double2* C, const GemmDesc& g, hipStream_t s) {
+// Split-K for GEMMs of few tiles and long K: about 1024 blocks, each K
+// range at least 4096 long and a multiple of 8.
+static int64_t gemm64_kchunk(const GemmDesc& g) {
+  const int64_t blocks = cdiv(g.M, 64) * cdiv(g.N, 64) * g.batch;
+  if (blocks >= 256 || g.K < 8192) return g.K;
+  const int64_t ks = std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, blocks), g.K / 4096));
+  return cdiv(cdiv(g.K, ks), 8) * 8;
+}
+
+size_t gemm64_workspace_bytes(const GemmDesc& g) {
+  const int64_t kc = gemm64_kchunk(g);
+  return kc >= g.K ? 0 : size_t(cdiv(g.K, kc)) * size_t(g.batch * g.M * g.N) * sizeof(double2);
+}
+
+void launch_gemm64(const double2* A, const double2* B, double2* C, const GemmDesc& g, void* work, hipStream_t s) {
   TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1 && g.batch <= 65535, TN_ERR_ARG, "bad GEMM shape");
   const int64_t tiles = cdiv(g.M, 64) * cdiv(g.N, 64);
   TN_REQUIRE(tiles < (int64_t(1) << 31), TN_ERR_UNSUPPORTED, "GEMM grid too large");
-  Gemm64Args P{g.M, g.N, g.K, g.transA, g.transB};
-  gemm64_kernel<<<dim3(unsigned(tiles), 1, unsigned(g.batch)), 256, 0, s>>>(A, B, C, P);
+  const int64_t kc = work ? gemm64_kchunk(g) : g.K;
+  const int64_t ks = cdiv(g.K, kc);
+  Gemm64Args P{g.M, g.N, g.K, g.transA, g.transB, kc};
+  double2* out = ks > 1 ? static_cast<double2*>(work) : C;
+  gemm64_kernel<<<dim3(unsigned(tiles), unsigned(ks), unsigned(g.batch)), 256, 0, s>>>(A, B, out, P);
   TN_HIP(hipGetLastError());
+  if (ks > 1) {
+    const int64_t n = g.batch * g.M * g.N;
+    gemm64_reduce_kernel<<<dim3(unsigned(std::min<int64_t>(cdiv(n, 256), 4096))), 256, 0, s>>>(out, int(ks), n, C);
+    TN_HIP(hipGetLastError());
+  }
 }
 
 size_t dot64_workspace_bytes(int64_t K, int64_t outs) {

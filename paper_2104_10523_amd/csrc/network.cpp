@@ -399,6 +399,8 @@ void parallel_for(int n, F&& body) {
 }
 }  // namespace
 
+void run_parallel(int n, const std::function<void(int)>& body) { parallel_for(n, body); }
+
 std::vector<std::pair<int, int>> random_greedy_path(const PathProblem& pr, uint64_t seed,
                                                     int trials, double temperature, double budget_bytes) {
   // Trial r draws from its own stream (seed + r * golden ratio), so the
@@ -647,11 +649,20 @@ std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t*
 // the largest internal frontier node (ties: smallest id); the cheapest order
 // of that frontier (exact search over subsets, flops 8*size(A u B) per step,
 // kept labels = the node's result) replaces the subtree when it is cheaper.
+// The cost of a step is its flops, or any StepCost of (A, B, result).
 constexpr int kReconf = 8;
 constexpr int kReconfPasses = 8;   // passes until one no longer lowers the flops
 
 std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
                                                   const std::vector<std::pair<int, int>>& path) {
+  return reconfigure_path(pr, path, [&pr](const std::vector<int>& a, const std::vector<int>& b,
+                                          const std::vector<int>&) {
+    return 8.0 * size_of(set_union(a, b), pr.ext);
+  });
+}
+
+std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                                                  const StepCost& step_cost) {
   const int n = int(pr.leaves.size());
   const int total = n + int(path.size());
   std::vector<int> ca(total, -1), cb(total, -1);
@@ -687,11 +698,8 @@ std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
       if (pr.open[l] || c < holders_n[l]) r.push_back(l);
     sets[v] = std::move(r);
   }
-  auto flops_of = [&](const std::vector<int>& a, const std::vector<int>& b) {
-    return 8.0 * size_of(set_union(a, b), pr.ext);
-  };
   std::vector<double> cost(total, 0.0);
-  for (int v = n; v < total; ++v) cost[v] = flops_of(sets[ca[v]], sets[cb[v]]);
+  for (int v = n; v < total; ++v) cost[v] = step_cost(sets[ca[v]], sets[cb[v]], sets[v]);
   for (int v = n; v < total; ++v) {
     // frontier of v
     std::vector<int> F = {ca[v], cb[v]};
@@ -749,7 +757,7 @@ std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
       for (int A = (S - 1) & S; A > 0; A = (A - 1) & S) {
         if (!(A & low)) continue;
         const int B = S ^ A;
-        const double c = best[A] + best[B] + flops_of(rs[A], rs[B]);
+        const double c = best[A] + best[B] + step_cost(rs[A], rs[B], rs[S]);
         if (bv < 0 || c < bv) { bv = c; bs = A; }
       }
       best[S] = bv;
@@ -768,7 +776,7 @@ std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
       ca[node] = x;
       cb[node] = y;
       sets[node] = rs[S];
-      cost[node] = flops_of(sets[x], sets[y]);
+      cost[node] = step_cost(sets[x], sets[y], sets[node]);
       return node;
     };
     make(full);
@@ -786,6 +794,47 @@ std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
   };
   emit(total - 1);
   return out;
+}
+
+double step_seconds(const PathProblem& pr, const std::vector<int>& a, const std::vector<int>& b,
+                    const std::vector<int>& c) {
+  constexpr double kSplit = 350e12, kFp32 = 120e12, kHbm = 4.0e12, kLaunch = 5e-6;
+  std::vector<int> inter, batch, summed;
+  std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(inter));
+  for (int l : inter) (std::binary_search(c.begin(), c.end(), l) ? batch : summed).push_back(l);
+  const double sa = size_of(a, pr.ext), sb = size_of(b, pr.ext), sc = size_of(c, pr.ext);
+  const double fl = 8.0 * size_of(set_union(a, b), pr.ext);
+  const double k = size_of(summed, pr.ext), bt = size_of(batch, pr.ext);
+  const double m = sa / (k * bt), nn = sb / (k * bt);
+  const double mem = 8.0 * (sa + sb + sc) / kHbm;
+  double t = std::max(fl / kFp32, mem);
+  if (m >= 128 && nn >= 128 && k >= 128) t = std::min(t, std::max(fl / kSplit, mem) + 24.0 * (sa + sb) / kHbm);
+  return t + kLaunch;
+}
+
+std::vector<std::pair<int, int>> reconfigure_for_time(const PathProblem& pr,
+                                                      const std::vector<std::pair<int, int>>& path,
+                                                      const std::vector<int>& sliced) {
+  PathProblem ps = pr;
+  for (int l : sliced) ps.ext[l] = 1.0;
+  const StepCost cost = [&ps](const std::vector<int>& a, const std::vector<int>& b, const std::vector<int>& c) {
+    return step_seconds(ps, a, b, c);
+  };
+  auto total = [&](const std::vector<std::pair<int, int>>& p) {
+    double t = 0;
+    for (const Step& s : path_stats(ps, p, {}).steps) t += step_seconds(ps, s.a, s.b, s.c);
+    return t;
+  };
+  auto cur = path;
+  double tc = total(cur);
+  for (int pass = 0; pass < kReconfPasses; ++pass) {
+    auto nxt = reconfigure_path(ps, cur, cost);
+    const double tn = total(nxt);
+    if (!(tn < tc)) break;
+    cur = std::move(nxt);
+    tc = tn;
+  }
+  return cur;
 }
 
 std::vector<std::vector<std::pair<int, int>>> partition_candidates(const PathProblem& pr, uint64_t seed,

@@ -1,6 +1,7 @@
 // Circuit -> tensor network and the path planner (host side).
 #pragma once
 
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -113,6 +114,21 @@ std::vector<std::pair<int, int>> partition_path(const PathProblem& pr, uint64_t*
 // frontier (at most kReconf tensors) is reordered optimally by flops.
 std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr,
                                                   const std::vector<std::pair<int, int>>& path);
+// The same with another additive step cost of (A, B, result) label sets.
+using StepCost = std::function<double(const std::vector<int>&, const std::vector<int>&, const std::vector<int>&)>;
+std::vector<std::pair<int, int>> reconfigure_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
+                                                  const StepCost& step_cost);
+// Modelled seconds of one pairwise step of a slice (sliced labels at extent
+// 1 in pr): max(flops / F, bytes / B) + launch, the faster of FP32 and split
+// FP16x3 where the GEMM is large enough (M, N, K >= 128), whose operands
+// take a max-abs and a packing pass (24 bytes per entry) first.
+double step_seconds(const PathProblem& pr, const std::vector<int>& a, const std::vector<int>& b,
+                    const std::vector<int>& c);
+// Subtree reconfiguration by step_seconds on the sliced problem (passes
+// until the summed step time stops falling); the caller re-slices.
+std::vector<std::pair<int, int>> reconfigure_for_time(const PathProblem& pr,
+                                                      const std::vector<std::pair<int, int>>& path,
+                                                      const std::vector<int>& sliced);
 // The `keep` best partition-search candidates by (total flops, peak, index),
 // best first (at least one: greedy when the budget rejects everything).
 std::vector<std::vector<std::pair<int, int>>> partition_candidates(const PathProblem& pr, uint64_t seed,
@@ -121,6 +137,8 @@ std::vector<std::pair<int, int>> partition_search(const PathProblem& pr, uint64_
                                                   double budget_bytes);
 std::vector<int> slice_path(const PathProblem& pr, const std::vector<std::pair<int, int>>& path,
                             double budget_bytes);
+// body(i) for i in [0, n) on up to 16 host threads; rethrows the first error.
+void run_parallel(int n, const std::function<void(int)>& body);
 uint64_t splitmix64_next(uint64_t* state);
 double splitmix64_uniform(uint64_t* state);
 

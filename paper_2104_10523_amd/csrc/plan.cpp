@@ -457,10 +457,14 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
     // room for the split-K partials of any candidate tile, so the
     // autotuner may pick any of them later
     size_t wb = 0;
-    for (int c : gemm_tile_candidates(op.gm)) {
-      GemmDesc gc = op.gm;
-      gc.tile = c;
-      wb = std::max(wb, gemm_workspace_bytes(gc));
+    if (prec == TN_PREC_FP64) {
+      wb = gemm64_workspace_bytes(op.gm);
+    } else {
+      for (int c : gemm_tile_candidates(op.gm)) {
+        GemmDesc gc = op.gm;
+        gc.tile = c;
+        wb = std::max(wb, gemm_workspace_bytes(gc));
+      }
     }
     if (wb > 0) {
       op.work_elems = int64_t((wb + 7) / 8);
@@ -521,7 +525,7 @@ void run_op64(const PlanOp& op, float2* const bufs[6], hipStream_t s) {
   switch (op.kind) {
     case OP_APPLY: launch_apply64(a, b, c, op.ap, s); break;
     case OP_PERMUTE: launch_permute64(a, c, op.pm, s); break;
-    case OP_GEMM: launch_gemm64(a, b, c, op.gm, s); break;
+    case OP_GEMM: launch_gemm64(a, b, c, op.gm, w, s); break;
     case OP_DOT:
       launch_dot64(a, b, c, op.dot_k, op.dot_batch, op.dot_m, op.dot_n, op.dot_ta, op.dot_tb, w, s);
       break;

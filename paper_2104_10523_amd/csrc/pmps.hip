@@ -566,7 +566,7 @@ std::vector<double> pmps_svd(tn_pmps* m, int mm, int nn, hipStream_t s) {
     gd.M = r;
     gd.N = mm;
     gd.K = nn;
-    launch_gemm64(m->V, m->Wo, m->W, gd, g);
+    launch_gemm64(m->V, m->Wo, m->W, gd, nullptr, g);
   }
   TN_HIP(hipGetLastError());
   TN_HIP(hipMemcpyAsync(S.data(), m->S, r * sizeof(double), hipMemcpyDeviceToHost, g));

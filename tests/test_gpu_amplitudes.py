@@ -192,3 +192,24 @@ def test_random_fsim_circuit_through_the_large_gemm_kernel(gpu, workspace, rqc_4
     tol = 4 * rep.err_bound if precision == "bf16x3" else 1e-5
     print(f"{precision}: floored {e1:.2e} l2 {e2:.2e} (estimate {rep.err_bound:.1e})", flush=True)
     assert e1 <= tol and e2 <= tol, (e1, e2, tol)
+
+
+@pytest.mark.parametrize("budget", [2.0 ** 20, 2.0 ** 24])
+def test_time_ranked_path_against_state_vector(gpu, workspace, rqc_4x5_14, budget):
+    """Time ranking (bisection trees reconfigured for modelled step time and
+    re-sliced) gives a different contraction order from the flop ranking
+    here; its sliced amplitudes of 16 bit-strings equal the state vector's."""
+    import paper_2104_10523_amd as tn
+    n, ops, ref = rqc_4x5_14
+    net = tn.tn_build_network(n, ops)
+    opts = dict(trials=48, seed=2, mem_budget_bytes=budget)
+    pf = tn.tn_find_path(net, "partition", **opts)
+    pt = tn.tn_find_path(net, "partition", rank="time", rank_precision="auto", **opts)
+    assert pt.pairs != pf.pairs and pt.cost.n_sliced >= 1
+    bits = random_bitstrings(16, n, 17)
+    idx = [int("".join(map(str, b)), 2) for b in bits]
+    for prec in ("fp32", "auto"):
+        out, rep = tn.tn_amplitudes(net, pt, bits, precision=prec, use_graph=True)
+        assert rep.nonfinite == 0
+        check_amps(out.cpu().numpy()[:, 0], ref[idx], n)
+

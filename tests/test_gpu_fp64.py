@@ -100,7 +100,16 @@ def test_fp64_cat_marginal_slice(gpu, workspace):
     assert np.abs(got[0] - want).max() <= 1e-15
 
 
-@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+# few output tiles and long K: the FP64 GEMM splits K over blocks and sums
+# the partials in order (16 ranges of 4096; 4 ranges of a batch of 2 with
+# tiles partly outside the 32 x 8 outputs)
+SPLIT_K_CASES = [
+    ("gemm_splitk_64x64_k65536", dict(nm=6, nk=16, nn=6)),
+    ("gemm_splitk_batched_ragged_tiles", dict(nb=1, nm=5, nk=14, nn=3)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CASES + SPLIT_K_CASES, ids=[c[0] for c in CASES + SPLIT_K_CASES])
 def test_fp64_contract_pair(gpu, workspace, name, kw):
     """Complex128 tensors through tn_contract_pair at TN_PREC_FP64."""
     import torch

@@ -239,6 +239,34 @@ def test_identity_coupled_7x7_has_benchmark_path():
     assert p.cost.n_sliced == p0.cost.n_sliced and p.cost.n_sliced >= 4
 
 
+def _modelled_seconds(net, path, precision="auto"):
+    """The library's kernel-time model of a whole job, from the plan's ops:
+    max(flops / F, bytes / 4e12) + 5 us per op, F = 350e12 for split GEMMs
+    and 120e12 otherwise; times the number of slices."""
+    kind, fl, by, sh = tn.tn_amplitudes_plan_ops(net, path, precision)
+    F = np.where((kind == 2) & (sh[:, 5] != 0), 350e12, 120e12)
+    return path.cost.n_slices * float(np.sum(np.maximum(fl / F, by / 4e12) + 5e-6))
+
+
+@pytest.mark.parametrize("rows,cols,cyc,budget", [(5, 5, 10, 2.0 ** 24), (6, 6, 12, 2.0 ** 28)])
+def test_time_ranking_never_models_slower_than_the_flop_winner(rows, cols, cyc, budget):
+    """Time ranking (the 16 best bisection trees by flops, each also
+    reconfigured for modelled step time and re-sliced) picks a plan whose
+    modelled time is at most that of the flop-ranked winner, which is one
+    of its candidates; the path stays a complete contraction order."""
+    n, ops = grid_random_circuit(rows, cols, cyc, 4, two_qubit="fsim")
+    net = tn.tn_build_network(n, ops)
+    opts = dict(trials=48, seed=2, mem_budget_bytes=budget)
+    pf = tn.tn_find_path(net, "partition", **opts)
+    pt = tn.tn_find_path(net, "partition", rank="time", rank_precision="auto", **opts)
+    assert len(pt.pairs) == net.info().n_tensors - 1
+    again = tn.tn_path_from_pairs(net, pt.pairs, mem_budget_bytes=budget)
+    assert again.sliced == pt.sliced and again.cost.total_flops == pt.cost.total_flops
+    assert 8.0 * pt.cost.peak_elems <= budget
+    tf, tt = _modelled_seconds(net, pf), _modelled_seconds(net, pt)
+    assert tt <= tf * (1 + 1e-12)
+
+
 # ---- recursive-bisection path search -------------------------------------
 
 @pytest.mark.parametrize("name,make", CIRCUITS, ids=[c[0] for c in CIRCUITS])
