@@ -1547,6 +1547,7 @@ bool dma_exact(const GemmDesc& g) {
 int default_tile(const GemmDesc& g) {
   if (g.N <= 16) return 0;
   if (g.N <= 32) return 1;
+  if (!g.packed && g.M <= 64 && g.N <= 64) return 3;   // one 64 x 64 tile
   if (g.packed && (g.precision == TN_PREC_BF16X3 || g.precision == TN_PREC_F16X3) && g.N >= 128 && g.M >= 256 &&
       g.M * g.N >= (int64_t(1) << 22))
     return dma_exact(g) ? 5 : 3;

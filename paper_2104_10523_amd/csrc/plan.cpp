@@ -660,9 +660,13 @@ void autotune_ops(std::vector<PlanOp>& ops, float2* const bufs[6], int reps, hip
       for (int cand : gemm_tile_candidates(op.gm)) {
         GemmDesc g = op.gm;
         g.tile = cand;
-        // time a K-truncated proxy: the tile ranking hardly depends on K, and
-        // every address of the proxy stays inside the op's real operands
-        g.K = std::min<int64_t>(g.K, 512);
+        // time a K-truncated proxy: the tile ranking hardly depends on K once
+        // the launch fills the chip, and every address of the proxy stays
+        // inside the op's real operands.  GEMMs of few output tiles split a
+        // long K over blocks; their proxy keeps a sixteenth of K (at least
+        // 512, a multiple of 64) so that it splits, and fills the chip, alike.
+        const int64_t out_tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+        g.K = std::min<int64_t>(g.K, out_tiles < 256 ? std::max<int64_t>(512, (g.K / 16) & ~int64_t(63)) : 512);
         if (gemm_workspace_bytes(g) > size_t(op.work_elems) * sizeof(float2)) continue;
         const uint32_t* sa = slot(bufs, op.smax_a);
         const uint32_t* sb = slot(bufs, op.smax_b);
