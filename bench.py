@@ -821,7 +821,7 @@ def op_kernel_name(precision, k, sh):
         return kernel_name(precision, int(sh[4]), int(sh[5]))
     if k == 0:
         if int(sh[3]) == 2:
-            return f"apply16_mfma_kernel<{int(sh[2])}>"
+            return f"apply16_mfma_kernel<{int(sh[2])}, {max(1, int(sh[1]) // 16)}>"
         return f"{'apply_tile_kernel' if sh[3] else 'apply_small_kernel'}<{int(sh[1])}>"
     if k == 3:
         return f"skinny_partial_kernel<{int(sh[0])}, {int(sh[1])}>" if sh[5] else "dot_partial_kernel"

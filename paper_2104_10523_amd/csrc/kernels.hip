@@ -622,7 +622,8 @@ __global__ __launch_bounds__(256) void apply_tile_kernel(const float2* __restric
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// NN = 16 on the FP32 matrix cores.  A wave takes 2 x 32 rows at a time:
+// NN = 16 NG (NG = 1, 2, 4: 4 to 6 N bits) on the FP32 matrix cores, each
+// group of 16 outputs one MFMA column block.  A wave takes 2 x 32 rows at a time:
 // every K value is one v_mfma_f32_32x32x2f32 per 32 rows in the real 2 x 2
 // block form of the complex product (the MFMA's two k slots carry re a and
 // im a; its 32 columns are the 16 outputs' re and im parts, B entered as
@@ -631,23 +632,24 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // (re for l < 32, im above), so a load instruction covers 32 rows' entries
 // once; accumulator register r holds row 8 (r / 4) + 4 (l / 32) + r % 4, so
 // each store instruction writes two contiguous 128-byte row segments.  A's
-// K values are loaded CH at a time ahead of their MFMAs; the two 32-row
-// groups keep two independent accumulator chains.  Needs n_rows a multiple
-// of 64.
-template <int KK>
+// K values are loaded CH at a time ahead of their MFMAs; every (32-row
+// group, column block) pair keeps its own accumulator chain.  Needs n_rows
+// a multiple of 64.
+template <int KK, int NG>
 __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restrict__ A,
                                                            const float2* __restrict__ B,
                                                            float2* __restrict__ C, ApplyArgs P) {
   constexpr int CH = KK < 8 ? KK : 8;
-  __shared__ float2 sB[KK * 16];
+  constexpr int NN = 16 * NG;
+  __shared__ float2 sB[KK * NN];
   __shared__ int64_t s_koff[KK];
   const int t = threadIdx.x;
-  for (int idx = t; idx < KK * 16; idx += 256) {
-    const int k = idx / 16, n = idx % 16;
+  for (int idx = t; idx < KK * NN; idx += 256) {
+    const int k = idx / NN, n = idx % NN;
     int64_t off = 0;
     for (int i = 0; i < P.nk; ++i)
       if (P.bk[i] >= 0 && ((k >> i) & 1)) off |= int64_t(1) << P.bk[i];
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < P.nn; ++i)
       if ((n >> i) & 1) off |= int64_t(1) << P.bn[i];
     float2 v = make_float2(0.f, 0.f);
     for (int e = 0; e < (1 << P.n_b_extra); ++e) {
@@ -684,7 +686,12 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
   const int64_t groups = P.n_rows >> 6;
   for (int64_t g = int64_t(blockIdx.x) * 4 + wave; g < groups; g += int64_t(gridDim.x) * 4) {
     const int64_t b0 = 2 * expand(g * 64 + li), b1 = 2 * expand(g * 64 + 32 + li);
-    floatx16 acc0 = {}, acc1 = {};
+    floatx16 acc0[NG], acc1[NG];
+#pragma unroll
+    for (int c = 0; c < NG; ++c) {
+      acc0[c] = floatx16{};
+      acc1[c] = floatx16{};
+    }
 #pragma unroll 1
     for (int k0 = 0; k0 < KK; k0 += CH) {
       float a0[CH], a1[CH];
@@ -696,18 +703,23 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
       }
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
-        const float2 b = sB[(k0 + j) * 16 + bn];
-        const float bv = sgn * (pick_re ? b.x : b.y);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], bv, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], bv, acc1, 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < NG; ++c) {
+          const float2 b = sB[(k0 + j) * NN + c * 16 + bn];
+          const float bv = sgn * (pick_re ? b.x : b.y);
+          acc0[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], bv, acc0[c], 0, 0, 0);
+          acc1[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], bv, acc1[c], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t row = g * 64 + 8 * (r >> 2) + 4 * lh + (r & 3);
-      Cf[(row * 16 + bn) * 2 + bt] = acc0[r];
-      Cf[((row + 32) * 16 + bn) * 2 + bt] = acc1[r];
-    }
+    for (int c = 0; c < NG; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = g * 64 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        Cf[(row * NN + c * 16 + bn) * 2 + bt] = acc0[c][r];
+        Cf[((row + 32) * NN + c * 16 + bn) * 2 + bt] = acc1[c][r];
+      }
   }
 }
 
@@ -724,10 +736,11 @@ bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C) {
 }
 
 namespace {
-bool apply_mfma_ok(const ApplySmallDesc& d) { return d.nn == 4 && d.a_bits - d.nk >= 6; }
+bool apply_mfma_ok(const ApplySmallDesc& d) { return d.nn >= 4 && d.nn <= 6 && d.a_bits - d.nk >= 6; }
 }  // namespace
 
 int apply_variant(const ApplySmallDesc& d, const void* A, const void* C) {
+  if (d.nn > 4) return 2;   // 32 or 64 outputs per row: matrix cores only
   if (d.variant == 2 && apply_mfma_ok(d)) return 2;
   const bool tiled = apply_tiled_ok(d, A, C);
   if (d.variant == 0) return tiled ? 1 : 0;
@@ -736,14 +749,31 @@ int apply_variant(const ApplySmallDesc& d, const void* A, const void* C) {
 }
 
 std::vector<int> apply_variant_candidates(const ApplySmallDesc& d) {
+  if (d.nn > 4) return {2};
   std::vector<int> v{0};
   if (apply_mfma_ok(d)) v.push_back(2);
   return v;
 }
 
+namespace {
+template <int NG>
+void launch_apply_mfma(const float2* A, const float2* B, float2* C, const ApplyArgs& P, int nk, dim3 g, dim3 b,
+                       hipStream_t s) {
+  switch (1 << nk) {
+    case 1: apply16_mfma_kernel<1, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 2: apply16_mfma_kernel<2, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 4: apply16_mfma_kernel<4, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 8: apply16_mfma_kernel<8, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 16: apply16_mfma_kernel<16, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    case 32: apply16_mfma_kernel<32, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+    default: apply16_mfma_kernel<64, NG><<<g, b, 0, s>>>(A, B, C, P); break;
+  }
+}
+}  // namespace
+
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
                         hipStream_t s) {
-  TN_REQUIRE(d.nk >= 0 && d.nk <= 6 && d.nn >= 0 && d.nn <= 4 && d.n_b_extra <= 12,
+  TN_REQUIRE(d.nk >= 0 && d.nk <= 6 && d.nn >= 0 && d.n_b_extra <= 12 && (d.nn <= 4 || apply_mfma_ok(d)),
              TN_ERR_UNSUPPORTED, "apply_small shape out of range");
   ApplyArgs P;
   std::memset(&P, 0, sizeof(P));
@@ -761,15 +791,9 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
   if (variant == 2) {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
     const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
-    switch (1 << d.nk) {
-      case 1: apply16_mfma_kernel<1><<<g, b, 0, s>>>(A, B, C, P); break;
-      case 2: apply16_mfma_kernel<2><<<g, b, 0, s>>>(A, B, C, P); break;
-      case 4: apply16_mfma_kernel<4><<<g, b, 0, s>>>(A, B, C, P); break;
-      case 8: apply16_mfma_kernel<8><<<g, b, 0, s>>>(A, B, C, P); break;
-      case 16: apply16_mfma_kernel<16><<<g, b, 0, s>>>(A, B, C, P); break;
-      case 32: apply16_mfma_kernel<32><<<g, b, 0, s>>>(A, B, C, P); break;
-      default: apply16_mfma_kernel<64><<<g, b, 0, s>>>(A, B, C, P); break;
-    }
+    if (d.nn == 4) launch_apply_mfma<1>(A, B, C, P, d.nk, g, b, s);
+    else if (d.nn == 5) launch_apply_mfma<2>(A, B, C, P, d.nk, g, b, s);
+    else launch_apply_mfma<4>(A, B, C, P, d.nk, g, b, s);
     TN_HIP(hipGetLastError());
     return;
   }

@@ -42,7 +42,7 @@ int permute_variant(const PermuteDesc& d);
 struct ApplySmallDesc {
   int a_bits = 0;
   int nk = 0;              // number of K bits (<= 6)
-  int nn = 0;              // number of N bits (<= 4)
+  int nn = 0;              // number of N bits (<= 4; 5 or 6 on the matrix cores only)
   int nb_b = 0;            // bits of B
   int8_t kpos[8];          // in A, ascending
   int8_t bk[8];            // K bit i of B (bit i of k <-> kpos[i])
@@ -56,7 +56,8 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
 // Whether launch_apply_small runs apply_tile_kernel (A and C may be NULL:
 // then alignment is assumed, as for the plan's buffers).
 bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C);
-// Kernel launch_apply_small picks: 0 one thread per row, 1 LDS-tiled, 2 matrix cores (NN = 16).
+// Kernel launch_apply_small picks: 0 one thread per row, 1 LDS-tiled, 2 matrix cores (NN = 16, 32
+// or 64; at least 64 rows; the only kernel for nn = 5, 6).
 // d.variant = 0 or 2 asks for that kernel where it applies (the autotuner's
 // choice); -1 takes the default: 1 where it applies, else 2 where it applies, else 0.
 int apply_variant(const ApplySmallDesc& d, const void* A, const void* C);

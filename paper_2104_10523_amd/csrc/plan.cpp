@@ -221,7 +221,12 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
   const auto& dsmall = x_big ? dy : dx;
 
   // ------------------------------------------------------------ apply path
-  if (batch.empty() && small.labels.size() <= 12 && K.size() + dbig.size() <= 6 && Nsm.size() <= 4 &&
+  // up to 16 outputs per row on every kernel; 32 or 64 (5 or 6 N bits) on
+  // the matrix-core apply, which reads the large operand in place where a
+  // GEMM would first regroup it, at complex64 precisions and >= 64 rows
+  const size_t n_max =
+      precision != TN_PREC_FP64 && big.labels.size() >= K.size() + dbig.size() + 6 ? 6 : 4;
+  if (batch.empty() && small.labels.size() <= 12 && K.size() + dbig.size() <= 6 && Nsm.size() <= n_max &&
       dsmall.size() <= 12) {
     const std::set<int> kset(K.begin(), K.end()), dbset(dbig.begin(), dbig.end());
     std::vector<int> Mbig;

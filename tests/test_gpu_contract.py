@@ -70,6 +70,11 @@ CASES = [
     ("apply_k1_n4", dict(nm=16, nk=1, nn=4)),
     ("apply_k3_n4_many_groups", dict(nm=20, nk=3, nn=4)),
     ("apply_k6_n4", dict(nm=5, nk=6, nn=4)),
+    # 32 and 64 outputs per row: the matrix-core apply with 2 or 4 column blocks
+    ("apply_k6_n6", dict(nm=10, nk=6, nn=6)),
+    ("apply_k5_n5", dict(nm=12, nk=5, nn=5)),
+    ("apply_k6_n6_64_rows", dict(nm=6, nk=6, nn=6)),
+    ("apply_k2_n5_b_summed", dict(nm=9, nk=2, nn=5, db=1)),
     ("gemm_square", dict(nm=9, nk=7, nn=8)),
     ("gemm_ragged_small_mn", dict(nm=5, nk=6, nn=5)),
     ("gemm_n16", dict(nm=11, nk=7, nn=4 + 1)),
