@@ -692,15 +692,7 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
       acc0[c] = floatx16{};
       acc1[c] = floatx16{};
     }
-#pragma unroll 1
-    for (int k0 = 0; k0 < KK; k0 += CH) {
-      float a0[CH], a1[CH];
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        const int64_t o = 2 * s_koff[k0 + j];
-        a0[j] = Af[b0 + o];
-        a1[j] = Af[b1 + o];
-      }
+    auto mfma_chunk = [&](const float* a0, const float* a1, int k0) {
 #pragma unroll
       for (int j = 0; j < CH; ++j) {
 #pragma unroll
@@ -709,6 +701,51 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
           const float bv = sgn * (pick_re ? b.x : b.y);
           acc0[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], bv, acc0[c], 0, 0, 0);
           acc1[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], bv, acc1[c], 0, 0, 0);
+        }
+      }
+    };
+    if constexpr (NG == 1) {
+      // memory-bound: K values CH at a time, a small register footprint
+      // keeps more waves resident to cover the load latency
+#pragma unroll 1
+      for (int k0 = 0; k0 < KK; k0 += CH) {
+        float a0[CH], a1[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          const int64_t o = 2 * s_koff[k0 + j];
+          a0[j] = Af[b0 + o];
+          a1[j] = Af[b1 + o];
+        }
+        mfma_chunk(a0, a1, k0);
+      }
+    } else {
+      // MFMA-bound: the next chunk's loads are issued before this chunk's
+      // MFMAs so that their latency overlaps the matrix work
+      float a0[CH], a1[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int64_t o = 2 * s_koff[j];
+        a0[j] = Af[b0 + o];
+        a1[j] = Af[b1 + o];
+      }
+#pragma unroll 1
+      for (int k0 = 0; k0 < KK; k0 += CH) {
+        float n0[CH], n1[CH];
+        if (k0 + CH < KK) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) {
+            const int64_t o = 2 * s_koff[k0 + CH + j];
+            n0[j] = Af[b0 + o];
+            n1[j] = Af[b1 + o];
+          }
+        }
+        mfma_chunk(a0, a1, k0);
+        if (k0 + CH < KK) {
+#pragma unroll
+          for (int j = 0; j < CH; ++j) {
+            a0[j] = n0[j];
+            a1[j] = n1[j];
+          }
         }
       }
     }
