@@ -80,6 +80,7 @@ CASES = [
     ("gemm_n16", dict(nm=11, nk=7, nn=4 + 1)),
     ("gemm_n32", dict(nm=10, nk=8, nn=5)),
     ("gemm_splitk", dict(nm=6, nk=14, nn=6)),
+    ("gemm_splitk_ragged", dict(nm=5, nk=15, nn=3)),      # 32 x 8 outputs, K = 2^15 split over blocks
     ("gemm_k_beyond_packed_panels", dict(nm=2, nk=21, nn=2)),   # K = 2^21: packed planes would overflow
     ("dot_small_mn", dict(nm=2, nk=17, nn=2)),          # 4 x 4 outputs, K = 2^17: dot per (m, n) pair
     ("dot_small_mn_batch", dict(nb=2, nm=1, nk=16, nn=3)),
