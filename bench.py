@@ -877,7 +877,7 @@ ROWS = {"c1": bench_c1, "c3": bench_c3, "traj": bench_traj, "mps": bench_mps, "p
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (one slice job at a time on its HBM); --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_2104_10523_amd as tn
