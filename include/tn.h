@@ -48,7 +48,7 @@ enum {
   TN_ERR_GATE = -8,        /* unknown gate, bad qubit index, channel where a  */
                            /* unitary is required, non-unitary gate matrix    */
   TN_ERR_SITE = -9,        /* MPS site out of range                           */
-  TN_ERR_UNSUPPORTED = -10,/* valid request this build does not implement     */
+  TN_ERR_UNSUPPORTED = -10,/* valid request the library does not implement    */
   TN_ERR_NOMEM = -11,      /* host or device allocation failed                */
   TN_ERR_STATE = -12       /* handle used in a state that does not allow it   */
 };
