@@ -1098,6 +1098,8 @@ struct PackedArgs {
   int beta;                    // 1: add into C (later K chunks); 0: overwrite
   int flush_tiles;             // direct-to-LDS kernel: add the accumulators into C
                                // every flush_tiles K tiles (0: only at the end)
+  uint32_t* cmax;              // direct-to-LDS kernel, ksplit 1: largest |re|, |im| of
+                               // the final C as float bits, combined with an atomic max
 };
 
 // Block -> output tile.  Workgroups are dispatched round-robin over the 8
@@ -1240,10 +1242,12 @@ __device__ __forceinline__ void packed_store_c(float* Cf, const floatx16 (&acc)[
 // Adds (beta) or writes a wave's accumulator tiles into an exactly tiled C
 // through a buffer descriptor on the wave's 64 x 64 complex block: one
 // per-lane byte offset, and per element a uniform (scalar) row offset, so the
-// flush needs almost no address registers.  `row_bytes` = 8 N.
+// flush needs almost no address registers.  `row_bytes` = 8 N.  Returns the
+// largest magnitude among the floats this lane stored.
 template <int TM, int TN, bool F16>
-__device__ __forceinline__ void packed_flush_exact(__amdgpu_buffer_rsrc_t cb, const floatx16 (&acc)[TM][TN],
-                                                   uint32_t lane_off, uint32_t row_bytes, int shift, int beta) {
+__device__ __forceinline__ float packed_flush_exact(__amdgpu_buffer_rsrc_t cb, const floatx16 (&acc)[TM][TN],
+                                                    uint32_t lane_off, uint32_t row_bytes, int shift, int beta) {
+  float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -1254,7 +1258,9 @@ __device__ __forceinline__ void packed_flush_exact(__amdgpu_buffer_rsrc_t cb, co
         float v = F16 ? ldexpf(acc[i][j][r], shift) : acc[i][j][r];
         if (beta) v += __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(cb, lane_off, soff, 0));
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), cb, lane_off, soff, 0);
+        mx = fmaxf(mx, fabsf(v));
       }
+  return mx;
 }
 
 // Undoes the two operand scales of a split-FP16 GEMM.
@@ -1567,7 +1573,23 @@ __global__ __launch_bounds__(WGM * WGN * 64) void gemm_packed_dma_kernel(const u
     }
   }
 
-  packed_flush_exact<TM, TN, F16>(cb, acc, lane_off, row_bytes, shift, beta);
+  const float mx = packed_flush_exact<TM, TN, F16>(cb, acc, lane_off, row_bytes, shift, beta);
+  if (P.cmax) {
+    // the largest |re|, |im| of C for the fp16 packing of a later GEMM: a
+    // wave reduction, the block's waves through LDS, one atomic per block
+    __shared__ float wave_max[NW];
+    float m = mx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) wave_max[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float b = wave_max[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) b = fmaxf(b, wave_max[w]);
+      atomicMax(P.cmax, __float_as_uint(b));
+    }
+  }
 #endif
 }
 
@@ -1732,7 +1754,7 @@ static void launch_packed_np(const uint32_t* A, const uint32_t* B, float2* C, co
 }
 
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
-                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s) {
+                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s, uint32_t* cmax) {
   TN_REQUIRE(g.M >= 1 && g.N >= 1 && g.K >= 1 && g.batch >= 1, TN_ERR_ARG, "bad GEMM shape");
   TN_REQUIRE(!g.packed || g.K % 4 == 0, TN_ERR_ARG, "internal: packed GEMM needs K % 4 == 0");
   const int id = tile_of(g);
@@ -1761,6 +1783,7 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     P.kbase = 0;
     P.beta = 0;
     P.flush_tiles = 0;
+    P.cmax = nullptr;
     P.ksplit = ksplit;
     P.kchunk = kchunk;
     P.tiles_m = tiles_m;
@@ -1782,6 +1805,11 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     // direct-to-LDS kernel (tile 5), else as one launch per K chunk.
     const int64_t nchunks = ksplit == 1 && id != 5 ? ceil_div(g.K, kAccChunk) : 1;
     if (id == 5) P.flush_tiles = int(kAccChunk / 16);
+    if (cmax && id == 5 && ksplit == 1) {
+      scale_clear_kernel<<<1, 1, 0, s>>>(cmax);
+      P.cmax = cmax;
+      cmax = nullptr;   // computed in the kernel's final flush
+    }
     for (int64_t c = 0; c < nchunks; ++c) {
       if (nchunks > 1) {
         P.kbase = c * kAccChunk;
@@ -1826,6 +1854,13 @@ void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g,
     const int64_t n = g.batch * g.M * g.N;
     const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), grid_cap());
     reduce_splitk_kernel<<<dim3(unsigned(blocks)), 256, 0, s>>>(out, C, ksplit, n);
+    TN_HIP(hipGetLastError());
+  }
+  if (cmax) {
+    // not fused into this kernel: a pass over the finished C
+    const int64_t n = g.batch * g.M * g.N;
+    scale_clear_kernel<<<1, 1, 0, s>>>(cmax);
+    maxabs_kernel<<<dim3(unsigned(std::min<int64_t>(ceil_div(n, 256), grid_cap()))), dim3(256), 0, s>>>(C, n, cmax);
     TN_HIP(hipGetLastError());
   }
 }

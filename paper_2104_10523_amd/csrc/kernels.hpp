@@ -89,8 +89,11 @@ int gemm_tile_of(const GemmDesc& g);
 // Launches of the GEMM kernel itself one launch_gemm makes (K chunks of the
 // accumulator chains; a split-K reduction is not counted).
 int64_t gemm_dispatches(const GemmDesc& g);
+// cmax (optional): a 4-byte device slot that receives the largest |re|, |im|
+// of C as float bits (for the fp16 packing of C by a later GEMM), computed in
+// the direct-to-LDS kernel's final flush or else by a pass over C.
 void launch_gemm(const float2* A, const float2* B, float2* C, const GemmDesc& g, void* work,
-                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s);
+                 const uint32_t* smax_a, const uint32_t* smax_b, hipStream_t s, uint32_t* cmax = nullptr);
 
 // Gather every leaf of one job into the leaf arena: fixed labels take their
 // value from the job's bit-string (kind 0) or slice index (kind 1).
