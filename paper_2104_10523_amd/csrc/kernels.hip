@@ -475,6 +475,7 @@ struct ApplyArgs {
   int8_t bk[8];
   int8_t bn[8];
   int8_t b_extra[12];
+  uint32_t* cmax;         // matrix-core apply: largest |re|, |im| of C (atomic max), or null
 };
 
 __device__ __forceinline__ void cmac(float2& acc, float2 a, float2 b) {
@@ -684,6 +685,7 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
     return m;
   };
   const int64_t groups = P.n_rows >> 6;
+  float mx = 0.f;   // largest magnitude this lane stores (NG = 1)
   for (int64_t g = int64_t(blockIdx.x) * 4 + wave; g < groups; g += int64_t(gridDim.x) * 4) {
     const int64_t b0 = 2 * expand(g * 64 + li), b1 = 2 * expand(g * 64 + 32 + li);
     floatx16 acc0[NG], acc1[NG];
@@ -756,7 +758,16 @@ __global__ __launch_bounds__(256) void apply16_mfma_kernel(const float2* __restr
         const int64_t row = g * 64 + 8 * (r >> 2) + 4 * lh + (r & 3);
         Cf[(row * NN + c * 16 + bn) * 2 + bt] = acc0[c][r];
         Cf[((row + 32) * NN + c * 16 + bn) * 2 + bt] = acc1[c][r];
+        if constexpr (NG == 1) mx = fmaxf(mx, fmaxf(fabsf(acc0[c][r]), fabsf(acc1[c][r])));
       }
+  }
+  // (one column block only: tracking the max costs the wider variants
+  // registers and resident waves, so their callers take a separate pass)
+  if constexpr (NG == 1) if (P.cmax) {
+    // the largest |re|, |im| of C for the fp16 packing of a later GEMM
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) atomicMax(P.cmax, __float_as_uint(mx));
   }
 }
 
@@ -808,8 +819,14 @@ void launch_apply_mfma(const float2* A, const float2* B, float2* C, const ApplyA
 }
 }  // namespace
 
+namespace {
+// apply_tile_kernel (variant 1) or apply_small_kernel (variant 0)
+void apply_scalar_kernels(const float2* A, const float2* B, float2* C, const ApplyArgs& P, const ApplySmallDesc& d,
+                          int variant, hipStream_t s);
+}  // namespace
+
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t* cmax) {
   TN_REQUIRE(d.nk >= 0 && d.nk <= 6 && d.nn >= 0 && d.n_b_extra <= 12 && (d.nn <= 4 || apply_mfma_ok(d)),
              TN_ERR_UNSUPPORTED, "apply_small shape out of range");
   ApplyArgs P;
@@ -825,15 +842,34 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
   }
   for (int i = 0; i < 12; ++i) P.b_extra[i] = d.b_extra[i];
   const int variant = apply_variant(d, A, C);
+  if (cmax) scale_clear_kernel<<<1, 1, 0, s>>>(cmax);
   if (variant == 2) {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
     const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
-    if (d.nn == 4) launch_apply_mfma<1>(A, B, C, P, d.nk, g, b, s);
-    else if (d.nn == 5) launch_apply_mfma<2>(A, B, C, P, d.nk, g, b, s);
-    else launch_apply_mfma<4>(A, B, C, P, d.nk, g, b, s);
+    if (d.nn == 4) {
+      P.cmax = cmax;   // computed as the kernel stores C
+      cmax = nullptr;
+      launch_apply_mfma<1>(A, B, C, P, d.nk, g, b, s);
+    } else if (d.nn == 5) {
+      launch_apply_mfma<2>(A, B, C, P, d.nk, g, b, s);
+    } else {
+      launch_apply_mfma<4>(A, B, C, P, d.nk, g, b, s);
+    }
     TN_HIP(hipGetLastError());
-    return;
+  } else {
+    apply_scalar_kernels(A, B, C, P, d, variant, s);
   }
+  if (cmax) {
+    // not computed by the kernel: a pass over the finished C
+    const int64_t n = P.n_rows << d.nn;
+    maxabs_kernel<<<dim3(unsigned(std::min<int64_t>(ceil_div(n, 256), grid_cap()))), dim3(256), 0, s>>>(C, n, cmax);
+    TN_HIP(hipGetLastError());
+  }
+}
+
+namespace {
+void apply_scalar_kernels(const float2* A, const float2* B, float2* C, const ApplyArgs& P, const ApplySmallDesc& d,
+                          int variant, hipStream_t s) {
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.n_rows, 256), grid_cap() * 2));
   const dim3 g = dim3(unsigned(blocks)), b = dim3(256);
   if (variant == 1) {
@@ -856,6 +892,7 @@ void launch_apply_small(const float2* A, const float2* B, float2* C, const Apply
   }
   TN_HIP(hipGetLastError());
 }
+}  // namespace
 
 // -------------------------------------------------------------- MFMA GEMM
 

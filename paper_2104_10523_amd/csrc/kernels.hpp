@@ -51,8 +51,11 @@ struct ApplySmallDesc {
   int n_b_extra = 0;
   int variant = -1;        // kernel (see apply_variant); -1: the default rule
 };
+// cmax (optional): a 4-byte device slot that receives the largest |re|, |im|
+// of C as float bits (for the fp16 packing of C by a later GEMM), computed
+// as the matrix-core apply stores C or else by a pass over C.
 void launch_apply_small(const float2* A, const float2* B, float2* C, const ApplySmallDesc& d,
-                        hipStream_t s);
+                        hipStream_t s, uint32_t* cmax = nullptr);
 // Whether launch_apply_small runs apply_tile_kernel (A and C may be NULL:
 // then alignment is assumed, as for the plan's buffers).
 bool apply_tiled_ok(const ApplySmallDesc& d, const void* A, const void* C);

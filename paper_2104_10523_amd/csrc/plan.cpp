@@ -106,9 +106,10 @@ TRef emit_permute(const TRef& in, const std::vector<int>& target, Arena& arena,
     scratch->push_back(out.off);
   }
   if (f16 && in.cslot >= 0 && in.producer >= 0 && in.producer < int(ops.size()) &&
-      ops[in.producer].kind == OP_GEMM && ops[in.producer].c_buf == in.buf && ops[in.producer].c_off == in.off) {
-    // the GEMM that produced the input reports its largest |re|, |im| into
-    // the slot reserved with its result
+      (ops[in.producer].kind == OP_GEMM || ops[in.producer].kind == OP_APPLY) &&
+      ops[in.producer].c_buf == in.buf && ops[in.producer].c_off == in.off) {
+    // the GEMM or apply that produced the input reports its largest |re|,
+    // |im| into the slot reserved with its result
     ops[in.producer].cmax = in.cslot;
     op.smax = in.cslot;
     out.smax = op.smax;
@@ -295,6 +296,10 @@ TRef compile_pair_impl(const TRef& X0, const TRef& Y0, const std::vector<int>& k
     op.bytes = 8.0 * (p2(big.labels.size()) + rows * p2(Norder.size()) + p2(small.labels.size()));
     ops.push_back(op);
     if (want && !direct) return emit_permute(out, *want, arena, ops, scratch, want_buf, want_off);
+    if (g_esz == 1 && out.buf == BUF_WORK) {
+      out.cslot = arena.alloc(1);
+      out.producer = int(ops.size()) - 1;
+    }
     return out;
   }
 
@@ -560,7 +565,7 @@ void run_ops(const std::vector<PlanOp>& ops, float2* const bufs[6], hipStream_t 
     float2* c = bufs[op.c_buf] + op.c_off;
     void* w = op.work_off >= 0 ? static_cast<void*>(bufs[BUF_WORK] + op.work_off) : nullptr;
     switch (op.kind) {
-      case OP_APPLY: launch_apply_small(a, b, c, op.ap, s); break;
+      case OP_APPLY: launch_apply_small(a, b, c, op.ap, s, slot(bufs, op.cmax)); break;
       case OP_PERMUTE: launch_permute(a, c, op.pm, slot(bufs, op.smax), s); break;
       case OP_GEMM:
         launch_gemm(a, b, c, op.gm, w, slot(bufs, op.smax_a), slot(bufs, op.smax_b), s, slot(bufs, op.cmax));

@@ -19,9 +19,10 @@ struct TRef {
   int64_t off = 0;            // element offset in the buffer
   std::vector<int> labels;    // layout, outermost first; every label is one bit
   int64_t smax = -1;          // split-FP16 planes: BUF_WORK offset of the max slot
-  // result of a split-precision GEMM: a max slot reserved with it (released
-  // with it) and the index of that GEMM op, so that an fp16 packing of this
-  // tensor can take its max from the GEMM instead of a pass of its own
+  // result of a split-precision GEMM or of an apply: a max slot reserved
+  // with it (released with it) and the index of that op, so that an fp16
+  // packing of this tensor can take its max from the op instead of a pass
+  // of its own
   int64_t cslot = -1;
   int producer = -1;
 };
@@ -36,7 +37,7 @@ struct PlanOp {
   int64_t work_elems = 0;     // size of that scratch
   int64_t smax = -1;          // PERMUTE to fp16 planes: its max slot (BUF_WORK offset)
   int64_t smax_a = -1, smax_b = -1;   // GEMM on fp16 planes: the operands' slots
-  int64_t cmax = -1;          // GEMM: slot for the largest |re|, |im| of its result
+  int64_t cmax = -1;          // GEMM / APPLY: slot for the largest |re|, |im| of its result
   ApplySmallDesc ap;
   PermuteDesc pm;
   GemmDesc gm;
