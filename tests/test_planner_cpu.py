@@ -368,3 +368,20 @@ def test_noalloc_contract_pair_rejects_scratch_beyond_its_array():
     assert "67108864" in msg and "needs" in msg, msg
     with pytest.raises(tn.TnError, match="WORKSPACE"):
         tn._native.check(code)
+
+
+@pytest.mark.parametrize("precision", ["f16x3", "auto"])
+def test_fp16_packing_takes_the_producers_max(precision):
+    """Packing an operand into scaled fp16 planes needs its largest |re|,
+    |im| first.  Where a direct-to-LDS split GEMM or a 16-output matrix-core
+    apply produced the operand, that op reports the max as it stores its
+    result, so the plan has fewer max-abs passes than fp16 packings (the
+    GPU tests contract this plan against the state vector)."""
+    n, ops = grid_random_circuit(4, 5, 14, 2, two_qubit="fsim")
+    net = tn.tn_build_network(n, ops)
+    path = tn.tn_find_path(net, "greedy", open_mask=[1] * n)
+    kind, _, _, sh = tn.tn_amplitudes_plan_ops(net, path, precision)
+    perm = kind == 1
+    maxabs = int(np.sum(perm & (sh[:, 3] == 3)))
+    packs = int(np.sum(perm & (sh[:, 1] == 2) & (sh[:, 2] == 1) & (sh[:, 3] != 3)))
+    assert packs > 0 and 0 < maxabs < packs
